@@ -1,0 +1,178 @@
+"""ctypes wrapper of the TREVR reference oracle (``trevr_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark use it; the product library never does.  Everything here
+is argument marshalling; the arithmetic is in the C file, in binary64.
+
+``mirror32=True`` makes the oracle read every value the walk reads (cell
+boxes, split planes, centres of luminosity, luminosities, far-vertex
+distances, alpha and alpha_max - alpha_min, particle positions and
+luminosities) rounded to binary32, as the GPU library stores them in its
+binary32 transport mode; all arithmetic stays binary64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "trevr_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NODE_F_FIELDS = (
+    "lo0", "lo1", "lo2", "hi0", "hi1", "hi2", "split", "A", "B", "SL",
+    "SLx0", "SLx1", "SLx2", "alpha", "alpha_min", "alpha_max", "dalpha",
+    "xl0", "xl1", "xl2", "lc", "lfar",
+)
+NODE_I_FIELDS = ("first", "count", "depth", "leaf", "parent", "right", "skip", "axis")
+COUNTER_FIELDS = ("n_open", "n_rays", "n_psrc", "n_seg", "n_trace")
+
+
+def build_library(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
+            "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm",
+        ])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build_library()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        L.oracle_build.restype = P
+        L.oracle_build.argtypes = [ctypes.c_int64] + [P] * 9 + [ctypes.c_int, ctypes.c_int]
+        L.oracle_free.argtypes = [P]
+        L.oracle_num_nodes.restype = ctypes.c_int64
+        L.oracle_num_nodes.argtypes = [P]
+        L.oracle_axis.restype = ctypes.c_int
+        L.oracle_axis.argtypes = [P, ctypes.c_int]
+        L.oracle_export.argtypes = [P] * 6
+        L.oracle_flux.restype = ctypes.c_int
+        L.oracle_flux.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
+                                  ctypes.c_int, P, P, P]
+        L.oracle_ray_log.restype = ctypes.c_int64
+        L.oracle_ray_log.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                     ctypes.c_int64] + [P] * 6
+        L.oracle_ray_pieces.restype = ctypes.c_int64
+        L.oracle_ray_pieces.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_int64, P, P]
+        L.oracle_adjoint.restype = ctypes.c_int
+        L.oracle_adjoint.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64, P,
+                                     ctypes.c_int, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleTree:
+    """The oracle's tree over one box of particles."""
+
+    def __init__(self, pos, rho, kappa, lum, mass=None, box_lo=(0.0, 0.0, 0.0),
+                 box_hi=(1.0, 1.0, 1.0), bucket_size=8, mirror32=False):
+        pos = _d(pos)
+        self.n = int(pos.shape[0])
+        self._keep = [_d(pos[:, 0]), _d(pos[:, 1]), _d(pos[:, 2]),
+                      None if mass is None else _d(mass), _d(rho), _d(kappa), _d(lum),
+                      _d(box_lo), _d(box_hi)]
+        k = self._keep
+        h = lib().oracle_build(self.n, _ptr(k[0]), _ptr(k[1]), _ptr(k[2]), _ptr(k[3]),
+                               _ptr(k[4]), _ptr(k[5]), _ptr(k[6]), _ptr(k[7]), _ptr(k[8]),
+                               int(bucket_size), int(bool(mirror32)))
+        if not h:
+            raise ValueError("oracle rejected the particle set")
+        self._h = ctypes.c_void_p(h)
+        self.m = int(lib().oracle_num_nodes(self._h))
+        self.mirror32 = bool(mirror32)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.oracle_free(h)
+            self._h = None
+
+    def axes(self):
+        return np.array([lib().oracle_axis(self._h, d) for d in range(64)], dtype=np.int64)
+
+    def export(self):
+        perm = np.empty(self.n, np.int64)
+        leaf_of = np.empty(self.n, np.int64)
+        node_i = np.empty((self.m, 8), np.int64)
+        node_key = np.empty(self.m, np.uint64)
+        node_f = np.empty((self.m, len(NODE_F_FIELDS)), np.float64)
+        lib().oracle_export(self._h, _ptr(perm), _ptr(leaf_of), _ptr(node_i), _ptr(node_key),
+                            _ptr(node_f))
+        out = {"perm": perm, "leaf_of": leaf_of, "key": node_key}
+        for j, f in enumerate(NODE_I_FIELDS):
+            out[f] = node_i[:, j].copy()
+        for j, f in enumerate(NODE_F_FIELDS):
+            out[f] = node_f[:, j].copy()
+        return out
+
+    def flux(self, theta, tau_ref, sinks=None, nthreads=0, with_g=False):
+        """Return (F, counters[ns,5]) (and G = sum f tau if with_g)."""
+        s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+        ns = self.n if s is None else int(s.shape[0])
+        F = np.empty(ns, np.float64)
+        C = np.empty((ns, 5), np.int64)
+        G = np.empty(ns, np.float64) if with_g else None
+        rc = lib().oracle_flux(self._h, float(theta), float(tau_ref), _ptr(s), ns,
+                               int(nthreads), _ptr(F), _ptr(C), _ptr(G))
+        if rc != 0:
+            raise ValueError("oracle_flux rejected its arguments")
+        return (F, C, G) if with_g else (F, C)
+
+    def ray_log(self, theta, tau_ref, sink, cap=1 << 20):
+        C = np.empty(cap, np.int64)
+        src = np.empty(cap, np.int64)
+        y = np.empty((cap, 3), np.float64)
+        L = np.empty(cap, np.float64)
+        tau = np.empty(cap, np.float64)
+        f = np.empty(cap, np.float64)
+        nr = lib().oracle_ray_log(self._h, float(theta), float(tau_ref), int(sink), cap,
+                                  _ptr(C), _ptr(src), _ptr(y), _ptr(L), _ptr(tau), _ptr(f))
+        k = min(nr, cap)
+        return {"C": C[:k], "src": src[:k], "y": y[:k], "L": L[:k], "tau": tau[:k], "f": f[:k]}
+
+    def ray_pieces(self, theta, tau_ref, sink, ray_index, cap=4096):
+        """Pieces of one ray: node, ta, tb, alpha, length (in the order added)."""
+        node = np.empty(cap, np.int64)
+        tp = np.empty((cap, 4), np.float64)
+        k = lib().oracle_ray_pieces(self._h, float(theta), float(tau_ref), int(sink),
+                                    int(ray_index), cap, _ptr(node), _ptr(tp))
+        k = min(k, cap)
+        return {"node": node[:k], "ta": tp[:k, 0], "tb": tp[:k, 1], "alpha": tp[:k, 2],
+                "len": tp[:k, 3]}
+
+    def adjoint(self, theta, tau_ref, grad_flux, sinks=None, nthreads=0):
+        """Gradients (rho, kappa, lum) of sum_i grad_flux[i] * F_i."""
+        s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+        ns = self.n if s is None else int(s.shape[0])
+        g = _d(grad_flux)
+        assert g.shape[0] == ns
+        gr = np.empty(self.n, np.float64)
+        gk = np.empty(self.n, np.float64)
+        gl = np.empty(self.n, np.float64)
+        lib().oracle_adjoint(self._h, float(theta), float(tau_ref), _ptr(s), ns, _ptr(g),
+                             int(nthreads), _ptr(gr), _ptr(gk), _ptr(gl))
+        return gr, gk, gl

@@ -1,0 +1,837 @@
+/*
+ * trevr_oracle.c -- reference oracle for the TREVR per-sink radiation field.
+ *
+ * Grond, Woods, Wadsley & Couchman (2019), "TREVR: A general N log^2 N
+ * radiative transfer algorithm", MNRAS.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product
+ * library neither links nor calls it, and the two share no source.
+ *
+ * This is a plain, slow, obviously-correct transcription of the method:
+ * recursive tree build, recursive source walk, recursive refinement, all in
+ * IEEE binary64 (no FMA contraction: build with -ffp-contract=off).  Where the
+ * paper is silent the reading taken is stated at the spot.
+ *
+ * Paper sections followed:
+ *   Sec. 2.1, eqs. (dtau), (ient), (simpflux), (simpint): I = L e^-tau/(4 pi s^2)
+ *   Sec. 2.2 / 2.3: space-filling binary tree, longest-axis bisection, buckets
+ *                   of at most N_B particles, separate radiation tree
+ *   Sec. 2.2.1, eq. (openangle): merge at the centre of luminosity when
+ *                   theta_open > l/r
+ *   Sec. 2.2.2, eqs. (taui), (tausum) and the algorithm figure: walk the ray
+ *                   up from the sink bucket and from the source cell, using a
+ *                   chain cell's own average away from its child
+ *   Sec. 2.2.3, eq. (refcrit): refine where tau_ref < (alpha_max-alpha_min) l;
+ *                   directional alpha_min / alpha_max built bottom-up
+ *   Sec. 2.3:       volume-weighted cell density sum(m)/sum(m/rho)
+ * The adjoint (gradients of a flux loss) is not in the paper; it is the exact
+ * derivative of the forward above with every discrete decision held fixed.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define DMAX 63 /* deepest level: 63 path bits fit a 64-bit key */
+
+typedef struct {
+  int64_t first, count; /* range in the sorted particle order */
+  int depth, leaf;
+  int64_t parent, right, skip; /* left child is always self+1 (pre-order) */
+  uint64_t key;                /* path bits, depth-0 decision at bit 62 */
+  double lo[3], hi[3], split;  /* space-filling box, split plane */
+  double A, B, SL, SLx[3];     /* sum m kappa, sum m/rho, sum L, sum L x */
+  double alpha, amin[3], amax[3], alpha_min, alpha_max, dalpha;
+  double xl[3], lc, lfar; /* centre of luminosity, luminosity, far vertex */
+  /* values as the walk sees them: binary64, or rounded to binary32 */
+  double t_lo[3], t_hi[3], t_split, t_xl[3], t_lc, t_lfar, t_alpha, t_dalpha;
+} onode;
+
+typedef struct {
+  int64_t n, m, cap;
+  int nb, mirror32;
+  int axis[DMAX + 1];
+  double rlo[3], rhi[3];
+  double *x, *mass, *rho, *kappa, *lum; /* x is [3n], particle-major */
+  uint64_t *pkey;
+  int64_t *perm, *leaf_of;
+  onode *nd;
+} otree;
+
+static double tr(const otree *t, double v) {
+  return t->mirror32 ? (double)(float)v : v;
+}
+
+/* ---------------------------------------------------------------- tree ---- */
+
+/* Split axis per depth: bisect the longest axis of the current cell shape
+ * (Sec. 2.3).  All cells at one depth share one shape, so the axis depends on
+ * the depth only.  Ties go to the lowest axis index (reading: paper silent). */
+static void level_axes(otree *t) {
+  double w[3];
+  for (int a = 0; a < 3; ++a) w[a] = t->rhi[a] - t->rlo[a];
+  for (int d = 0; d <= DMAX; ++d) {
+    int a = 0;
+    if (w[1] > w[a]) a = 1;
+    if (w[2] > w[a]) a = 2;
+    t->axis[d] = a;
+    w[a] *= 0.5;
+  }
+}
+
+/* A particle's path: at each level the cell is cut at the midpoint of its
+ * split axis; a point on the plane goes to the upper (right) child. */
+static uint64_t path_key(const otree *t, const double *x) {
+  double lo[3], hi[3];
+  uint64_t k = 0;
+  memcpy(lo, t->rlo, sizeof lo);
+  memcpy(hi, t->rhi, sizeof hi);
+  for (int d = 0; d < DMAX; ++d) {
+    int a = t->axis[d];
+    double s = 0.5 * (lo[a] + hi[a]);
+    if (x[a] >= s) {
+      k |= (uint64_t)1 << (62 - d);
+      lo[a] = s;
+    } else {
+      hi[a] = s;
+    }
+  }
+  return k;
+}
+
+static const uint64_t *g_sort_keys; /* qsort has no context argument */
+static int cmp_key_index(const void *pa, const void *pb) {
+  int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+  uint64_t ka = g_sort_keys[a], kb = g_sort_keys[b];
+  if (ka != kb) return ka < kb ? -1 : 1;
+  return a < b ? -1 : (a > b);
+}
+
+static int64_t new_node(otree *t) {
+  if (t->m == t->cap) {
+    t->cap = t->cap ? 2 * t->cap : 1024;
+    t->nd = (onode *)realloc(t->nd, (size_t)t->cap * sizeof(onode));
+  }
+  memset(&t->nd[t->m], 0, sizeof(onode));
+  return t->m++;
+}
+
+/* Nodes are numbered in depth-first pre-order, left before right.  A cell
+ * with more than N_B particles (and depth below DMAX) gets both children even
+ * when one is empty: the radiation tree must fill space (Sec. 2.2.2, 2.3). */
+static int64_t build_node(otree *t, int64_t b, int64_t e, int depth,
+                          uint64_t prefix, const double lo[3],
+                          const double hi[3], int64_t parent) {
+  int64_t id = new_node(t);
+  onode *p = &t->nd[id];
+  p->first = b;
+  p->count = e - b;
+  p->depth = depth;
+  p->parent = parent;
+  p->key = prefix;
+  memcpy(p->lo, lo, 3 * sizeof(double));
+  memcpy(p->hi, hi, 3 * sizeof(double));
+  if (e - b > t->nb && depth < DMAX) {
+    int a = t->axis[depth];
+    double s = 0.5 * (lo[a] + hi[a]);
+    int64_t mid = b;
+    while (mid < e && !((t->pkey[t->perm[mid]] >> (62 - depth)) & 1)) ++mid;
+    double lhi[3], rlo[3];
+    memcpy(lhi, hi, sizeof lhi);
+    memcpy(rlo, lo, sizeof rlo);
+    lhi[a] = s;
+    rlo[a] = s;
+    build_node(t, b, mid, depth + 1, prefix, lo, lhi, id);
+    int64_t r = build_node(t, mid, e, depth + 1,
+                           prefix | ((uint64_t)1 << (62 - depth)), rlo, hi, id);
+    p = &t->nd[id]; /* the array may have moved */
+    p->leaf = 0;
+    p->split = s;
+    p->right = r;
+  } else {
+    p->leaf = 1;
+    p->right = -1;
+    p->split = 0.0;
+    for (int64_t k = b; k < e; ++k) t->leaf_of[t->perm[k]] = id;
+  }
+  t->nd[id].skip = t->m;
+  return id;
+}
+
+/* Cell properties (Sec. 2.2.1, 2.2.3, 2.3). */
+static void cell_properties(otree *t) {
+  /* sums, bottom-up: children have larger pre-order indices than parents */
+  for (int64_t id = t->m - 1; id >= 0; --id) {
+    onode *p = &t->nd[id];
+    if (p->leaf) {
+      for (int64_t k = p->first; k < p->first + p->count; ++k) {
+        int64_t q = t->perm[k];
+        if (t->mass[q] > 0) {
+          p->A += t->mass[q] * t->kappa[q];
+          p->B += t->mass[q] / t->rho[q];
+        }
+        p->SL += t->lum[q];
+        for (int a = 0; a < 3; ++a) p->SLx[a] += t->lum[q] * t->x[3 * q + a];
+      }
+    } else {
+      const onode *l = &t->nd[id + 1], *r = &t->nd[p->right];
+      p->A = l->A + r->A;
+      p->B = l->B + r->B;
+      p->SL = l->SL + r->SL;
+      for (int a = 0; a < 3; ++a) p->SLx[a] = l->SLx[a] + r->SLx[a];
+    }
+  }
+  /* absorption coefficient alpha = kappa rho_cell with the volume-weighted
+   * density; a cell with no absorbing mass takes its parent's value (reading:
+   * paper silent), top-down */
+  for (int64_t id = 0; id < t->m; ++id) {
+    onode *p = &t->nd[id];
+    if (p->B > 0)
+      p->alpha = p->A / p->B;
+    else
+      p->alpha = (p->parent < 0) ? 0.0 : t->nd[p->parent].alpha;
+  }
+  /* directional bounds, bottom-up: along the split axis a ray crosses both
+   * children, so their optical depths add and the sum is divided by the
+   * parent width (children have equal widths: the mean); across it a ray
+   * sees one child or the other (min / max). */
+  for (int64_t id = t->m - 1; id >= 0; --id) {
+    onode *p = &t->nd[id];
+    if (p->leaf) {
+      for (int b = 0; b < 3; ++b) p->amin[b] = p->amax[b] = p->alpha;
+    } else {
+      const onode *l = &t->nd[id + 1], *r = &t->nd[p->right];
+      int s = t->axis[p->depth];
+      for (int b = 0; b < 3; ++b) {
+        if (b == s) {
+          p->amin[b] = 0.5 * (l->amin[b] + r->amin[b]);
+          p->amax[b] = 0.5 * (l->amax[b] + r->amax[b]);
+        } else {
+          p->amin[b] = l->amin[b] < r->amin[b] ? l->amin[b] : r->amin[b];
+          p->amax[b] = l->amax[b] > r->amax[b] ? l->amax[b] : r->amax[b];
+        }
+      }
+    }
+    double mn = p->amin[0], mx = p->amax[0];
+    for (int b = 1; b < 3; ++b) {
+      if (p->amin[b] < mn) mn = p->amin[b];
+      if (p->amax[b] > mx) mx = p->amax[b];
+    }
+    p->alpha_min = mn;
+    p->alpha_max = mx;
+    p->dalpha = mx - mn;
+  }
+  /* merged source: centre of luminosity and the distance from it to the
+   * furthest vertex of the (space-filling) cell */
+  for (int64_t id = 0; id < t->m; ++id) {
+    onode *p = &t->nd[id];
+    if (p->SL > 0) {
+      p->lc = p->SL;
+      for (int a = 0; a < 3; ++a) p->xl[a] = p->SLx[a] / p->SL;
+      double far2 = 0.0;
+      for (int v = 0; v < 8; ++v) {
+        double dv[3];
+        for (int a = 0; a < 3; ++a)
+          dv[a] = ((v >> a) & 1 ? p->hi[a] : p->lo[a]) - p->xl[a];
+        double q = (dv[0] * dv[0] + dv[1] * dv[1]) + dv[2] * dv[2];
+        if (q > far2) far2 = q;
+      }
+      p->lfar = sqrt(far2);
+    }
+  }
+  for (int64_t id = 0; id < t->m; ++id) {
+    onode *p = &t->nd[id];
+    for (int a = 0; a < 3; ++a) {
+      p->t_lo[a] = tr(t, p->lo[a]);
+      p->t_hi[a] = tr(t, p->hi[a]);
+      p->t_xl[a] = tr(t, p->xl[a]);
+    }
+    p->t_split = tr(t, p->split);
+    p->t_lc = tr(t, p->lc);
+    p->t_lfar = tr(t, p->lfar);
+    p->t_alpha = tr(t, p->alpha);
+    p->t_dalpha = tr(t, p->dalpha);
+  }
+}
+
+void oracle_free(void *h) {
+  otree *t = (otree *)h;
+  if (!t) return;
+  free(t->x);
+  free(t->mass);
+  free(t->rho);
+  free(t->kappa);
+  free(t->lum);
+  free(t->pkey);
+  free(t->perm);
+  free(t->leaf_of);
+  free(t->nd);
+  free(t);
+}
+
+/* Build the tree and its properties.  mass may be NULL (all ones).  Returns
+ * NULL on invalid input (particle outside [lo, hi), non-positive density of
+ * an absorber, negative opacity or luminosity, N_B < 1). */
+void *oracle_build(int64_t n, const double *x, const double *y,
+                   const double *z, const double *mass, const double *rho,
+                   const double *kappa, const double *lum, const double *lo,
+                   const double *hi, int nb, int mirror32) {
+  if (n < 0 || nb < 1) return NULL;
+  otree *t = (otree *)calloc(1, sizeof(otree));
+  t->n = n;
+  t->nb = nb;
+  t->mirror32 = mirror32;
+  for (int a = 0; a < 3; ++a) {
+    t->rlo[a] = lo[a];
+    t->rhi[a] = hi[a];
+    if (!(hi[a] > lo[a])) {
+      oracle_free(t);
+      return NULL;
+    }
+  }
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  t->x = (double *)malloc(3 * nn * sizeof(double));
+  t->mass = (double *)malloc(nn * sizeof(double));
+  t->rho = (double *)malloc(nn * sizeof(double));
+  t->kappa = (double *)malloc(nn * sizeof(double));
+  t->lum = (double *)malloc(nn * sizeof(double));
+  t->pkey = (uint64_t *)malloc(nn * sizeof(uint64_t));
+  t->perm = (int64_t *)malloc(nn * sizeof(int64_t));
+  t->leaf_of = (int64_t *)malloc(nn * sizeof(int64_t));
+  for (int64_t i = 0; i < n; ++i) {
+    double p[3] = {x[i], y[i], z[i]};
+    for (int a = 0; a < 3; ++a) {
+      if (!(p[a] >= lo[a] && p[a] < hi[a])) {
+        oracle_free(t);
+        return NULL;
+      }
+      t->x[3 * i + a] = tr(t, p[a]);
+    }
+    t->mass[i] = mass ? mass[i] : 1.0;
+    t->rho[i] = rho[i];
+    t->kappa[i] = kappa[i];
+    t->lum[i] = tr(t, lum[i]);
+    if (!(t->mass[i] >= 0) || !(t->kappa[i] >= 0) || !(t->lum[i] >= 0) ||
+        (t->mass[i] > 0 && !(t->rho[i] > 0)) || !isfinite(t->rho[i]) ||
+        !isfinite(t->kappa[i]) || !isfinite(t->lum[i]) ||
+        !isfinite(t->mass[i])) {
+      oracle_free(t);
+      return NULL;
+    }
+  }
+  level_axes(t);
+  for (int64_t i = 0; i < n; ++i) {
+    t->pkey[i] = path_key(t, &t->x[3 * i]);
+    t->perm[i] = i;
+  }
+  g_sort_keys = t->pkey;
+  qsort(t->perm, (size_t)n, sizeof(int64_t), cmp_key_index);
+  build_node(t, 0, n, 0, 0, t->rlo, t->rhi, -1);
+  cell_properties(t);
+  return t;
+}
+
+int64_t oracle_num_nodes(void *h) { return ((otree *)h)->m; }
+int oracle_axis(void *h, int depth) { return ((otree *)h)->axis[depth]; }
+
+/* Node export.  node_i: 8 per node {first, count, depth, leaf, parent, right,
+ * skip, axis-of-depth}.  node_f: ORACLE_NF per node, see the order below. */
+#define ORACLE_NF 22
+int oracle_export(void *h, int64_t *perm, int64_t *leaf_of, int64_t *node_i,
+                  uint64_t *node_key, double *node_f) {
+  otree *t = (otree *)h;
+  for (int64_t i = 0; i < t->n; ++i) {
+    if (perm) perm[i] = t->perm[i];
+    if (leaf_of) leaf_of[i] = t->leaf_of[i];
+  }
+  for (int64_t id = 0; id < t->m; ++id) {
+    const onode *p = &t->nd[id];
+    if (node_i) {
+      int64_t *o = node_i + 8 * id;
+      o[0] = p->first;
+      o[1] = p->count;
+      o[2] = p->depth;
+      o[3] = p->leaf;
+      o[4] = p->parent;
+      o[5] = p->right;
+      o[6] = p->skip;
+      o[7] = t->axis[p->depth];
+    }
+    if (node_key) node_key[id] = p->key;
+    if (node_f) {
+      double *o = node_f + ORACLE_NF * id;
+      for (int a = 0; a < 3; ++a) {
+        o[0 + a] = p->lo[a];
+        o[3 + a] = p->hi[a];
+        o[10 + a] = p->SLx[a];
+        o[17 + a] = p->xl[a];
+      }
+      o[6] = p->split;
+      o[7] = p->A;
+      o[8] = p->B;
+      o[9] = p->SL;
+      o[13] = p->alpha;
+      o[14] = p->alpha_min;
+      o[15] = p->alpha_max;
+      o[16] = p->dalpha;
+      o[20] = p->lc;
+      o[21] = p->lfar;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------ the walk ---- */
+
+typedef struct {
+  int64_t node;      /* cell whose alpha multiplies this piece */
+  double ta, tb;     /* piece of the ray, parameter t in [0,1] from the sink */
+  int taga, tagb;    /* axis of the plane that produced ta / tb, -1 if none */
+  double alpha, len; /* alpha used and the length r (tb - ta) */
+} oseg;
+
+typedef struct {
+  double d[3], inv[3], r2, r;
+  double tau;
+  int nseg, cap;
+  oseg *seg;
+} oray;
+
+typedef struct {
+  const otree *t;
+  int64_t i, S;
+  double xi[3];
+  double theta2, tau_ref;
+  double F, G;
+  int64_t n_open, n_rays, n_psrc, n_seg, n_trace;
+  /* adjoint accumulators (NULL in a forward pass) */
+  double w;
+  double *abar, *lbar, *xbar, *direct;
+  /* optional piece log of one ray (ray number piece_ray of the walk) */
+  int64_t piece_ray, piece_n, piece_cap;
+  int64_t *piece_node;
+  double *piece_t; /* ta, tb, alpha, len per piece */
+  /* optional ray log */
+  int64_t log_n, log_cap;
+  int64_t *log_C, *log_src;
+  double *log_y, *log_L, *log_tau, *log_f;
+} osink;
+
+/* one alpha * l term of eq. (tausum) */
+static void add_piece(osink *c, oray *ry, int64_t node, double ta, int taga,
+                      double tb, int tagb, double l) {
+  double alpha = c->t->nd[node].t_alpha;
+  if (l > 0) c->n_seg++;
+  ry->tau += alpha * l;
+  if (c->abar || (c->piece_node && c->log_n == c->piece_ray)) {
+    if (ry->nseg == ry->cap) {
+      ry->cap = ry->cap ? 2 * ry->cap : 32;
+      ry->seg = (oseg *)realloc(ry->seg, (size_t)ry->cap * sizeof(oseg));
+    }
+    oseg *s = &ry->seg[ry->nseg++];
+    s->node = node;
+    s->ta = ta;
+    s->tb = tb;
+    s->taga = taga;
+    s->tagb = tagb;
+    s->alpha = alpha;
+    s->len = l;
+  }
+}
+
+/* Refinement (Sec. 2.2.3): use cell X's average on [ta, tb] unless
+ * tau_ref < (alpha_max - alpha_min) l, in which case the cell's children
+ * are used instead, recursively.  Buckets are not refined further (the
+ * sub-bucket particle trace is a separate step). */
+static void refine(osink *c, oray *ry, int64_t X, double ta, int taga,
+                   double tb, int tagb) {
+  const otree *t = c->t;
+  const onode *p = &t->nd[X];
+  double l = ry->r * (tb - ta);
+  c->n_trace++;
+  if (p->leaf || !(p->t_dalpha * l > c->tau_ref)) {
+    add_piece(c, ry, X, ta, taga, tb, tagb, l);
+    return;
+  }
+  int ax = t->axis[p->depth];
+  double s = p->t_split;
+  int64_t L = X + 1, R = p->right;
+  if (ry->d[ax] == 0.0) { /* ray parallel to the plane: one side only */
+    refine(c, ry, c->xi[ax] >= s ? R : L, ta, taga, tb, tagb);
+    return;
+  }
+  double ts = (s - c->xi[ax]) * ry->inv[ax];
+  int64_t nearc = ry->d[ax] > 0 ? L : R;
+  int64_t farc = ry->d[ax] > 0 ? R : L;
+  double t1 = tb;
+  int g1 = tagb;
+  if (ts < tb) {
+    t1 = ts;
+    g1 = ax;
+  }
+  if (t1 > ta) refine(c, ry, nearc, ta, taga, t1, g1);
+  double t0 = ta;
+  int g0 = taga;
+  if (ts > ta) {
+    t0 = ts;
+    g0 = ax;
+  }
+  if (tb > t0) refine(c, ry, farc, t0, g0, tb, tagb);
+}
+
+/* A piece of the ray inside chain cell P but outside P's child on the path,
+ * i.e. inside the sibling X.  The chain cell's own average is used there
+ * (the ray walks up the tree: lowest resolution mid-ray); if P fails the
+ * refinement test the sibling is refined instead. */
+static void chain_piece(osink *c, oray *ry, int64_t P, int64_t X, double ta,
+                        int taga, double tb, int tagb) {
+  double l = ry->r * (tb - ta);
+  c->n_trace++;
+  if (c->t->nd[P].t_dalpha * l > c->tau_ref) {
+    refine(c, ry, X, ta, taga, tb, tagb);
+    return;
+  }
+  add_piece(c, ry, P, ta, taga, tb, tagb, l);
+}
+
+static int key_bit(uint64_t k, int depth) { return (int)((k >> (62 - depth)) & 1); }
+
+/* Reverse ray trace from the sink (t = 0) to a source at y in cell C (t = 1).
+ * Eqs. (taui), (tausum); the flux contribution is eq. (simpint). */
+static void trace_ray(osink *c, int64_t C, const double y[3], double L,
+                      int64_t src) {
+  const otree *t = c->t;
+  oray ry;
+  memset(&ry, 0, sizeof ry);
+  for (int a = 0; a < 3; ++a) {
+    ry.d[a] = y[a] - c->xi[a];
+    ry.inv[a] = ry.d[a] != 0.0 ? 1.0 / ry.d[a] : 0.0;
+  }
+  ry.r2 = (ry.d[0] * ry.d[0] + ry.d[1] * ry.d[1]) + ry.d[2] * ry.d[2];
+  ry.r = sqrt(ry.r2);
+  const int64_t S = c->S;
+  if (C == S) {
+    c->n_trace++;
+    add_piece(c, &ry, S, 0.0, -1, 1.0, -1, ry.r * (1.0 - 0.0));
+  } else {
+    uint64_t kS = t->nd[S].key, kC = t->nd[C].key;
+    int a = __builtin_clzll(kS ^ kC) - 1; /* depth of the meeting cell */
+    int64_t A = S;
+    while (t->nd[A].depth > a) A = t->nd[A].parent;
+    int axA = t->axis[a];
+    double sA = t->nd[A].t_split;
+    int sr = key_bit(kS, a), cr = key_bit(kC, a);
+    double tA;
+    int gA;
+    if (ry.d[axA] != 0.0) {
+      tA = (sA - c->xi[axA]) * ry.inv[axA];
+      gA = axA;
+      if (tA < 0.0) {
+        tA = 0.0;
+        gA = -1;
+      }
+      if (tA > 1.0) {
+        tA = 1.0;
+        gA = -1;
+      }
+    } else { /* ray in the plane: it belongs to the upper side */
+      tA = sr ? 1.0 : 0.0;
+      gA = -1;
+    }
+    /* sink side: [0, tA] lies in A's child toward S; walk down to S */
+    double tP = tA;
+    int gP = gA;
+    int64_t P = sr ? t->nd[A].right : A + 1;
+    for (int dd = a + 1; dd < t->nd[S].depth; ++dd) {
+      int b = key_bit(kS, dd);
+      int ax = t->axis[dd];
+      int64_t child = b ? t->nd[P].right : P + 1;
+      int64_t sib = b ? P + 1 : t->nd[P].right;
+      double dax = ry.d[ax];
+      if (dax != 0.0 && ((!b && dax > 0) || (b && dax < 0))) {
+        double tc = (t->nd[P].t_split - c->xi[ax]) * ry.inv[ax];
+        int gc = ax;
+        if (tc < 0.0) {
+          tc = 0.0;
+          gc = -1;
+        }
+        if (tc < tP) {
+          chain_piece(c, &ry, P, sib, tc, gc, tP, gP);
+          tP = tc;
+          gP = gc;
+        }
+      }
+      P = child;
+    }
+    c->n_trace++;
+    add_piece(c, &ry, S, 0.0, -1, tP, gP, ry.r * (tP - 0.0));
+    /* source side: [tA, 1] lies in A's child toward C; walk down to C */
+    double tQ = tA;
+    int gQ = gA;
+    int64_t Q = cr ? t->nd[A].right : A + 1;
+    for (int dd = a + 1; dd < t->nd[C].depth; ++dd) {
+      int b = key_bit(kC, dd);
+      int ax = t->axis[dd];
+      int64_t child = b ? t->nd[Q].right : Q + 1;
+      int64_t sib = b ? Q + 1 : t->nd[Q].right;
+      double dax = ry.d[ax];
+      if (dax != 0.0 && ((b && dax > 0) || (!b && dax < 0))) {
+        double tc = (t->nd[Q].t_split - c->xi[ax]) * ry.inv[ax];
+        int gc = ax;
+        if (tc > 1.0) {
+          tc = 1.0;
+          gc = -1;
+        }
+        if (tc > tQ) {
+          chain_piece(c, &ry, Q, sib, tQ, gQ, tc, gc);
+          tQ = tc;
+          gQ = gc;
+        }
+      }
+      Q = child;
+    }
+    refine(c, &ry, C, tQ, gQ, 1.0, -1);
+  }
+  double f = (L * exp(-ry.tau)) / ((4.0 * M_PI) * ry.r2);
+  c->F += f;
+  c->G += f * ry.tau;
+  if (c->log_C && c->log_n < c->log_cap) {
+    int64_t k = c->log_n;
+    c->log_C[k] = C;
+    c->log_src[k] = src;
+    for (int a = 0; a < 3; ++a) c->log_y[3 * k + a] = y[a];
+    c->log_L[k] = L;
+    c->log_tau[k] = ry.tau;
+    c->log_f[k] = f;
+  }
+  if (c->piece_node && c->log_n == c->piece_ray) {
+    for (int k = 0; k < ry.nseg && k < c->piece_cap; ++k) {
+      c->piece_node[k] = ry.seg[k].node;
+      c->piece_t[4 * k + 0] = ry.seg[k].ta;
+      c->piece_t[4 * k + 1] = ry.seg[k].tb;
+      c->piece_t[4 * k + 2] = ry.seg[k].alpha;
+      c->piece_t[4 * k + 3] = ry.seg[k].len;
+    }
+    c->piece_n = ry.nseg;
+  }
+  c->log_n++;
+  if (c->abar) {
+    /* adjoint of this ray with decisions held fixed */
+    double g = c->w * f;
+    for (int k = 0; k < ry.nseg; ++k) c->abar[ry.seg[k].node] -= g * ry.seg[k].len;
+    if (src >= 0) {
+      c->direct[src] += g / L;
+    } else {
+      /* d tau / d y: the length scales with r, each plane crossing
+       * t = (s - x_a)/d_a moves with d tau_b / d y_a = -t / d_a */
+      double dtdy[3];
+      for (int a = 0; a < 3; ++a) dtdy[a] = (ry.tau / ry.r) * (ry.d[a] / ry.r);
+      for (int k = 0; k < ry.nseg; ++k) {
+        const oseg *s = &ry.seg[k];
+        if (s->tagb >= 0)
+          dtdy[s->tagb] += ry.r * s->alpha * (-s->tb * ry.inv[s->tagb]);
+        if (s->taga >= 0)
+          dtdy[s->taga] -= ry.r * s->alpha * (-s->ta * ry.inv[s->taga]);
+      }
+      c->lbar[C] += g / L;
+      for (int a = 0; a < 3; ++a)
+        c->xbar[3 * C + a] += g * (-2.0 * ry.d[a] / ry.r2 - dtdy[a]);
+    }
+  }
+  free(ry.seg);
+}
+
+/* Source walk (Sec. 2.2.1): depth-first from the root, left before right;
+ * cells without luminosity are skipped; a cell is merged at its centre of
+ * luminosity when theta_open > l / r, l = distance from the centre of
+ * luminosity to the furthest vertex, r = distance from the sink to the
+ * closest point of the cell (strict, compared squared). */
+static void walk(osink *c, int64_t id) {
+  const otree *t = c->t;
+  const onode *p = &t->nd[id];
+  if (p->t_lc == 0.0) return;
+  c->n_open++;
+  double dd[3];
+  for (int a = 0; a < 3; ++a) {
+    double u = p->t_lo[a] - c->xi[a];
+    double v = c->xi[a] - p->t_hi[a];
+    double g = u > v ? u : v;
+    dd[a] = g > 0.0 ? g : 0.0;
+  }
+  double r2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
+  if (p->t_lfar * p->t_lfar < c->theta2 * r2) {
+    c->n_rays++;
+    trace_ray(c, id, p->t_xl, p->t_lc, -1);
+    return;
+  }
+  if (p->leaf) {
+    for (int64_t k = p->first; k < p->first + p->count; ++k) {
+      int64_t j = t->perm[k];
+      const double *xj = &t->x[3 * j];
+      if (!(t->lum[j] > 0) || j == c->i) continue;
+      if (xj[0] == c->xi[0] && xj[1] == c->xi[1] && xj[2] == c->xi[2]) continue;
+      c->n_rays++;
+      c->n_psrc++;
+      trace_ray(c, id, xj, t->lum[j], j);
+    }
+    return;
+  }
+  walk(c, id + 1);
+  walk(c, p->right);
+}
+
+static void sink_init(osink *c, const otree *t, int64_t i, double theta,
+                      double tau_ref) {
+  memset(c, 0, sizeof *c);
+  c->t = t;
+  c->i = i;
+  c->S = t->leaf_of[i];
+  for (int a = 0; a < 3; ++a) c->xi[a] = t->x[3 * i + a];
+  c->theta2 = theta * theta;
+  c->tau_ref = tau_ref;
+}
+
+/* Flux (angle-summed intensity, eq. simpint summed over sources) at each
+ * sink.  sinks == NULL means every particle, in index order.  counters, if
+ * given, receive 5 per sink: n_open, n_rays, n_psrc, n_seg, n_trace.  G, if
+ * given, receives sum over rays of f * tau. */
+int oracle_flux(void *h, double theta, double tau_ref, const int64_t *sinks,
+                int64_t ns, int nthreads, double *F, int64_t *counters,
+                double *G) {
+  const otree *t = (const otree *)h;
+  if (!(theta >= 0)) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t q = 0; q < ns; ++q) {
+    int64_t i = sinks ? sinks[q] : q;
+    osink c;
+    sink_init(&c, t, i, theta, tau_ref);
+    walk(&c, 0);
+    F[q] = c.F;
+    if (G) G[q] = c.G;
+    if (counters) {
+      counters[5 * q + 0] = c.n_open;
+      counters[5 * q + 1] = c.n_rays;
+      counters[5 * q + 2] = c.n_psrc;
+      counters[5 * q + 3] = c.n_seg;
+      counters[5 * q + 4] = c.n_trace;
+    }
+  }
+  return 0;
+}
+
+/* Every ray of one sink, in walk order.  Returns the number of rays (the
+ * arrays hold the first cap of them).  src = -1 for a merged cell. */
+int64_t oracle_ray_log(void *h, double theta, double tau_ref, int64_t sink,
+                       int64_t cap, int64_t *C, int64_t *src, double *y,
+                       double *L, double *tau, double *f) {
+  const otree *t = (const otree *)h;
+  osink c;
+  sink_init(&c, t, sink, theta, tau_ref);
+  c.log_cap = cap;
+  c.log_C = C;
+  c.log_src = src;
+  c.log_y = y;
+  c.log_L = L;
+  c.log_tau = tau;
+  c.log_f = f;
+  walk(&c, 0);
+  return c.log_n;
+}
+
+/* The pieces (cell, ta, tb, alpha, length) of ray number ray_index of one
+ * sink's walk, in the order they were added.  Returns the piece count. */
+int64_t oracle_ray_pieces(void *h, double theta, double tau_ref, int64_t sink,
+                          int64_t ray_index, int64_t cap, int64_t *node,
+                          double *tparams) {
+  const otree *t = (const otree *)h;
+  osink c;
+  sink_init(&c, t, sink, theta, tau_ref);
+  c.piece_ray = ray_index;
+  c.piece_cap = cap;
+  c.piece_node = node;
+  c.piece_t = tparams;
+  walk(&c, 0);
+  return c.piece_n;
+}
+
+/* Gradient of sum_i gradF_i F_i with respect to every particle's rho, kappa
+ * and L, with the traversal (every accept / open / refine decision and every
+ * piece's cell) held fixed.  alpha = A/B gives
+ *   d alpha / d kappa_p = m_p / B,  d alpha / d rho_p = alpha m_p / (B rho_p^2)
+ * for every cell holding p; a cell without absorbing mass took its parent's
+ * alpha, so its adjoint goes to the parent.  A merged source has
+ * L_C = sum L_j and x_L = sum L_j x_j / L_C, so
+ *   dL_C/dL_j = 1,  dx_L/dL_j = (x_j - x_L) / L_C. */
+int oracle_adjoint(void *h, double theta, double tau_ref, const int64_t *sinks,
+                   int64_t ns, const double *gradF, int nthreads,
+                   double *grad_rho, double *grad_kappa, double *grad_lum) {
+  const otree *t = (const otree *)h;
+  int64_t m = t->m, n = t->n;
+  int nt = 1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  nt = omp_get_max_threads();
+#endif
+  size_t per = (size_t)(5 * m + n);
+  double *acc = (double *)calloc((size_t)nt * per, sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    double *mine = acc + (size_t)tid * per;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+    for (int64_t q = 0; q < ns; ++q) {
+      int64_t i = sinks ? sinks[q] : q;
+      osink c;
+      sink_init(&c, t, i, theta, tau_ref);
+      c.w = gradF[q];
+      c.abar = mine;
+      c.lbar = mine + m;
+      c.xbar = mine + 2 * m;
+      c.direct = mine + 5 * m;
+      walk(&c, 0);
+    }
+  }
+  double *abar = acc, *lbar = acc + m, *xbar = acc + 2 * m, *direct = acc + 5 * m;
+  for (int k = 1; k < nt; ++k) {
+    const double *o = acc + (size_t)k * per;
+    for (size_t e = 0; e < per; ++e) acc[e] += o[e];
+  }
+  for (int64_t id = m - 1; id > 0; --id)
+    if (!(t->nd[id].B > 0)) abar[t->nd[id].parent] += abar[id];
+  for (int64_t p = 0; p < n; ++p) {
+    double gk = 0.0, gr = 0.0, gl = direct[p];
+    for (int64_t id = t->leaf_of[p]; id >= 0; id = t->nd[id].parent) {
+      const onode *c = &t->nd[id];
+      if (c->B > 0 && t->mass[p] > 0) {
+        gk += abar[id] * t->mass[p] / c->B;
+        gr += abar[id] * c->alpha * t->mass[p] / (c->B * t->rho[p] * t->rho[p]);
+      }
+      if (c->lc > 0) {
+        double dot = 0.0;
+        for (int a = 0; a < 3; ++a)
+          dot += xbar[3 * id + a] * (t->x[3 * p + a] - c->xl[a]);
+        gl += lbar[id] + dot / c->lc;
+      }
+    }
+    grad_rho[p] = gr;
+    grad_kappa[p] = gk;
+    grad_lum[p] = gl;
+  }
+  free(acc);
+  return 0;
+}
