@@ -1,0 +1,230 @@
+"""Benchmark of the TREVR radiation field on one MI355X.
+
+A step is one pass of the whole hot path over the headline workload: build
+the radiation tree (keys, sort, cells, cell properties) and evaluate the flux
+at every sink.  Workload: 2^21 particles in a clustered log-normal medium
+(box optical depth 10), every particle a source and a sink, theta_open =
+0.75, tau_ref = 0.1, bucket size 8, binary32 transport, binary64 arithmetic.
+Inputs are resident in HBM before the timed region.
+
+Printed: one JSON line with the throughput (sink fluxes per second), the
+cell visits per second, the forward+adjoint / forward time ratio on the
+2^20-particle adjoint workload, the roofline of the dominant kernel (the
+flux walk) and the oracle's CPU throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "sink fluxes/s + cell visits/s at 2^21 particles; fwd+adjoint vs fwd time"
+# algorithmic bytes per unit of work (binary32 transport): an opening test
+# reads the cell's centre of luminosity, luminosity, far-vertex distance and
+# topology (24 B); a ray-trace step reads alpha, its spread and topology
+# (12 B); a source particle its position and luminosity (16 B); a sink its
+# position, bucket and flux (20 B)
+BYTES_OPEN, BYTES_TRACE, BYTES_PSRC, BYTES_SINK = 24, 12, 16, 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_flux_c3.json")
+FLUX_SRC = os.path.join(ROOT, "paper_1902_08083_amd", "csrc", "flux.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_dev(w, torch, keys=("pos", "rho", "kappa", "lum", "mass")):
+    return [torch.as_tensor(w[k], device="cuda") for k in keys]
+
+
+def timed_steps(torch, P, w, steps, warmup, tree):
+    pos, rho, kappa, lum, mass = to_dev(w, torch)
+    n = pos.shape[0]
+    flux = torch.empty(n, dtype=pos.dtype, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def step():
+        tree.build(pos, rho, kappa, lum, mass, w["box_lo"], w["box_hi"], w["bucket_size"])
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        tree.flux(w["theta"], w["tau_ref"], out=flux)
+        e1.record(st)
+        return e0, e1
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        evs.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    flux_ms = [a.elapsed_time(b) for a, b in evs]
+    return (t1 - t0) * 1e3 / steps, float(np.mean(flux_ms)), flux
+
+
+def counters_run(torch, tree, w):
+    _, C = tree.flux(w["theta"], w["tau_ref"], counters=True)
+    return C.to(torch.int64).sum(0).cpu().numpy()
+
+
+def adjoint_ratio(torch, P, reps=3):
+    from paper_1902_08083_amd import workloads as W
+    w = W.c5()
+    pos, rho, kappa, lum, mass = to_dev(w, torch)
+    tree = P.build_tree(pos, rho, kappa, lum, mass, bucket_size=w["bucket_size"])
+    gF = torch.ones(pos.shape[0], dtype=pos.dtype, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def t_of(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            fn()
+            b.record(st)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms))
+
+    t_f = t_of(lambda: tree.flux(w["theta"], w["tau_ref"]))
+    t_a = t_of(lambda: tree.adjoint(w["theta"], w["tau_ref"], gF))
+    return {"workload": w["name"], "fwd_ms": t_f, "adj_ms": t_a,
+            "fwd_plus_adj_over_fwd": (t_f + t_a) / t_f}
+
+
+def cpu_baseline(w, target_s=10.0):
+    """The oracle (binary64, OpenMP over sinks) on this host: full tree build
+    plus the flux at a seeded sample of sinks, scaled to sink fluxes/s."""
+    from oracle.oracle import OracleTree
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = min(cores, 16)
+    f64 = lambda a: np.asarray(a, np.float64)  # noqa: E731
+    t0 = time.perf_counter()
+    o = OracleTree(f64(w["pos"]), f64(w["rho"]), f64(w["kappa"]), f64(w["lum"]), f64(w["mass"]),
+                   w["box_lo"], w["box_hi"], w["bucket_size"], mirror32=True)
+    t_build = time.perf_counter() - t0
+    n = w["pos"].shape[0]
+    rng = np.random.default_rng(7)
+    pilot = rng.choice(n, size=512, replace=False)
+    t0 = time.perf_counter()
+    o.flux(w["theta"], w["tau_ref"], sinks=pilot, nthreads=cores)
+    per = (time.perf_counter() - t0) / pilot.size
+    ns = int(min(n, max(2048, target_s / max(per, 1e-9))))
+    sample = rng.choice(n, size=ns, replace=False)
+    t0 = time.perf_counter()
+    o.flux(w["theta"], w["tau_ref"], sinks=sample, nthreads=cores)
+    t_flux = time.perf_counter() - t0
+    t_full = t_build + t_flux * n / ns
+    return {"value": n / t_full, "unit": "sink fluxes/s", "cores": cores, "kind": "oracle",
+            "sample": "full tree build (%.1f s) + flux at %d seeded random sinks of %d (%.1f s), "
+                      "scaled to all sinks" % (t_build, ns, n, t_flux)}
+
+
+def recorded_traffic(launch_key):
+    """HBM bytes per flux launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source and launch."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = json.load(open(TRAFFIC_FILE))
+    src = hashlib.sha256(open(FLUX_SRC, "rb").read()).hexdigest()
+    if rec.get("flux_hip_sha256") != src or rec.get("launch") != launch_key:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--n", type=int, default=1 << 21, help="particles (default: the headline 2^21)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the per-sink walk shards over sinks with a "
+              "replicated tree, and this build measures the single-GPU share (--gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1902_08083_amd as P
+    from paper_1902_08083_amd import workloads as W
+
+    log("generating workload")
+    w = W.c3(n=args.n)
+    n = w["pos"].shape[0]
+    tree = P.Tree()
+    log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
+    ms_step, ms_flux, flux = timed_steps(torch, P, w, args.steps, args.warmup, tree)
+    log("step %.2f ms, flux kernel %.2f ms" % (ms_step, ms_flux))
+    tot = counters_run(torch, tree, w)
+    n_open, n_rays, n_psrc, n_seg, n_trace = [int(v) for v in tot]
+    visits = n_open + n_trace
+    alg_bytes = (BYTES_OPEN * n_open + BYTES_TRACE * n_trace + BYTES_PSRC * n_psrc
+                 + BYTES_SINK * n)
+    achieved = alg_bytes / (ms_flux * 1e-3) / 1e9
+    launch = tree.get_launch()
+    launch_key = "%d/%d/%d" % (launch["blocks_per_cu"], launch["waves_per_block"],
+                               launch["chunk"])
+    traffic = recorded_traffic(launch_key)
+    info = tree.info()
+    out = {
+        "metric": METRIC,
+        "value": n / (ms_step * 1e-3),
+        "unit": "sink fluxes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "n_particles": n, "n_sources": int((w["lum"] > 0).sum()),
+                   "n_sinks": n, "theta_open": w["theta"], "tau_ref": w["tau_ref"],
+                   "bucket_size": w["bucket_size"], "box_tau": 10.0, "transport": "f32",
+                   "cells": info["m"], "max_depth": info["max_depth"], "launch": launch},
+        "cell_visits_per_s": visits / (ms_step * 1e-3),
+        "flux_kernel_ms": ms_flux,
+        "build_ms": ms_step - ms_flux,
+        "sink_fluxes_per_s_flux_only": n / (ms_flux * 1e-3),
+        "per_sink": {"n_open": n_open / n, "n_rays": n_rays / n, "n_psrc": n_psrc / n,
+                     "n_seg": n_seg / n, "n_trace": n_trace / n},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "trevr::k_walk<float, false>",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_adjoint:
+        log("adjoint ratio on the 2^20 workload")
+        out["adjoint"] = adjoint_ratio(torch, P)
+    if not args.no_cpu:
+        log("oracle CPU baseline")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * trevr.h -- C ABI of the MI355X (gfx950) TREVR radiation-field library.
+ *
+ * TREVR (Grond, Woods, Wadsley & Couchman 2019, "TREVR: A general N log^2 N
+ * radiative transfer algorithm") evaluates, at every sink, the angle-summed
+ * intensity of point sources attenuated along straight rays:
+ *
+ *     F_i = sum over rays of  L exp(-tau) / (4 pi r^2)           (Sec. 2.1)
+ *
+ * Sources are merged on a space-filling binary tree with the opening-angle
+ * criterion (Sec. 2.2.1), and each ray's optical depth tau = sum alpha l is
+ * accumulated over tree cells, refining a cell only where its spread of
+ * optical depth exceeds tau_ref (Sec. 2.2.2-2.2.3).
+ *
+ * Conventions shared by every entry point:
+ *  - Every array argument named as "device" is a device pointer owned by the
+ *    caller; the library never frees or retains it beyond the call, except
+ *    where stated.  Host arrays are read during the call only.
+ *  - Floating-point arrays are float (TREVR_F32) or double (TREVR_F64) as
+ *    the particle set's precision says.  In TREVR_F32 the tree stores its
+ *    cell data rounded to binary32 ("transport") and all arithmetic is
+ *    binary64; TREVR_F64 stores binary64.
+ *  - Every function returns a trevr_status (0 = success).  On failure a
+ *    message is available from trevr_last_error() (per host thread).  The
+ *    library never aborts and never prints.
+ *  - Calls that take a stream enqueue their work on it and return without
+ *    waiting, except trevr_build_tree, which waits on its stream.
+ *  - Calls on one tree handle must not overlap in time.
+ */
+#ifndef TREVR_H
+#define TREVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { TREVR_F32 = 0, TREVR_F64 = 1 } trevr_prec;
+
+typedef enum {
+  TREVR_OK = 0,
+  TREVR_E_ARG = -1,       /* invalid argument (NULL pointer, bad size, ...) */
+  TREVR_E_RANGE = -2,     /* a particle lies outside its box [lo, hi)       */
+  TREVR_E_NONFINITE = -3, /* NaN or infinity in an input array               */
+  TREVR_E_VALUE = -4,     /* negative mass, opacity or luminosity, or a
+                             non-positive density where the mass is > 0     */
+  TREVR_E_STATE = -5,     /* the tree handle holds no (suitable) tree        */
+  TREVR_E_CAPACITY = -6,  /* more nodes or particles than the layout holds   */
+  TREVR_E_HIP = -100      /* a HIP runtime call failed                        */
+} trevr_status;
+
+/* The particle set: one or more independent boxes ("a forest").  Box b holds
+ * the particles [box_offsets[b], box_offsets[b+1]) of the arrays below and
+ * its own space-filling tree over [box_lo[3b..3b+2], box_hi[3b..3b+2]).
+ * One particle set carries every role (Sec. 2.2): a particle with L > 0 is a
+ * source, every particle may be a sink, and a particle with mass > 0 is an
+ * absorber with absorption coefficient kappa rho.  */
+typedef struct {
+  int64_t n;                   /* total particles over all boxes, >= 0        */
+  trevr_prec prec;             /* element type of every float array below     */
+  const void *x, *y, *z;       /* device, n each: positions inside their box  */
+  const void *mass;            /* device, n, or NULL (all 1); mass >= 0       */
+  const void *rho;             /* device, n: density, > 0 where mass > 0      */
+  const void *kappa;           /* device, n: opacity, >= 0                    */
+  const void *lum;             /* device, n: luminosity, >= 0                 */
+  int32_t n_boxes;             /* >= 1                                        */
+  const int64_t *box_offsets;  /* host, n_boxes + 1 (NULL allowed if 1 box)   */
+  const double *box_lo;        /* host, 3 n_boxes: lower corners               */
+  const double *box_hi;        /* host, 3 n_boxes: upper corners (exclusive)  */
+  int32_t bucket_size;         /* N_B >= 1: most particles per leaf (Sec. 2.2) */
+} trevr_particles;
+
+/* Launch knobs of the flux and adjoint kernels (set by the autotuner). */
+typedef struct {
+  int32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..32   */
+  int32_t waves_per_block; /* 1..16 wavefronts (64 lanes) per workgroup        */
+  int32_t chunk;           /* sinks per work-queue grab, a multiple of 64      */
+} trevr_launch;
+
+typedef struct {
+  int64_t n;          /* particles                                          */
+  int64_t m;          /* tree cells (all boxes)                             */
+  int32_t n_boxes;
+  int32_t max_depth;  /* deepest cell                                       */
+  trevr_prec prec;
+  int32_t bucket_size;
+} trevr_tree_info_t;
+
+typedef struct trevr_tree trevr_tree; /* opaque handle */
+
+const char *trevr_status_string(int status);
+const char *trevr_last_error(void);
+
+/* Create an empty tree handle.  Its device buffers are allocated by
+ * trevr_build_tree and grow as needed; trevr_tree_destroy frees them. */
+int trevr_tree_create(trevr_tree **out);
+void trevr_tree_destroy(trevr_tree *tree);
+
+/* (Re)build the radiation tree and its cell properties (Sec. 2.2, 2.3):
+ *  - each box is bisected at the midpoint of its longest axis (ties to the
+ *    lowest axis index), recursively; a point on a plane goes to the upper
+ *    half; a cell with more than bucket_size particles gets both halves even
+ *    if one is empty (the tree fills space); depth is capped at 63;
+ *  - cells are numbered depth-first, lower half first; particles are ordered
+ *    by their 63-level path, ties by input index;
+ *  - per cell: alpha = sum(m kappa) / sum(m / rho) (the volume-weighted
+ *    density times the mass-weighted opacity; a cell without absorbing mass
+ *    takes its parent's), directional alpha_min / alpha_max combined
+ *    bottom-up (Sec. 2.2.3), luminosity, centre of luminosity and the
+ *    distance from it to the furthest vertex (Sec. 2.2.1).
+ * The tree copies what it needs from the particle arrays.  Waits on
+ * `stream`.  Errors: TREVR_E_ARG, _RANGE, _NONFINITE, _VALUE, _CAPACITY,
+ * _HIP; on error the handle holds no tree. */
+int trevr_build_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream);
+
+int trevr_tree_info(const trevr_tree *tree, trevr_tree_info_t *info);
+
+/* Radiation field at the sinks (Sec. 2.1-2.2.3): for each sink a depth-first
+ * source walk merges every luminous cell whose centre-of-luminosity to
+ * furthest-vertex distance l satisfies l < theta_open r (r = distance from
+ * the sink to the closest point of the cell, eq. openangle), else opens it
+ * (a bucket then gives its particles, other than the sink and points at the
+ * sink's position, as individual sources); each ray's optical depth is
+ * summed over cells walking up from the sink's bucket and the source cell
+ * (Sec. 2.2.2), refining where (alpha_max - alpha_min) l > tau_ref
+ * (eq. refcrit); flux += L exp(-tau) / (4 pi r^2).
+ *   theta_open >= 0; tau_ref any (negative: refine to buckets always,
+ *   +infinity: never refine).
+ *   sinks: device, n_sinks particle indices, or NULL for every particle (then
+ *   n_sinks must equal n and flux[i] belongs to particle i).  An index
+ *   outside [0, n) is not evaluated: its flux is NaN and its counters -1
+ *   (in the adjoint it contributes nothing).
+ *   flux: device, n_sinks, precision of the tree.
+ *   counters: device int32 [n_sinks][5] or NULL: cells tested for opening,
+ *   rays, rays from single particles, pieces with positive length, cell
+ *   records read by the ray trace.
+ * Asynchronous; allocates nothing (graph-capturable) once the tree is built.
+ * Errors: TREVR_E_ARG, _STATE, _HIP. */
+int trevr_compute_flux(const trevr_tree *tree, double theta_open, double tau_ref,
+                       const int32_t *sinks, int64_t n_sinks, void *flux, int32_t *counters,
+                       hipStream_t stream);
+
+/* Gradient of  sum_k grad_flux[k] * flux[k]  (flux as trevr_compute_flux
+ * returns it for the same arguments) with respect to every particle's rho,
+ * kappa and lum, with every accept / open / refine decision of the forward
+ * held fixed.  Merged sources contribute through their luminosity and their
+ * centre of luminosity.  The traversal is recomputed, not stored.
+ *   grad_flux: device, n_sinks.  grad_rho, grad_kappa, grad_lum: device, n
+ *   each (overwritten; zero for massless particles' rho and kappa).
+ * Uses scratch owned by the tree (allocated on first use, so the first call
+ * is not graph-capturable).  Asynchronous.  Errors: TREVR_E_ARG, _STATE, _HIP. */
+int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_ref,
+                               const int32_t *sinks, int64_t n_sinks, const void *grad_flux,
+                               void *grad_rho, void *grad_kappa, void *grad_lum,
+                               hipStream_t stream);
+
+/* Launch knobs for later flux / adjoint calls on this tree (autotuning). */
+int trevr_set_launch(trevr_tree *tree, const trevr_launch *cfg);
+int trevr_get_launch(const trevr_tree *tree, trevr_launch *cfg);
+
+/* Copy the tree to host memory for inspection (all host pointers, any may be
+ * NULL):
+ *   perm[n]: particle index at each sorted position;
+ *   leaf_of[n]: leaf cell of each particle;
+ *   node_i[m][8]: first, count, depth, leaf (0/1), parent (-1 at a root),
+ *                 upper child (-1 at a leaf), next cell after the subtree,
+ *                 split axis of the cell's depth;
+ *   node_key[m]: path bits, the depth-0 choice at bit 62;
+ *   node_f[m][22]: binary64 lo[3], hi[3], split plane, sum m kappa,
+ *                 sum m / rho, sum L, sum L x[3], alpha, alpha_min,
+ *                 alpha_max, alpha_max - alpha_min, centre of luminosity[3],
+ *                 luminosity, far-vertex distance.
+ * Waits on `stream`.  Errors: TREVR_E_ARG, _STATE, _HIP. */
+int trevr_export_tree(const trevr_tree *tree, int64_t *perm, int64_t *leaf_of, int64_t *node_i,
+                      uint64_t *node_key, double *node_f, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TREVR_H */

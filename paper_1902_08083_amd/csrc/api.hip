@@ -1,0 +1,187 @@
+// C ABI entry points: argument validation, error reporting, dispatch.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "trevr_internal.h"
+
+namespace trevr {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  g_last_error = std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) +
+                 ") in " + what;
+  return TREVR_E_HIP;
+}
+
+static int check_particles(const trevr_particles *p) {
+  if (!p) return fail(TREVR_E_ARG, "particles is NULL");
+  if (p->n < 0) return fail(TREVR_E_ARG, "n < 0");
+  if (p->n >= (int64_t)1 << 31) return fail(TREVR_E_CAPACITY, "more than 2^31 - 1 particles");
+  if (p->prec != TREVR_F32 && p->prec != TREVR_F64) return fail(TREVR_E_ARG, "bad precision");
+  if (p->n_boxes < 1) return fail(TREVR_E_ARG, "n_boxes < 1");
+  if (p->bucket_size < 1) return fail(TREVR_E_ARG, "bucket_size < 1");
+  if (!p->box_lo || !p->box_hi) return fail(TREVR_E_ARG, "box corners are NULL");
+  if (p->n_boxes > 1 && !p->box_offsets) return fail(TREVR_E_ARG, "box_offsets is NULL");
+  if (p->n > 0 && (!p->x || !p->y || !p->z || !p->rho || !p->kappa || !p->lum))
+    return fail(TREVR_E_ARG, "a particle array is NULL");
+  for (int b = 0; b < 3 * p->n_boxes; ++b) {
+    if (!std::isfinite(p->box_lo[b]) || !std::isfinite(p->box_hi[b]))
+      return fail(TREVR_E_NONFINITE, "non-finite box corner");
+    if (!(p->box_hi[b] > p->box_lo[b])) return fail(TREVR_E_ARG, "box with hi <= lo");
+  }
+  if (p->box_offsets) {
+    if (p->box_offsets[0] != 0 || p->box_offsets[p->n_boxes] != p->n)
+      return fail(TREVR_E_ARG, "box_offsets must run from 0 to n");
+    for (int b = 0; b < p->n_boxes; ++b)
+      if (p->box_offsets[b + 1] < p->box_offsets[b])
+        return fail(TREVR_E_ARG, "box_offsets must not decrease");
+  }
+  return TREVR_OK;
+}
+
+static int check_walk(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                      int64_t n_sinks) {
+  if (!t) return fail(TREVR_E_ARG, "tree is NULL");
+  if (!t->built) return fail(TREVR_E_STATE, "tree holds no built tree");
+  if (!(theta >= 0) || !std::isfinite(theta)) return fail(TREVR_E_ARG, "theta_open must be >= 0");
+  if (std::isnan(tau_ref)) return fail(TREVR_E_ARG, "tau_ref is NaN");
+  if (n_sinks < 0) return fail(TREVR_E_ARG, "n_sinks < 0");
+  if (!sinks && n_sinks != t->n) return fail(TREVR_E_ARG, "sinks NULL needs n_sinks == n");
+  if (n_sinks >= (int64_t)1 << 31) return fail(TREVR_E_CAPACITY, "too many sinks");
+  return TREVR_OK;
+}
+
+}  // namespace trevr
+
+trevr_tree::~trevr_tree() {
+  trevr::DevBuf *all[] = {&walk, &trace, &key, &psrc, &perm, &inv, &leaf, &pbox, &pmass, &prho,
+                          &box_root, &box_off, &box_lo, &box_hi, &axis_tab, &n_first, &n_count,
+                          &n_depth, &n_parent, &n_right, &n_skip, &n_box, &n_axis, &n_lo,
+                          &n_hi, &n_split, &n_A, &n_B, &n_SL, &n_SLx, &n_alpha, &n_amin,
+                          &n_amax, &n_alpha_min, &n_alpha_max, &n_dalpha, &n_xl, &n_lc,
+                          &n_lfar, &keys_in, &keys_out, &vals_in, &vals_out, &sort_tmp, &bfs,
+                          &flags, &scan, &err, &box_key, &skeys, &small, &queue, &adj_node,
+                          &adj_part};
+  for (auto *b : all) b->release();
+}
+
+extern "C" {
+
+const char *trevr_status_string(int status) {
+  switch (status) {
+    case TREVR_OK: return "ok";
+    case TREVR_E_ARG: return "invalid argument";
+    case TREVR_E_RANGE: return "particle outside its box";
+    case TREVR_E_NONFINITE: return "non-finite input";
+    case TREVR_E_VALUE: return "invalid input value";
+    case TREVR_E_STATE: return "tree not built";
+    case TREVR_E_CAPACITY: return "size beyond the layout's capacity";
+    case TREVR_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char *trevr_last_error(void) { return trevr::g_last_error.c_str(); }
+
+int trevr_tree_create(trevr_tree **out) {
+  if (!out) return trevr::fail(TREVR_E_ARG, "out is NULL");
+  trevr_tree *t = new (std::nothrow) trevr_tree();
+  if (!t) return trevr::fail(TREVR_E_ARG, "out of host memory");
+  hipError_t e = hipGetDevice(&t->device);
+  if (e != hipSuccess) {
+    delete t;
+    return trevr::hip_fail(e, "hipGetDevice");
+  }
+  int cu = 0;
+  e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, t->device);
+  if (e != hipSuccess) {
+    delete t;
+    return trevr::hip_fail(e, "hipDeviceGetAttribute");
+  }
+  t->num_cu = cu > 0 ? cu : 256;
+  e = t->queue.ensure(256);
+  if (e != hipSuccess) {
+    delete t;
+    return trevr::hip_fail(e, "hipMalloc(queue)");
+  }
+  *out = t;
+  return TREVR_OK;
+}
+
+void trevr_tree_destroy(trevr_tree *tree) { delete tree; }
+
+int trevr_build_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream) {
+  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
+  int rc = trevr::check_particles(p);
+  if (rc != TREVR_OK) return rc;
+  return trevr::build_tree_impl(tree, p, stream);
+}
+
+int trevr_tree_info(const trevr_tree *tree, trevr_tree_info_t *info) {
+  if (!tree || !info) return trevr::fail(TREVR_E_ARG, "NULL argument");
+  if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");
+  info->n = tree->n;
+  info->m = tree->m;
+  info->n_boxes = tree->n_boxes;
+  info->max_depth = tree->max_depth;
+  info->prec = tree->prec;
+  info->bucket_size = tree->nb;
+  return TREVR_OK;
+}
+
+int trevr_compute_flux(const trevr_tree *tree, double theta_open, double tau_ref,
+                       const int32_t *sinks, int64_t n_sinks, void *flux, int32_t *counters,
+                       hipStream_t stream) {
+  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (n_sinks > 0 && !flux) return trevr::fail(TREVR_E_ARG, "flux is NULL");
+  return trevr::flux_impl(tree, theta_open, tau_ref, sinks, n_sinks, flux, counters, stream);
+}
+
+int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_ref,
+                               const int32_t *sinks, int64_t n_sinks, const void *grad_flux,
+                               void *grad_rho, void *grad_kappa, void *grad_lum,
+                               hipStream_t stream) {
+  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (tree->n > 0 && (!grad_rho || !grad_kappa || !grad_lum))
+    return trevr::fail(TREVR_E_ARG, "a gradient output is NULL");
+  if (n_sinks > 0 && !grad_flux) return trevr::fail(TREVR_E_ARG, "grad_flux is NULL");
+  return trevr::adjoint_impl(tree, theta_open, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
+                             grad_kappa, grad_lum, stream);
+}
+
+int trevr_set_launch(trevr_tree *tree, const trevr_launch *cfg) {
+  if (!tree || !cfg) return trevr::fail(TREVR_E_ARG, "NULL argument");
+  if (cfg->blocks_per_cu < 1 || cfg->blocks_per_cu > 32)
+    return trevr::fail(TREVR_E_ARG, "blocks_per_cu must be 1..32");
+  if (cfg->waves_per_block < 1 || cfg->waves_per_block > 16)
+    return trevr::fail(TREVR_E_ARG, "waves_per_block must be 1..16");
+  if (cfg->chunk < 64 || cfg->chunk % 64 != 0 || cfg->chunk > 4096)
+    return trevr::fail(TREVR_E_ARG, "chunk must be a multiple of 64 in 64..4096");
+  tree->launch = *cfg;
+  return TREVR_OK;
+}
+
+int trevr_get_launch(const trevr_tree *tree, trevr_launch *cfg) {
+  if (!tree || !cfg) return trevr::fail(TREVR_E_ARG, "NULL argument");
+  *cfg = tree->launch;
+  return TREVR_OK;
+}
+
+int trevr_export_tree(const trevr_tree *tree, int64_t *perm, int64_t *leaf_of, int64_t *node_i,
+                      uint64_t *node_key, double *node_f, hipStream_t stream) {
+  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
+  if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");
+  return trevr::export_tree_impl(tree, perm, leaf_of, node_i, node_key, node_f, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,767 @@
+// Per-sink radiation field on gfx950 (Sec. 2.1-2.2.3 of the TREVR paper) and
+// its adjoint.
+//
+// One wavefront evaluates 64 sinks that are adjacent in tree order, so their
+// source walks (Sec. 2.2.1) visit nearly the same cells.  The walk is done
+// once per wave: each visited cell is read with wave-uniform (scalar) loads,
+// every lane applies the opening test (eq. openangle) for its own sink, the
+// accepting lanes trace their ray at once, and the wave descends into a cell
+// if any lane opened it.  Lanes that accepted an ancestor are masked off in
+// its subtree; the per-depth masks and the cell path live in LDS.
+//
+// A ray (Sec. 2.2.2-2.2.3) is traced by its own lane: split at the meeting
+// cell A of the sink bucket S and the source cell C, walk down from A toward
+// S and toward C, and wherever the ray lies in a chain cell's other half use
+// that chain cell's average unless (alpha_max - alpha_min) l > tau_ref, in
+// which case the other half is refined recursively (eq. refcrit).  All
+// geometry and sums are binary64 with no contraction; cell data come from the
+// transport records (binary32 or binary64).
+//
+// The tracer hands every piece (cell, alpha, length, end points) to a policy:
+// the forward sums tau; the adjoint, which re-runs the identical tracer,
+// scatters d(loss)/d(alpha) to the cells and accumulates d tau / d y.
+//
+// Work distribution: a persistent grid; each wave takes chunks of 64 sinks
+// from an atomic queue.  Workgroups are dealt round-robin to the 8 XCDs, so
+// the queue is split into 8 contiguous ranges (one per XCD, taken by
+// blockIdx % 8) and a wave steals from the next range once its own is empty:
+// each XCD's L2 then sees a compact region of the tree.
+#include <cmath>
+
+#include "trevr_internal.h"
+
+namespace trevr {
+
+constexpr int kXcd = 8;
+
+template <typename T>
+struct FluxArgs {
+  const WalkRecT<T> *__restrict__ W;
+  const TraceRecT<T> *__restrict__ TR;
+  const uint64_t *__restrict__ key;
+  const int32_t *__restrict__ ndepth;
+  const P4<T> *__restrict__ ps;
+  const int32_t *__restrict__ perm;
+  const int32_t *__restrict__ inv;
+  const int32_t *__restrict__ leaf;
+  const int32_t *__restrict__ pbox;
+  const int32_t *__restrict__ box_root;
+  const int32_t *__restrict__ sinks;
+  int64_t n_sinks;
+  int64_t n;  // particles
+  int32_t n_chunks;
+  double theta2, tau_ref;
+  T *flux;
+  int32_t *counters;
+  int32_t *queue;  // kXcd counters
+  // adjoint
+  const T *__restrict__ grad_flux;
+  double *abar;    // [m]  d loss / d alpha
+  double *lbar;    // [m]  d loss / d L_C
+  double *xbar;    // [3][m] d loss / d x_L
+  double *direct;  // [n]  d loss / d L_j (rays from single particles), sorted order
+  int64_t m;
+};
+
+__device__ __forceinline__ double sel3(const double v[3], int a) {
+  return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]);
+}
+
+// Atomic adds with an explicit address space: LDS accumulators through
+// ds_add_f64, device memory through global_atomic_add_f64 (never FLAT).
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(1))) double gbl_f64;
+__device__ __forceinline__ void lds_add(double *p, double v) {
+  __builtin_amdgcn_ds_atomic_fadd_f64((lds_f64 *)p, v);
+}
+__device__ __forceinline__ void gbl_add(double *p, double v) {
+  (void)__builtin_amdgcn_global_atomic_fadd_f64((gbl_f64 *)p, v);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+struct RayCtx {
+  double xi[3], d[3], inv[3];
+  double r, r2;
+  double tau_ref;
+  int n_seg, n_trace;
+};
+
+struct StackEntry {
+  int32_t node, tag;
+  double tb;
+};
+
+// A piece's accumulator slot in the adjoint: [0, 64) the sink chain at that
+// depth, [64, 128) the walk path at that depth, -1 the cell itself.
+constexpr int kSlotSrc = 64;
+
+// Forward policy: tau = sum alpha l (eq. tausum).
+struct TauSum {
+  double tau = 0.0;
+  __device__ __forceinline__ void operator()(int, int, double alpha, double l, double, int,
+                                             double, int) {
+    tau += alpha * l;
+  }
+};
+
+// Adjoint policy: d loss / d alpha_cell += -g l, and d tau / d y gets
+// r alpha (d tb/dy - d ta/dy) with d t/d y_a = -t / d_a for a plane crossing.
+struct Scatter {
+  double g;        // weight * flux contribution of the ray
+  double dtdy[3];  // d tau / d y
+  double r;
+  const double *inv;
+  double *abar;
+  double *acc_s, *acc_p;  // LDS, per wave
+  int d_common;           // sink-chain depths <= this are shared by the wave
+  int nodes_s_unused;
+  __device__ __forceinline__ void operator()(int node, int slot, double alpha, double l,
+                                             double ta, int ga, double tb, int gb) {
+    const double v = -(g * l);
+    if (slot >= kSlotSrc)
+      lds_add(&acc_p[slot - kSlotSrc], v);
+    else if (slot >= 0 && slot <= d_common)
+      lds_add(&acc_s[slot], v);
+    else
+      gbl_add(&abar[node], v);
+    if (gb >= 0) {
+      const double q = r * alpha * (-tb * sel3(inv, gb));
+      if (gb == 0) dtdy[0] += q; else if (gb == 1) dtdy[1] += q; else dtdy[2] += q;
+    }
+    if (ga >= 0) {
+      const double q = r * alpha * (-ta * sel3(inv, ga));
+      if (ga == 0) dtdy[0] -= q; else if (ga == 1) dtdy[1] -= q; else dtdy[2] -= q;
+    }
+  }
+};
+
+// Refinement of cell X on [ta, tb]: the cell's own average unless it is not a
+// bucket and (alpha_max - alpha_min) l > tau_ref; then the near and far
+// halves in ray order (an explicit stack replaces the recursion).
+template <typename T, typename Emit>
+__device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, double ta,
+                       int ga, double tb, int gb, RayCtx &c, Emit &emit) {
+  StackEntry stk[kRefineStack];
+  int sp = 0;
+  int cur = X;
+  double cta = ta, ctb = tb;
+  int cga = ga, cgb = gb;
+  for (;;) {
+    const TraceRecT<T> rec = TR[cur];
+    const double l = c.r * (ctb - cta);
+    c.n_trace++;
+    const int right = rax_right(rec.right_ax);
+    if (right == 0 || !((double)rec.dalpha * l > c.tau_ref)) {
+      if (l > 0) c.n_seg++;
+      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb);
+      if (sp == 0) return;
+      --sp;
+      cur = stk[sp].node;
+      cta = ctb;
+      cga = cgb;
+      ctb = stk[sp].tb;
+      cgb = stk[sp].tag;
+      continue;
+    }
+    const int ax = rax_axis(rec.right_ax);
+    const double s = (double)rec.split;
+    const double dax = sel3(c.d, ax), xax = sel3(c.xi, ax);
+    if (dax == 0.0) {  // parallel to the plane: one side only
+      cur = xax >= s ? right : cur + 1;
+      continue;
+    }
+    const double ts = (s - xax) * sel3(c.inv, ax);
+    const int nearc = dax > 0 ? cur + 1 : right;
+    const int farc = dax > 0 ? right : cur + 1;
+    double t1 = ctb;
+    int g1 = cgb;
+    if (ts < ctb) {
+      t1 = ts;
+      g1 = ax;
+    }
+    double t0 = cta;
+    int g0 = cga;
+    if (ts > cta) {
+      t0 = ts;
+      g0 = ax;
+    }
+    const bool has_near = t1 > cta, has_far = ctb > t0;
+    if (has_near) {
+      if (has_far) {
+        stk[sp].node = farc;
+        stk[sp].tag = cgb;
+        stk[sp].tb = ctb;
+        ++sp;
+      }
+      cur = nearc;
+      ctb = t1;
+      cgb = g1;
+    } else if (has_far) {
+      cur = farc;
+      cta = t0;
+      cga = g0;
+    } else {
+      return;  // empty interval (only at the top call)
+    }
+  }
+}
+
+// A piece of the ray in chain cell P but outside P's child on the path: P's
+// own average, or the sibling X refined.
+template <typename T, typename Emit>
+__device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
+                                            const TraceRecT<T> &rP, int P, int slot, int X,
+                                            double ta, int ga, double tb, int gb, RayCtx &c,
+                                            Emit &emit) {
+  const double l = c.r * (tb - ta);
+  c.n_trace++;
+  if ((double)rP.dalpha * l > c.tau_ref) {
+    refine<T>(TR, X, -1, ta, ga, tb, gb, c, emit);
+    return;
+  }
+  if (l > 0) c.n_seg++;
+  emit(P, slot, (double)rP.alpha, l, ta, ga, tb, gb);
+}
+
+struct SinkCtx {
+  int S;
+  uint64_t keyS;
+  int depthS;
+  double alphaS;
+  int anc[kDmax + 1];  // ancestors of S by depth
+};
+
+__device__ __forceinline__ void ray_setup(RayCtx &c, double y0, double y1, double y2) {
+  c.d[0] = y0 - c.xi[0];
+  c.d[1] = y1 - c.xi[1];
+  c.d[2] = y2 - c.xi[2];
+  for (int q = 0; q < 3; ++q) c.inv[q] = c.d[q] != 0.0 ? 1.0 / c.d[q] : 0.0;
+  c.r2 = (c.d[0] * c.d[0] + c.d[1] * c.d[1]) + c.d[2] * c.d[2];
+  c.r = sqrt(c.r2);
+}
+
+// Reverse ray trace from the sink (t = 0) to the source in cell C (t = 1),
+// handing every piece to `emit` in a fixed order: sink chain (from the
+// meeting cell down), the sink's bucket, source chain, the source cell.
+template <typename T, typename Emit>
+__device__ void trace_pieces(const FluxArgs<T> &a, const int32_t *s_path, int C, uint64_t keyC,
+                             int depthC, const SinkCtx &sk, RayCtx &c, Emit &emit) {
+  if (C == sk.S) {
+    c.n_trace++;
+    const double l = c.r * (1.0 - 0.0);
+    if (l > 0) c.n_seg++;
+    emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, 1.0, -1);
+    return;
+  }
+  const int ad = __clzll((long long)(sk.keyS ^ keyC)) - 1;  // depth of the meeting cell
+  const int A = s_path[ad];
+  const TraceRecT<T> rA = a.TR[A];
+  const int axA = rax_axis(rA.right_ax);
+  const int sr = (int)((sk.keyS >> (62 - ad)) & 1);
+  const double dA = sel3(c.d, axA);
+  double tA;
+  int gA = -1;
+  if (dA != 0.0) {
+    tA = ((double)rA.split - sel3(c.xi, axA)) * sel3(c.inv, axA);
+    gA = axA;
+    if (tA < 0.0) {
+      tA = 0.0;
+      gA = -1;
+    }
+    if (tA > 1.0) {
+      tA = 1.0;
+      gA = -1;
+    }
+  } else {
+    tA = sr ? 1.0 : 0.0;  // ray in the plane: it belongs to the upper side
+  }
+  // sink side, [0, tP]
+  double tP = tA;
+  int gP = gA;
+  for (int dd = ad + 1; dd < sk.depthS; ++dd) {
+    const int P = sk.anc[dd];
+    const TraceRecT<T> rP = a.TR[P];
+    const int b = (int)((sk.keyS >> (62 - dd)) & 1);
+    const int ax = rax_axis(rP.right_ax);
+    const double dax = sel3(c.d, ax);
+    if (dax != 0.0 && (b ? dax < 0.0 : dax > 0.0)) {
+      double tc = ((double)rP.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
+      int gc = ax;
+      if (tc < 0.0) {
+        tc = 0.0;
+        gc = -1;
+      }
+      if (tc < tP) {
+        const int sib = b ? P + 1 : rax_right(rP.right_ax);
+        chain_piece<T>(a.TR, rP, P, dd, sib, tc, gc, tP, gP, c, emit);
+        tP = tc;
+        gP = gc;
+      }
+    }
+  }
+  {
+    c.n_trace++;
+    const double l = c.r * (tP - 0.0);
+    if (l > 0) c.n_seg++;
+    emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, tP, gP);
+  }
+  // source side, [tQ, 1]
+  double tQ = tA;
+  int gQ = gA;
+  for (int dd = ad + 1; dd < depthC; ++dd) {
+    const int Q = s_path[dd];
+    const TraceRecT<T> rQ = a.TR[Q];
+    const int b = (int)((keyC >> (62 - dd)) & 1);
+    const int ax = rax_axis(rQ.right_ax);
+    const double dax = sel3(c.d, ax);
+    if (dax != 0.0 && (b ? dax > 0.0 : dax < 0.0)) {
+      double tc = ((double)rQ.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
+      int gc = ax;
+      if (tc > 1.0) {
+        tc = 1.0;
+        gc = -1;
+      }
+      if (tc > tQ) {
+        const int sib = b ? Q + 1 : rax_right(rQ.right_ax);
+        chain_piece<T>(a.TR, rQ, Q, kSlotSrc + dd, sib, tQ, gQ, tc, gc, c, emit);
+        tQ = tc;
+        gQ = gc;
+      }
+    }
+  }
+  refine<T>(a.TR, C, kSlotSrc + depthC, tQ, gQ, 1.0, -1, c, emit);
+}
+
+__device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
+  // contiguous range per XCD, then steal from the following ranges
+  const int x0 = (int)(blockIdx.x % kXcd);
+  const int per = (n_chunks + kXcd - 1) / kXcd;
+  for (int k = 0; k < kXcd; ++k) {
+    const int x = (x0 + k) % kXcd;
+    const int lo = x * per;
+    const int hi = min(n_chunks, lo + per);
+    if (lo >= hi) continue;
+    int got = 0;
+    if ((threadIdx.x & 63) == 0) got = atomicAdd(&queue[x], 1);
+    got = __shfl(got, 0);
+    if (lo + got < hi) return lo + got;
+  }
+  return -1;
+}
+
+// Per-wave LDS: open masks, walk path, and (adjoint) two accumulator rows.
+template <bool ADJ>
+__host__ __device__ constexpr size_t lds_per_wave() {
+  return 64 * 8 + 64 * 4 + (ADJ ? 2 * 64 * 8 : 0);
+}
+
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(256) void k_walk(FluxArgs<T> a) {
+  extern __shared__ unsigned char smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  unsigned char *base = smem + wv * lds_per_wave<ADJ>();
+  uint64_t *s_open = reinterpret_cast<uint64_t *>(base);
+  int32_t *s_path = reinterpret_cast<int32_t *>(base + 64 * 8);
+  double *acc_s = reinterpret_cast<double *>(base + 64 * 12);
+  double *acc_p = acc_s + 64;
+  if (ADJ) {
+    acc_s[lane] = 0.0;
+    acc_p[lane] = 0.0;
+  }
+  for (;;) {
+    const int chunk = wave_take(a.queue, a.n_chunks);
+    if (chunk < 0) break;
+    const int64_t q = (int64_t)chunk * 64 + lane;
+    const bool in_list = q < a.n_sinks;
+    bool bad = false;  // a sink index outside [0, n)
+    int k = 0;
+    if (in_list) {
+      if (a.sinks) {
+        const int32_t si = a.sinks[q];
+        bad = si < 0 || (int64_t)si >= a.n;
+        if (!bad) k = a.inv[si];
+      } else {
+        k = (int)q;
+      }
+    }
+    const bool valid = in_list && !bad;
+    const P4<T> me = a.ps[k];
+    SinkCtx sk;
+    RayCtx c;
+    c.xi[0] = (double)me.x;
+    c.xi[1] = (double)me.y;
+    c.xi[2] = (double)me.z;
+    c.tau_ref = a.tau_ref;
+    c.n_seg = 0;
+    c.n_trace = 0;
+    sk.S = a.leaf[k];
+    sk.keyS = a.key[sk.S];
+    sk.depthS = a.ndepth[sk.S];
+    sk.alphaS = (double)a.TR[sk.S].alpha;
+    const int my_root = a.box_root[a.pbox[k]];
+    {  // the ancestors of the sink's bucket, by depth
+      int node = my_root;
+      for (int dd = 0; dd <= sk.depthS; ++dd) {
+        sk.anc[dd] = node;
+        if (dd < sk.depthS) {
+          const int right = rax_right(a.TR[node].right_ax);
+          node = ((sk.keyS >> (62 - dd)) & 1) ? right : node + 1;
+        }
+      }
+    }
+    const uint64_t vmask = __ballot(valid);
+    const int lead0 = __ffsll((unsigned long long)vmask) - 1;
+    // sink-chain depths whose cell is the same for every valid lane
+    int d_common = -1;
+    double wgt = 0.0;
+    if (ADJ) {
+      // grad_flux is indexed like flux: by list position, or by particle
+      if (valid) wgt = (double)a.grad_flux[a.sinks ? q : (int64_t)a.perm[k]];
+      const int dmin = __shfl(valid ? sk.depthS : 1000, lead0);
+      for (int dd = 0; dd <= kDmax; ++dd) {
+        const int mine_node = (dd <= sk.depthS) ? sk.anc[dd] : -1;
+        const int ref = __shfl(mine_node, lead0);
+        const bool differs = valid && (mine_node != ref || ref < 0);
+        if (__ballot(differs) != 0 || dd > dmin) break;
+        d_common = dd;
+      }
+    }
+    double F = 0.0;
+    int n_open = 0, n_rays = 0, n_psrc = 0;
+    uint64_t pending = vmask;
+    while (pending) {
+      const int lead = __ffsll((unsigned long long)pending) - 1;
+      const int root = __shfl(my_root, lead);
+      const uint64_t group = __ballot(valid && my_root == root);
+      pending &= ~group;
+      const int end = a.W[root].skip;
+      int n = root;
+      int depth_prev = 0;
+      uint64_t active = group;
+      bool from_skip = false;
+      s_path[0] = root;
+      for (;;) {
+        const WalkRecT<T> w = a.W[n];
+        const int depth = w.depth;
+        if (from_skip) {
+          if (ADJ && lane == 0) {  // the path cells at depths >= depth are done
+            for (int dd = depth; dd <= depth_prev; ++dd) {
+              const double v = acc_p[dd];
+              if (v != 0.0) gbl_add(&a.abar[s_path[dd]], v);
+              acc_p[dd] = 0.0;
+            }
+          }
+          active = s_open[depth - 1];
+          s_path[depth] = n;
+        }
+        depth_prev = depth;
+        const bool mine = (active >> lane) & 1;
+        bool descend = false;
+        uint64_t openm = 0;
+        if (w.L != (T)0) {
+          bool acc = false;
+          if (mine) {
+            n_open++;
+            double g[3];
+            for (int q3 = 0; q3 < 3; ++q3) {
+              const double u = (double)w.lo[q3] - c.xi[q3];
+              const double v = c.xi[q3] - (double)w.hi[q3];
+              const double gg = u > v ? u : v;
+              g[q3] = gg > 0.0 ? gg : 0.0;
+            }
+            const double r2 = (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+            const double lf = (double)w.lfar;
+            acc = lf * lf < a.theta2 * r2;
+          }
+          const uint64_t accm = __ballot(acc);
+          const uint64_t keyC = a.key[n];
+          double cl = 0.0, cx0 = 0.0, cx1 = 0.0, cx2 = 0.0;
+          if (acc) {
+            n_rays++;
+            ray_setup(c, (double)w.xl[0], (double)w.xl[1], (double)w.xl[2]);
+            TauSum ts;
+            trace_pieces<T>(a, s_path, n, keyC, depth, sk, c, ts);
+            const double f = ((double)w.L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
+            if (!ADJ) {
+              F += f;
+            } else {
+              Scatter sc;
+              sc.g = wgt * f;
+              for (int q3 = 0; q3 < 3; ++q3) sc.dtdy[q3] = (ts.tau / c.r) * (c.d[q3] / c.r);
+              sc.r = c.r;
+              sc.inv = c.inv;
+              sc.abar = a.abar;
+              sc.acc_s = acc_s;
+              sc.acc_p = acc_p;
+              sc.d_common = d_common;
+              trace_pieces<T>(a, s_path, n, keyC, depth, sk, c, sc);
+              cl = sc.g / (double)w.L;
+              cx0 = sc.g * (-2.0 * c.d[0] / c.r2 - sc.dtdy[0]);
+              cx1 = sc.g * (-2.0 * c.d[1] / c.r2 - sc.dtdy[1]);
+              cx2 = sc.g * (-2.0 * c.d[2] / c.r2 - sc.dtdy[2]);
+            }
+          }
+          if (ADJ && accm) {  // d loss / d L_C and d loss / d x_L of this cell
+            const double s0 = wave_sum(cl), s1 = wave_sum(cx0), s2 = wave_sum(cx1),
+                         s3 = wave_sum(cx2);
+            if (lane == 0) {
+              gbl_add(&a.lbar[n], s0);
+              gbl_add(&a.xbar[n], s1);
+              gbl_add(&a.xbar[a.m + n], s2);
+              gbl_add(&a.xbar[2 * a.m + n], s3);
+            }
+          }
+          openm = active & ~accm;
+          if (openm) {
+            if (rax_right(w.right_ax) == 0) {  // bucket: its particles one by one
+              const bool op = (openm >> lane) & 1;
+              for (int kk = w.first; kk < w.first + w.count; ++kk) {
+                const P4<T> pj = a.ps[kk];
+                const bool use = op && pj.L > (T)0 && kk != k &&
+                                 !(pj.x == me.x && pj.y == me.y && pj.z == me.z);
+                double dl = 0.0;
+                if (use) {
+                  n_rays++;
+                  n_psrc++;
+                  ray_setup(c, (double)pj.x, (double)pj.y, (double)pj.z);
+                  TauSum ts;
+                  trace_pieces<T>(a, s_path, n, keyC, depth, sk, c, ts);
+                  const double f = ((double)pj.L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
+                  if (!ADJ) {
+                    F += f;
+                  } else {
+                    Scatter sc;
+                    sc.g = wgt * f;
+                    sc.dtdy[0] = sc.dtdy[1] = sc.dtdy[2] = 0.0;
+                    sc.r = c.r;
+                    sc.inv = c.inv;
+                    sc.abar = a.abar;
+                    sc.acc_s = acc_s;
+                    sc.acc_p = acc_p;
+                    sc.d_common = d_common;
+                    trace_pieces<T>(a, s_path, n, keyC, depth, sk, c, sc);
+                    dl = sc.g / (double)pj.L;
+                  }
+                }
+                if (ADJ && __ballot(use)) {
+                  const double s0 = wave_sum(dl);
+                  if (lane == 0) gbl_add(&a.direct[kk], s0);
+                }
+              }
+            } else {
+              descend = true;
+            }
+          }
+        }
+        if (descend) {
+          s_open[depth] = openm;
+          active = openm;
+          n = n + 1;
+          s_path[depth + 1] = n;
+          from_skip = false;
+          continue;
+        }
+        n = w.skip;
+        if (n >= end) break;
+        from_skip = true;
+      }
+      if (ADJ && lane == 0) {
+        for (int dd = 0; dd <= depth_prev; ++dd) {
+          const double v = acc_p[dd];
+          if (v != 0.0) gbl_add(&a.abar[s_path[dd]], v);
+          acc_p[dd] = 0.0;
+        }
+      }
+    }
+    if (ADJ) {
+      if (lane == lead0) {
+        for (int dd = 0; dd <= d_common; ++dd) {
+          const double v = acc_s[dd];
+          if (v != 0.0) gbl_add(&a.abar[sk.anc[dd]], v);
+          acc_s[dd] = 0.0;
+        }
+      }
+    } else if (in_list) {
+      const int64_t out = a.sinks ? q : (int64_t)a.perm[k];
+      a.flux[out] = bad ? (T)NAN : (T)F;
+      if (a.counters) {
+        int32_t *o = a.counters + 5 * out;
+        o[0] = bad ? -1 : n_open;
+        o[1] = bad ? -1 : n_rays;
+        o[2] = bad ? -1 : n_psrc;
+        o[3] = bad ? -1 : c.n_seg;
+        o[4] = bad ? -1 : c.n_trace;
+      }
+    }
+  }
+}
+
+__global__ void k_zero_i32(int32_t *p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_zero_f64(double *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// A cell without absorbing mass took its parent's alpha: its adjoint goes to
+// the parent (one level, deepest first).
+__global__ void k_adj_empty_up(const BfsNode *lvl, int cnt, const double *B,
+                               const int32_t *parent, double *abar) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt) return;
+  const int p = lvl[j].pre;
+  const int par = parent[p];
+  if (par >= 0 && !(B[p] > 0)) gbl_add(&abar[par], abar[p]);
+}
+
+// Per particle: sum over the cells holding it (bucket up to the root) of
+//   d alpha / d kappa_p = m_p / B,  d alpha / d rho_p = alpha m_p / (B rho_p^2),
+//   d L_C / d L_p = 1,  d x_L / d L_p = (x_p - x_L) / L_C.
+template <typename T>
+__global__ void k_adj_particles(int64_t n, int64_t m, const int32_t *perm, const int32_t *leaf,
+                                const int32_t *parent, const double *B, const double *alpha,
+                                const double *lc, const double *xl, const P4<T> *ps,
+                                const T *pmass, const T *prho, const double *abar,
+                                const double *lbar, const double *xbar, const double *direct,
+                                T *grad_rho, T *grad_kappa, T *grad_lum) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const P4<T> p = ps[k];
+  const double x[3] = {(double)p.x, (double)p.y, (double)p.z};
+  const double mp = (double)pmass[k], rp = (double)prho[k];
+  double gk = 0.0, gr = 0.0, gl = direct[k];
+  for (int id = leaf[k]; id >= 0; id = parent[id]) {
+    const double Bc = B[id];
+    if (Bc > 0 && mp > 0) {
+      gk += abar[id] * mp / Bc;
+      gr += abar[id] * alpha[id] * mp / (Bc * rp * rp);
+    }
+    const double L = lc[id];
+    if (L > 0) {
+      double dot = 0.0;
+      for (int q = 0; q < 3; ++q) dot += xbar[q * m + id] * (x[q] - xl[q * m + id]);
+      gl += lbar[id] + dot / L;
+    }
+  }
+  const int i = perm[k];
+  grad_rho[i] = (T)gr;
+  grad_kappa[i] = (T)gk;
+  grad_lum[i] = (T)gl;
+}
+
+static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+template <typename T>
+static FluxArgs<T> make_args(const trevr_tree *t, double theta, double tau_ref,
+                             const int32_t *sinks, int64_t n_sinks) {
+  FluxArgs<T> a{};
+  a.W = static_cast<const WalkRecT<T> *>(t->walk.p);
+  a.TR = static_cast<const TraceRecT<T> *>(t->trace.p);
+  a.key = t->key.as<uint64_t>();
+  a.ndepth = t->n_depth.as<int32_t>();
+  a.ps = static_cast<const P4<T> *>(t->psrc.p);
+  a.perm = t->perm.as<int32_t>();
+  a.inv = t->inv.as<int32_t>();
+  a.leaf = t->leaf.as<int32_t>();
+  a.pbox = t->pbox.as<int32_t>();
+  a.box_root = t->box_root.as<int32_t>();
+  a.sinks = sinks;
+  a.n_sinks = n_sinks;
+  a.n = t->n;
+  a.n_chunks = (int32_t)((n_sinks + 63) / 64);
+  a.theta2 = theta * theta;
+  a.tau_ref = tau_ref;
+  a.queue = t->queue.as<int32_t>();
+  a.m = t->m;
+  return a;
+}
+
+template <typename T, bool ADJ>
+static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s) {
+  k_zero_i32<<<1, 64, 0, s>>>(a.queue, kXcd);
+  const int waves = t->launch.waves_per_block > 4 ? 4 : t->launch.waves_per_block;
+  const int threads = 64 * waves;
+  int64_t blocks = (int64_t)t->launch.blocks_per_cu * t->num_cu;
+  const int64_t need = (a.n_chunks + waves - 1) / waves;
+  if (blocks > need) blocks = need;
+  const size_t shmem = (size_t)waves * lds_per_wave<ADJ>();
+  k_walk<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  TREVR_HIP(hipGetLastError());
+  return TREVR_OK;
+}
+
+template <typename T>
+static int flux_typed(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                      int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s) {
+  if (n_sinks == 0) return TREVR_OK;
+  FluxArgs<T> a = make_args<T>(t, theta, tau_ref, sinks, n_sinks);
+  a.flux = static_cast<T *>(flux);
+  a.counters = counters;
+  return launch_walk<T, false>(t, a, s);
+}
+
+int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+              int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s) {
+  if (t->prec == TREVR_F64)
+    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
+  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
+}
+
+template <typename T>
+static int adjoint_typed(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                         int64_t n_sinks, const void *grad_flux, void *grad_rho,
+                         void *grad_kappa, void *grad_lum, hipStream_t s) {
+  const int64_t m = t->m, n = t->n;
+  TREVR_HIP(t->adj_node.ensure(sizeof(double) * 5 * (size_t)(m > 0 ? m : 1)));
+  TREVR_HIP(t->adj_part.ensure(sizeof(double) * (size_t)(n > 0 ? n : 1)));
+  double *abar = t->adj_node.as<double>();
+  double *lbar = abar + m, *xbar = abar + 2 * m;
+  double *direct = t->adj_part.as<double>();
+  k_zero_f64<<<nblk(5 * m), 256, 0, s>>>(abar, 5 * m);
+  if (n > 0) k_zero_f64<<<nblk(n), 256, 0, s>>>(direct, n);
+  if (n_sinks > 0) {
+    FluxArgs<T> a = make_args<T>(t, theta, tau_ref, sinks, n_sinks);
+    a.grad_flux = static_cast<const T *>(grad_flux);
+    a.abar = abar;
+    a.lbar = lbar;
+    a.xbar = xbar;
+    a.direct = direct;
+    int rc = launch_walk<T, true>(t, a, s);
+    if (rc != TREVR_OK) return rc;
+  }
+  const BfsNode *bfs = t->bfs.as<BfsNode>();
+  for (int d = (int)t->level_cnt.size() - 1; d >= 1; --d)
+    k_adj_empty_up<<<nblk(t->level_cnt[d]), 256, 0, s>>>(
+        bfs + t->level_off[d], (int)t->level_cnt[d], t->n_B.as<double>(),
+        t->n_parent.as<int32_t>(), abar);
+  if (n > 0)
+    k_adj_particles<T><<<nblk(n), 256, 0, s>>>(
+        n, m, t->perm.as<int32_t>(), t->leaf.as<int32_t>(), t->n_parent.as<int32_t>(),
+        t->n_B.as<double>(), t->n_alpha.as<double>(), t->n_lc.as<double>(),
+        t->n_xl.as<double>(), static_cast<const P4<T> *>(t->psrc.p),
+        static_cast<const T *>(t->pmass.p), static_cast<const T *>(t->prho.p), abar, lbar, xbar,
+        direct, static_cast<T *>(grad_rho), static_cast<T *>(grad_kappa),
+        static_cast<T *>(grad_lum));
+  TREVR_HIP(hipGetLastError());
+  return TREVR_OK;
+}
+
+int adjoint_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                 int64_t n_sinks, const void *grad_flux, void *grad_rho, void *grad_kappa,
+                 void *grad_lum, hipStream_t s) {
+  if (t->prec == TREVR_F64)
+    return adjoint_typed<double>(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
+                                 grad_kappa, grad_lum, s);
+  return adjoint_typed<float>(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
+                              grad_kappa, grad_lum, s);
+}
+
+}  // namespace trevr

@@ -1,0 +1,174 @@
+// Internal layouts of the TREVR gfx950 library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "trevr.h"
+
+namespace trevr {
+
+constexpr int kDmax = 63;           // deepest level; 63 path bits per key
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kRefineStack = 64;    // refinement recursion never exceeds the depth
+
+// ---- transport records (what the kernels read in the hot loops) ----------
+//
+// Source-walk record, one per cell in depth-first order.  Read wave-uniformly
+// (scalar loads) by the opening test; 64 B in binary32, 128 B in binary64.
+template <typename T>
+struct WalkRecT;
+template <>
+struct alignas(64) WalkRecT<float> {
+  float lo[3], hi[3];  // space-filling box
+  float xl[3];         // centre of luminosity
+  float L;             // luminosity (0: no sources below)
+  float lfar;          // centre of luminosity -> furthest vertex
+  int32_t skip;        // next cell after this subtree
+  int32_t right_ax;    // upper child (0 at a leaf) | split axis << 30
+  int32_t first;       // first particle (sorted order)
+  int32_t count;       // particles in the cell
+  int32_t depth;
+};
+template <>
+struct alignas(64) WalkRecT<double> {
+  double lo[3], hi[3];
+  double xl[3];
+  double L;
+  double lfar;
+  int32_t skip, right_ax, first, count, depth;
+  int32_t pad[5];
+};
+static_assert(sizeof(WalkRecT<float>) == 64, "walk record layout");
+static_assert(sizeof(WalkRecT<double>) == 128, "walk record layout");
+
+// Ray-trace record: what a chain step or a refinement step reads.
+template <typename T>
+struct TraceRecT;
+template <>
+struct alignas(16) TraceRecT<float> {
+  float split, alpha, dalpha;
+  int32_t right_ax;
+};
+template <>
+struct alignas(32) TraceRecT<double> {
+  double split, alpha, dalpha;
+  int32_t right_ax, pad;
+};
+static_assert(sizeof(TraceRecT<float>) == 16, "trace record layout");
+static_assert(sizeof(TraceRecT<double>) == 32, "trace record layout");
+
+// Particle in sorted order: position and luminosity.
+template <typename T>
+struct P4;
+template <>
+struct alignas(16) P4<float> {
+  float x, y, z, L;
+};
+template <>
+struct alignas(32) P4<double> {
+  double x, y, z, L;
+};
+
+__host__ __device__ inline int rax_right(int32_t ra) { return ra & 0x3fffffff; }
+__host__ __device__ inline int rax_axis(int32_t ra) { return (int)((uint32_t)ra >> 30); }
+
+// Level-order (breadth-first) cell record used while building.
+struct BfsNode {
+  int32_t first, count, box, parent;  // parent: index in the previous level
+  int32_t child;                      // index of the lower child in the next level, -1 leaf
+  int32_t size;                       // cells in the subtree
+  int32_t pre;                        // depth-first index
+  int32_t pad;
+  uint64_t prefix;                    // path bits
+  double lo[3], hi[3];
+};
+
+// ---- device buffers -------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t need) {
+    if (need <= bytes && p) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    size_t want = need < 256 ? 256 : need;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename U>
+  U *as() const {
+    return static_cast<U *>(p);
+  }
+};
+
+}  // namespace trevr
+
+// The tree handle.
+struct trevr_tree {
+  bool built = false;
+  int64_t n = 0, m = 0;
+  trevr_prec prec = TREVR_F32;
+  int32_t nb = 8;
+  int32_t n_boxes = 0;
+  int32_t max_depth = 0;
+  int device = 0;
+  int num_cu = 256;
+  trevr_launch launch{2, 4, 64};
+
+  // transport
+  trevr::DevBuf walk, trace, key, psrc;
+  // particles in sorted order
+  trevr::DevBuf perm, inv, leaf, pbox, pmass, prho;
+  // per box
+  trevr::DevBuf box_root, box_off, box_lo, box_hi, axis_tab;
+  std::vector<int32_t> h_box_root;
+  std::vector<int64_t> h_box_off;
+  // binary64 cell data (build, export, adjoint)
+  trevr::DevBuf n_first, n_count, n_depth, n_parent, n_right, n_skip, n_box, n_axis;
+  trevr::DevBuf n_lo, n_hi, n_split, n_A, n_B, n_SL, n_SLx, n_alpha, n_amin, n_amax;
+  trevr::DevBuf n_alpha_min, n_alpha_max, n_dalpha, n_xl, n_lc, n_lfar;
+  // build scratch
+  trevr::DevBuf keys_in, keys_out, vals_in, vals_out, sort_tmp, bfs, flags, scan, err;
+  trevr::DevBuf box_key, skeys, small;
+  std::vector<int64_t> level_off, level_cnt;
+  // work queue (one counter per XCD) and adjoint scratch
+  trevr::DevBuf queue;
+  trevr::DevBuf adj_node, adj_part;
+
+  ~trevr_tree();
+};
+
+namespace trevr {
+// error reporting (per host thread)
+int fail(int status, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+int build_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s);
+int export_tree_impl(const trevr_tree *t, int64_t *perm, int64_t *leaf_of, int64_t *node_i,
+                     uint64_t *node_key, double *node_f, hipStream_t s);
+int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+              int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s);
+int adjoint_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                 int64_t n_sinks, const void *grad_flux, void *grad_rho, void *grad_kappa,
+                 void *grad_lum, hipStream_t s);
+}  // namespace trevr
+
+#define TREVR_HIP(call)                                      \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return ::trevr::hip_fail(e_, #call); \
+  } while (0)

@@ -1,0 +1,290 @@
+"""Python binding of ``libtrevr.so`` (ctypes).
+
+Argument marshalling only: every step of the radiation-field path runs in the
+library's HIP kernels; torch provides device memory and the current stream.
+The names follow the C ABI in ``include/trevr.h``:
+
+    tree = build_tree(pos, rho, kappa, lum, mass=None, ...)
+    F = compute_flux(tree, theta_open, tau_ref, sinks=None)
+    g_rho, g_kappa, g_lum = compute_flux_adjoint(tree, theta_open, tau_ref, grad_flux)
+
+If the library has not been built the import of this module succeeds but
+every call raises ``TrevrNotBuilt``; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrevr.so")
+
+TREVR_F32, TREVR_F64 = 0, 1
+COUNTER_FIELDS = ("n_open", "n_rays", "n_psrc", "n_seg", "n_trace")
+
+
+class TrevrNotBuilt(RuntimeError):
+    pass
+
+
+class TrevrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("trevr status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Particles(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("prec", ctypes.c_int),
+        ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
+        ("lum", ctypes.c_void_p), ("n_boxes", ctypes.c_int32),
+        ("box_offsets", ctypes.POINTER(ctypes.c_int64)),
+        ("box_lo", ctypes.POINTER(ctypes.c_double)), ("box_hi", ctypes.POINTER(ctypes.c_double)),
+        ("bucket_size", ctypes.c_int32),
+    ]
+
+
+class _Launch(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("chunk", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("n_boxes", ctypes.c_int32),
+                ("max_depth", ctypes.c_int32), ("prec", ctypes.c_int),
+                ("bucket_size", ctypes.c_int32)]
+
+
+_lib = None
+
+EXPORTED = (
+    "trevr_status_string", "trevr_last_error", "trevr_tree_create", "trevr_tree_destroy",
+    "trevr_build_tree", "trevr_tree_info", "trevr_compute_flux", "trevr_compute_flux_adjoint",
+    "trevr_set_launch", "trevr_get_launch", "trevr_export_tree",
+)
+
+
+def lib():
+    """Load the library (raises TrevrNotBuilt if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TrevrNotBuilt("%s is missing: build it with `python -m paper_1902_08083_amd.build`"
+                            % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    L.trevr_status_string.restype = ctypes.c_char_p
+    L.trevr_status_string.argtypes = [I]
+    L.trevr_last_error.restype = ctypes.c_char_p
+    L.trevr_last_error.argtypes = []
+    L.trevr_tree_create.restype = I
+    L.trevr_tree_create.argtypes = [ctypes.POINTER(P)]
+    L.trevr_tree_destroy.restype = None
+    L.trevr_tree_destroy.argtypes = [P]
+    L.trevr_build_tree.restype = I
+    L.trevr_build_tree.argtypes = [P, ctypes.POINTER(_Particles), P]
+    L.trevr_tree_info.restype = I
+    L.trevr_tree_info.argtypes = [P, ctypes.POINTER(_Info)]
+    L.trevr_compute_flux.restype = I
+    L.trevr_compute_flux.argtypes = [P, D, D, P, I64, P, P, P]
+    L.trevr_compute_flux_adjoint.restype = I
+    L.trevr_compute_flux_adjoint.argtypes = [P, D, D, P, I64, P, P, P, P, P]
+    L.trevr_set_launch.restype = I
+    L.trevr_set_launch.argtypes = [P, ctypes.POINTER(_Launch)]
+    L.trevr_get_launch.restype = I
+    L.trevr_get_launch.argtypes = [P, ctypes.POINTER(_Launch)]
+    L.trevr_export_tree.restype = I
+    L.trevr_export_tree.argtypes = [P, P, P, P, P, P, P]
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().trevr_last_error().decode(errors="replace")
+        raise TrevrError(rc, msg)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_array(a, dtype, device):
+    t = torch.as_tensor(a, device=device)
+    if t.dtype != dtype:
+        raise TypeError("expected %s, got %s" % (dtype, t.dtype))
+    return t.contiguous()
+
+
+class Tree:
+    """A radiation tree (one or more boxes) held on the GPU."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().trevr_tree_create(ctypes.byref(h)))
+        self._h = h
+        self.n = 0
+        self.prec = None
+        self.dtype = None
+        self.device = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.trevr_tree_destroy(h)
+            self._h = None
+
+    # -- build -----------------------------------------------------------
+    def build(self, pos, rho, kappa, lum, mass=None, box_lo=(0.0, 0.0, 0.0),
+              box_hi=(1.0, 1.0, 1.0), bucket_size=8, box_offsets=None, device="cuda"):
+        """pos: (n, 3) tensor; rho, kappa, lum, mass: (n,) of the same float dtype
+        (float32 -> binary32 transport, float64 -> binary64).  box_lo/box_hi:
+        one corner triple, or (n_boxes, 3) with box_offsets (n_boxes + 1)."""
+        pos = torch.as_tensor(pos, device=device)
+        dtype = pos.dtype
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("positions must be float32 or float64")
+        n = int(pos.shape[0])
+        keep = [pos[:, 0].contiguous(), pos[:, 1].contiguous(), pos[:, 2].contiguous(),
+                None if mass is None else _dev_array(mass, dtype, pos.device),
+                _dev_array(rho, dtype, pos.device), _dev_array(kappa, dtype, pos.device),
+                _dev_array(lum, dtype, pos.device)]
+        lo = torch.as_tensor(box_lo, dtype=torch.float64).reshape(-1, 3).contiguous()
+        hi = torch.as_tensor(box_hi, dtype=torch.float64).reshape(-1, 3).contiguous()
+        nbox = int(lo.shape[0])
+        if box_offsets is None:
+            if nbox != 1:
+                raise ValueError("box_offsets are needed for several boxes")
+            off = None
+        else:
+            off = torch.as_tensor(box_offsets, dtype=torch.int64).contiguous()
+        p = _Particles()
+        p.n = n
+        p.prec = TREVR_F64 if dtype == torch.float64 else TREVR_F32
+        p.x, p.y, p.z, p.mass, p.rho, p.kappa, p.lum = [
+            None if t is None else t.data_ptr() for t in keep]
+        p.n_boxes = nbox
+        p.box_offsets = (None if off is None else
+                         ctypes.cast(off.data_ptr(), ctypes.POINTER(ctypes.c_int64)))
+        p.box_lo = ctypes.cast(lo.data_ptr(), ctypes.POINTER(ctypes.c_double))
+        p.box_hi = ctypes.cast(hi.data_ptr(), ctypes.POINTER(ctypes.c_double))
+        p.bucket_size = int(bucket_size)
+        _check(lib().trevr_build_tree(self._h, ctypes.byref(p), _stream()))
+        self.n = n
+        self.dtype = dtype
+        self.prec = p.prec
+        self.device = pos.device
+        self.n_boxes = nbox
+        return self
+
+    def info(self):
+        i = _Info()
+        _check(lib().trevr_tree_info(self._h, ctypes.byref(i)))
+        return {"n": i.n, "m": i.m, "n_boxes": i.n_boxes, "max_depth": i.max_depth,
+                "prec": i.prec, "bucket_size": i.bucket_size}
+
+    def set_launch(self, blocks_per_cu=2, waves_per_block=4, chunk=64):
+        c = _Launch(int(blocks_per_cu), int(waves_per_block), int(chunk))
+        _check(lib().trevr_set_launch(self._h, ctypes.byref(c)))
+
+    def get_launch(self):
+        c = _Launch()
+        _check(lib().trevr_get_launch(self._h, ctypes.byref(c)))
+        return {"blocks_per_cu": c.blocks_per_cu, "waves_per_block": c.waves_per_block,
+                "chunk": c.chunk}
+
+    # -- walks -----------------------------------------------------------
+    def _sinks(self, sinks):
+        if sinks is None:
+            return None, self.n
+        s = torch.as_tensor(sinks, device=self.device).to(torch.int32).contiguous()
+        return s, int(s.shape[0])
+
+    def flux(self, theta_open, tau_ref, sinks=None, counters=False, out=None):
+        s, ns = self._sinks(sinks)
+        F = out if out is not None else torch.empty(ns, dtype=self.dtype, device=self.device)
+        C = torch.empty((ns, 5), dtype=torch.int32, device=self.device) if counters else None
+        _check(lib().trevr_compute_flux(self._h, float(theta_open), float(tau_ref), _ptr(s), ns,
+                                        _ptr(F), _ptr(C), _stream()))
+        return (F, C) if counters else F
+
+    def adjoint(self, theta_open, tau_ref, grad_flux, sinks=None):
+        s, ns = self._sinks(sinks)
+        g = grad_flux.to(device=self.device, dtype=self.dtype).contiguous()
+        if g.shape[0] != ns:
+            raise ValueError("grad_flux has %d entries, expected %d" % (g.shape[0], ns))
+        outs = [torch.empty(self.n, dtype=self.dtype, device=self.device) for _ in range(3)]
+        _check(lib().trevr_compute_flux_adjoint(self._h, float(theta_open), float(tau_ref),
+                                                _ptr(s), ns, _ptr(g), _ptr(outs[0]),
+                                                _ptr(outs[1]), _ptr(outs[2]), _stream()))
+        return tuple(outs)
+
+    def export(self):
+        """Host copy of the tree, in the oracle's field layout (numpy)."""
+        import numpy as np
+        info = self.info()
+        n, m = info["n"], info["m"]
+        perm = np.empty(n, np.int64)
+        leaf_of = np.empty(n, np.int64)
+        node_i = np.empty((m, 8), np.int64)
+        node_key = np.empty(m, np.uint64)
+        node_f = np.empty((m, 22), np.float64)
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(lib().trevr_export_tree(self._h, c(perm), c(leaf_of), c(node_i), c(node_key),
+                                       c(node_f), _stream()))
+        from . import NODE_F_FIELDS, NODE_I_FIELDS
+        out = {"perm": perm, "leaf_of": leaf_of, "key": node_key}
+        for j, f in enumerate(NODE_I_FIELDS):
+            out[f] = node_i[:, j].copy()
+        for j, f in enumerate(NODE_F_FIELDS):
+            out[f] = node_f[:, j].copy()
+        return out
+
+
+def build_tree(pos, rho, kappa, lum, mass=None, box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0),
+               bucket_size=8, box_offsets=None, device="cuda", tree=None):
+    t = tree if tree is not None else Tree()
+    return t.build(pos, rho, kappa, lum, mass, box_lo, box_hi, bucket_size, box_offsets, device)
+
+
+def compute_flux(tree, theta_open, tau_ref, sinks=None, counters=False, out=None):
+    return tree.flux(theta_open, tau_ref, sinks, counters, out)
+
+
+def compute_flux_adjoint(tree, theta_open, tau_ref, grad_flux, sinks=None):
+    return tree.adjoint(theta_open, tau_ref, grad_flux, sinks)
+
+
+class TrevrFlux(torch.autograd.Function):
+    """F = flux(rho, kappa, lum) at fixed positions; backward runs the adjoint
+    kernel over the same traversal (decisions held fixed)."""
+
+    @staticmethod
+    def forward(ctx, rho, kappa, lum, pos, mass, theta_open, tau_ref, bucket_size, sinks):
+        tree = build_tree(pos, rho.detach(), kappa.detach(), lum.detach(), mass,
+                          bucket_size=bucket_size, device=pos.device)
+        F = tree.flux(theta_open, tau_ref, sinks)
+        ctx.tree = tree
+        ctx.args = (theta_open, tau_ref, sinks)
+        return F
+
+    @staticmethod
+    def backward(ctx, gF):
+        theta_open, tau_ref, sinks = ctx.args
+        g_rho, g_kappa, g_lum = ctx.tree.adjoint(theta_open, tau_ref, gF.contiguous(), sinks)
+        ctx.tree = None
+        return g_rho, g_kappa, g_lum, None, None, None, None, None, None
+
+
+def flux(pos, rho, kappa, lum, mass=None, theta_open=0.75, tau_ref=0.1, bucket_size=8,
+         sinks=None):
+    """Differentiable flux at the sinks with respect to rho, kappa and lum."""
+    return TrevrFlux.apply(rho, kappa, lum, pos, mass, theta_open, tau_ref, bucket_size, sinks)
