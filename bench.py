@@ -109,6 +109,37 @@ def adjoint_ratio(torch, P, reps=3):
             "fwd_plus_adj_over_fwd": (t_f + t_a) / t_f}
 
 
+def batched(torch, P, reps=5):
+    """64 independent boxes (2^12..2^17 particles each) as one forest: the
+    flux launch autotuned, captured in a HIP graph and replayed."""
+    from paper_1902_08083_amd import workloads as W
+    boxes = W.c4()
+    t0 = time.perf_counter()
+    plan = P.BatchedPlan(boxes)
+    t_setup = time.perf_counter() - t0
+    n = int(plan.offsets[-1])
+    plan.capture()
+    st = torch.cuda.current_stream()
+    plan.replay()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        plan.replay()
+        b.record(st)
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    ms_graph = float(np.median(ms))
+    return {"workload": "c4_batched64_f32", "boxes": len(boxes), "n_particles": n,
+            "graph_replay_ms": ms_graph, "sink_fluxes_per_s": n / (ms_graph * 1e-3),
+            "autotuned_launch": list(plan.tuning["launch"]),
+            "autotune_best_ms": plan.tuning["ms"],
+            "autotune_worst_ms": plan.tuning["table"][-1][0],
+            "build_plus_tune_s": t_setup}
+
+
 def cpu_baseline(w, target_s=10.0):
     """The oracle (binary64, OpenMP over sinks) on this host: full tree build
     plus the flux at a seeded sample of sinks, scaled to sink fluxes/s."""
@@ -159,7 +190,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--n", type=int, default=1 << 21, help="particles (default: the headline 2^21)")
+    ap.add_argument("--profile-once", action="store_true",
+                    help="one tree build and one flux launch of the headline workload, then a "
+                         "copy of 1 GiB (counter calibration); prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the per-sink walk shards over sinks with a "
@@ -173,6 +208,18 @@ def main():
 
     log("generating workload")
     w = W.c3(n=args.n)
+    if args.profile_once:
+        pos, rho, kappa, lum, mass = to_dev(w, torch)
+        tree = P.build_tree(pos, rho, kappa, lum, mass, w["box_lo"], w["box_hi"],
+                            w["bucket_size"])
+        tree.flux(w["theta"], w["tau_ref"])
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("profile-once done: launch %s" % tree.get_launch())
+        return
     n = w["pos"].shape[0]
     tree = P.Tree()
     log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
@@ -220,6 +267,9 @@ def main():
     if not args.no_adjoint:
         log("adjoint ratio on the 2^20 workload")
         out["adjoint"] = adjoint_ratio(torch, P)
+    if not args.no_batched:
+        log("batched boxes under a HIP graph")
+        out["batched"] = batched(torch, P)
     if not args.no_cpu:
         log("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(w)

@@ -13,10 +13,10 @@ NODE_F_FIELDS = (
 NODE_I_FIELDS = ("first", "count", "depth", "leaf", "parent", "right", "skip", "axis")
 
 from .trevr import (  # noqa: E402
-    COUNTER_FIELDS, Tree, TrevrError, TrevrFlux, TrevrNotBuilt, build_tree, compute_flux,
-    compute_flux_adjoint, flux, lib,
+    COUNTER_FIELDS, BatchedPlan, Tree, TrevrError, TrevrFlux, TrevrNotBuilt, autotune, build_tree,
+    compute_flux, compute_flux_adjoint, flux, lib,
 )
 
-__all__ = ["Tree", "TrevrError", "TrevrFlux", "TrevrNotBuilt", "build_tree", "compute_flux",
+__all__ = ["BatchedPlan", "autotune", "Tree", "TrevrError", "TrevrFlux", "TrevrNotBuilt", "build_tree", "compute_flux",
            "compute_flux_adjoint", "flux", "lib", "COUNTER_FIELDS", "NODE_F_FIELDS",
            "NODE_I_FIELDS"]

@@ -48,8 +48,9 @@ struct FluxArgs {
   const int32_t *__restrict__ box_root;
   const int32_t *__restrict__ sinks;
   int64_t n_sinks;
-  int64_t n;  // particles
-  int32_t n_chunks;
+  int64_t n;         // particles
+  int32_t n_chunks;  // work-queue grabs
+  int32_t group;     // 64-sink groups per grab
   double theta2, tau_ref;
   T *flux;
   int32_t *counters;
@@ -373,10 +374,18 @@ __global__ __launch_bounds__(256) void k_walk(FluxArgs<T> a) {
     acc_s[lane] = 0.0;
     acc_p[lane] = 0.0;
   }
+  int chunk = -1, sub = a.group;
   for (;;) {
-    const int chunk = wave_take(a.queue, a.n_chunks);
-    if (chunk < 0) break;
-    const int64_t q = (int64_t)chunk * 64 + lane;
+    if (sub == a.group) {
+      chunk = wave_take(a.queue, a.n_chunks);
+      if (chunk < 0) break;
+      sub = 0;
+    }
+    const int64_t q = ((int64_t)chunk * a.group + sub++) * 64 + lane;
+    if (__ballot(q < a.n_sinks) == 0) {
+      sub = a.group;
+      continue;
+    }
     const bool in_list = q < a.n_sinks;
     bool bad = false;  // a sink index outside [0, n)
     int k = 0;
@@ -676,7 +685,8 @@ static FluxArgs<T> make_args(const trevr_tree *t, double theta, double tau_ref,
   a.sinks = sinks;
   a.n_sinks = n_sinks;
   a.n = t->n;
-  a.n_chunks = (int32_t)((n_sinks + 63) / 64);
+  a.group = t->launch.chunk / 64;
+  a.n_chunks = (int32_t)((n_sinks + 64 * a.group - 1) / (64 * a.group));
   a.theta2 = theta * theta;
   a.tau_ref = tau_ref;
   a.queue = t->queue.as<int32_t>();

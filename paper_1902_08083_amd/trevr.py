@@ -288,3 +288,111 @@ def flux(pos, rho, kappa, lum, mass=None, theta_open=0.75, tau_ref=0.1, bucket_s
          sinks=None):
     """Differentiable flux at the sinks with respect to rho, kappa and lum."""
     return TrevrFlux.apply(rho, kappa, lum, pos, mass, theta_open, tau_ref, bucket_size, sinks)
+
+
+# ---------------------------------------------------------------- batching ---
+
+def _concat_boxes(boxes, device):
+    """boxes: list of dicts with pos (n,3), rho, kappa, lum, mass (optional),
+    box_lo, box_hi.  Returns device tensors and host box tables."""
+    import numpy as np
+    pos = np.concatenate([np.asarray(b["pos"]) for b in boxes])
+    cat = lambda k: np.concatenate([np.asarray(b[k]) for b in boxes])  # noqa: E731
+    off = np.cumsum([0] + [int(np.asarray(b["pos"]).shape[0]) for b in boxes]).astype(np.int64)
+    lo = np.array([b.get("box_lo", (0.0, 0.0, 0.0)) for b in boxes], np.float64)
+    hi = np.array([b.get("box_hi", (1.0, 1.0, 1.0)) for b in boxes], np.float64)
+    has_mass = all(b.get("mass") is not None for b in boxes)
+    t = lambda a: torch.as_tensor(a, device=device)  # noqa: E731
+    return (t(pos), t(cat("rho")), t(cat("kappa")), t(cat("lum")),
+            t(cat("mass")) if has_mass else None, lo, hi, off)
+
+
+_TUNE_CACHE = {}
+
+DEFAULT_CANDIDATES = tuple((bpc, wpb, chunk)
+                           for wpb in (4, 2, 1)
+                           for bpc in (1, 2, 3, 4, 6, 8)
+                           for chunk in (64, 128, 256)
+                           if 2 <= bpc * wpb <= 16)
+
+
+def autotune(tree, theta_open, tau_ref, sinks=None, candidates=DEFAULT_CANDIDATES, reps=3,
+             key=None):
+    """Time the flux launch under each (workgroups per CU, waves per
+    workgroup, sinks per queue grab) candidate and keep the fastest on the
+    tree.  Results are cached per `key` (default: tree shape and parameters)."""
+    import numpy as np
+    info = tree.info()
+    key = key or (info["n"], info["m"], info["n_boxes"], info["prec"], float(theta_open),
+                  float(tau_ref), None if sinks is None else int(len(sinks)))
+    if key in _TUNE_CACHE:
+        best = _TUNE_CACHE[key]
+        tree.set_launch(*best["launch"])
+        return best
+    s, ns = tree._sinks(sinks)
+    out = torch.empty(ns, dtype=tree.dtype, device=tree.device)
+    st = torch.cuda.current_stream()
+    table = []
+    for cand in candidates:
+        tree.set_launch(*cand)
+        tree.flux(theta_open, tau_ref, s, out=out)  # warm-up
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            tree.flux(theta_open, tau_ref, s, out=out)
+            e1.record(st)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        table.append((float(np.median(ms)), cand))
+    table.sort()
+    best = {"launch": table[0][1], "ms": table[0][0], "table": table}
+    tree.set_launch(*best["launch"])
+    _TUNE_CACHE[key] = best
+    return best
+
+
+class BatchedPlan:
+    """Many independent boxes of uneven size evaluated as one forest: one
+    tree build, then one persistent flux launch (queue reset + walk kernel)
+    captured in a HIP graph and replayed.  The launch shape is autotuned
+    before capture."""
+
+    def __init__(self, boxes, theta_open=0.75, tau_ref=0.1, bucket_size=8, device="cuda",
+                 tune=True, candidates=DEFAULT_CANDIDATES):
+        pos, rho, kappa, lum, mass, lo, hi, off = _concat_boxes(boxes, device)
+        self.offsets = off
+        self.theta_open = float(theta_open)
+        self.tau_ref = float(tau_ref)
+        self.tree = Tree().build(pos, rho, kappa, lum, mass, lo, hi, bucket_size, off, device)
+        self.flux = torch.empty(pos.shape[0], dtype=pos.dtype, device=pos.device)
+        self.tuning = (autotune(self.tree, self.theta_open, self.tau_ref, candidates=candidates)
+                       if tune else None)
+        self.graph = None
+
+    def eager(self):
+        return self.tree.flux(self.theta_open, self.tau_ref, out=self.flux)
+
+    def capture(self):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.eager()
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.eager()
+        self.graph = g
+        return self
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+        return self.flux
+
+    def per_box(self, F=None):
+        F = self.flux if F is None else F
+        return [F[int(self.offsets[b]):int(self.offsets[b + 1])]
+                for b in range(len(self.offsets) - 1)]

@@ -1,0 +1,60 @@
+"""Batched boxes: 64 independent boxes of uneven size (2^12..2^17 particles,
+uniform or log-normal media, 1..512 sources, box optical depth 0.1..20) as
+one forest, one persistent flux launch captured in a HIP graph and replayed;
+the launch shape picked by the autotuner."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import paper_1902_08083_amd as P  # noqa: E402
+from oracle.oracle import OracleTree  # noqa: E402
+from paper_1902_08083_amd import workloads as W  # noqa: E402
+
+NTHREADS = min(16, os.cpu_count() or 1)
+
+
+def test_batched_graph_replays_match_eager_and_oracle():
+    print("batched c4: build + autotune", flush=True)
+    boxes = W.c4()
+    plan = P.BatchedPlan(boxes, candidates=[(3, 4, 64), (2, 4, 128), (4, 2, 64)])
+    eager = plan.eager().clone()
+    plan.capture()
+    for rep in range(3):
+        F = plan.replay().clone()
+        torch.cuda.synchronize()
+        assert torch.equal(F, eager), "replay %d differs from the eager launch" % rep
+        # unrelated eager work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+    Fb = plan.per_box(eager)
+    sizes = [b["pos"].shape[0] for b in boxes]
+    check = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 31, 50})
+    for b in check:
+        bx = boxes[b]
+        f64 = lambda a: np.asarray(a, np.float64)  # noqa: E731
+        o = OracleTree(f64(bx["pos"]), f64(bx["rho"]), f64(bx["kappa"]), f64(bx["lum"]),
+                       f64(bx["mass"]), bucket_size=8, mirror32=True)
+        Fo, _ = o.flux(0.75, 0.1, nthreads=NTHREADS)
+        g = Fb[b].cpu().numpy().astype(np.float64)
+        rel = np.abs(g - Fo) / np.where(Fo > 0, Fo, 1.0)
+        print("box %d (%d particles): max rel %.2e" % (b, sizes[b], rel.max()), flush=True)
+        assert rel.max() <= 1e-5
+
+
+def test_autotune_keeps_results_identical():
+    w = W._pack("tune", *W.lognormal_box(1 << 14, 0, 10.0, 3, all_sources=True), prec="f32")
+    t = P.build_tree(*[torch.as_tensor(w[k], device="cuda") for k in
+                       ("pos", "rho", "kappa", "lum", "mass")])
+    ref = t.flux(0.75, 0.1).clone()
+    best = P.autotune(t, 0.75, 0.1, candidates=[(1, 1, 64), (2, 4, 256), (8, 2, 128)], reps=1)
+    assert tuple(best["launch"]) in [(1, 1, 64), (2, 4, 256), (8, 2, 128)]
+    for cand in [(1, 1, 64), (2, 4, 256), (8, 2, 128), (3, 4, 4096)]:
+        t.set_launch(*cand)
+        assert torch.equal(t.flux(0.75, 0.1), ref), cand
