@@ -361,7 +361,7 @@ __host__ __device__ constexpr size_t lds_per_wave() {
 }
 
 template <typename T, bool ADJ>
-__global__ __launch_bounds__(256) void k_walk(FluxArgs<T> a) {
+__device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -610,6 +610,35 @@ __global__ __launch_bounds__(256) void k_walk(FluxArgs<T> a) {
   }
 }
 
+// The walk kernel at several register budgets: with fewer VGPRs more waves
+// share a SIMD (better latency hiding) at the price of spills; the launch
+// shape picks one (waves per SIMD = workgroups per CU x waves per workgroup
+// / 4, at least 3).
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(256) void k_walk(FluxArgs<T> a) {
+  walk_body<T, ADJ>(a);
+}
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
+    FluxArgs<T> a) {
+  walk_body<T, ADJ>(a);
+}
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
+    FluxArgs<T> a) {
+  walk_body<T, ADJ>(a);
+}
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_walk6(
+    FluxArgs<T> a) {
+  walk_body<T, ADJ>(a);
+}
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_walk8(
+    FluxArgs<T> a) {
+  walk_body<T, ADJ>(a);
+}
+
 __global__ void k_zero_i32(int32_t *p, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -703,7 +732,17 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   const int64_t need = (a.n_chunks + waves - 1) / waves;
   if (blocks > need) blocks = need;
   const size_t shmem = (size_t)waves * lds_per_wave<ADJ>();
-  k_walk<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  const int per_simd = (t->launch.blocks_per_cu * waves + 3) / 4;
+  if (per_simd >= 8)
+    k_walk8<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  else if (per_simd >= 6)
+    k_walk6<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  else if (per_simd == 5)
+    k_walk5<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  else if (per_simd == 4)
+    k_walk4<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  else
+    k_walk<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
   TREVR_HIP(hipGetLastError());
   return TREVR_OK;
 }

@@ -55,6 +55,8 @@ def test_autotune_keeps_results_identical():
     ref = t.flux(0.75, 0.1).clone()
     best = P.autotune(t, 0.75, 0.1, candidates=[(1, 1, 64), (2, 4, 256), (8, 2, 128)], reps=1)
     assert tuple(best["launch"]) in [(1, 1, 64), (2, 4, 256), (8, 2, 128)]
-    for cand in [(1, 1, 64), (2, 4, 256), (8, 2, 128), (3, 4, 4096)]:
+    # every register-budget variant of the walk kernel (3..8 waves per SIMD)
+    for cand in [(1, 1, 64), (2, 4, 256), (8, 2, 128), (3, 4, 4096), (5, 4, 64), (6, 4, 64),
+                 (8, 4, 64), (16, 2, 128)]:
         t.set_launch(*cand)
         assert torch.equal(t.flux(0.75, 0.1), ref), cand
