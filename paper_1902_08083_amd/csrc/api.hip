@@ -63,13 +63,13 @@ static int check_walk(const trevr_tree *t, double theta, double tau_ref, const i
 
 trevr_tree::~trevr_tree() {
   trevr::DevBuf *all[] = {&walk, &trace, &key, &psrc, &perm, &inv, &leaf, &pbox, &pmass, &prho,
-                          &box_root, &box_off, &box_lo, &box_hi, &axis_tab, &n_first, &n_count,
+                          &box_root, &box_off, &box_lo, &box_hi, &axis_tab, &axmask, &n_first, &n_count,
                           &n_depth, &n_parent, &n_right, &n_skip, &n_box, &n_axis, &n_lo,
                           &n_hi, &n_split, &n_A, &n_B, &n_SL, &n_SLx, &n_alpha, &n_amin,
                           &n_amax, &n_alpha_min, &n_alpha_max, &n_dalpha, &n_xl, &n_lc,
                           &n_lfar, &keys_in, &keys_out, &vals_in, &vals_out, &sort_tmp, &bfs,
                           &flags, &scan, &err, &box_key, &skeys, &small, &queue, &adj_node,
-                          &adj_part};
+                          &adj_part, &adj_heap};
   for (auto *b : all) b->release();
 }
 

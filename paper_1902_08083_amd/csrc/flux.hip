@@ -46,6 +46,7 @@ struct FluxArgs {
   const int32_t *__restrict__ leaf;
   const int32_t *__restrict__ pbox;
   const int32_t *__restrict__ box_root;
+  const uint64_t *__restrict__ axmask;  // per box: 3 masks of path-bit positions
   const int32_t *__restrict__ sinks;
   int64_t n_sinks;
   int64_t n;         // particles
@@ -233,6 +234,7 @@ struct SinkCtx {
   uint64_t keyS;
   int depthS;
   double alphaS;
+  uint64_t axm[3];     // the box's split axis masks over path-bit positions
   int anc[kDmax + 1];  // ancestors of S by depth
 };
 
@@ -280,28 +282,47 @@ __device__ void trace_pieces(const FluxArgs<T> &a, const int32_t *s_path, int C,
   } else {
     tA = sr ? 1.0 : 0.0;  // ray in the plane: it belongs to the upper side
   }
-  // sink side, [0, tP]
+  // Chain levels where the ray crosses into (sink side) or arrives from
+  // (source side) the other half.  The split axis depends on the depth only,
+  // so per axis a mask of path-bit positions (bit 62 - depth) selects them:
+  // moving up axis a the other half of a lower-half sink chain is upper, etc.
+  uint64_t mS = 0, mC = 0;
+  for (int q = 0; q < 3; ++q) {
+    const uint64_t axm = sk.axm[q];
+    if (c.d[q] > 0.0) {
+      mS |= axm & ~sk.keyS;
+      mC |= axm & keyC;
+    } else if (c.d[q] < 0.0) {
+      mS |= axm & sk.keyS;
+      mC |= axm & ~keyC;
+    }
+  }
+  // depths ad+1 .. depth-1 are path-bit positions 63-depth .. 61-ad
+  const uint64_t below_A = (1ull << (62 - ad)) - 1;
+  mS &= below_A & ~((1ull << (63 - sk.depthS)) - 1);
+  mC &= below_A & ~((1ull << (63 - depthC)) - 1);
+  // sink side, [0, tP], shallowest level first
   double tP = tA;
   int gP = gA;
-  for (int dd = ad + 1; dd < sk.depthS; ++dd) {
+  while (mS) {
+    const int pos = 63 - __clzll((long long)mS);
+    mS &= ~(1ull << pos);
+    const int dd = 62 - pos;
     const int P = sk.anc[dd];
     const TraceRecT<T> rP = a.TR[P];
     const int b = (int)((sk.keyS >> (62 - dd)) & 1);
     const int ax = rax_axis(rP.right_ax);
-    const double dax = sel3(c.d, ax);
-    if (dax != 0.0 && (b ? dax < 0.0 : dax > 0.0)) {
-      double tc = ((double)rP.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
-      int gc = ax;
-      if (tc < 0.0) {
-        tc = 0.0;
-        gc = -1;
-      }
-      if (tc < tP) {
-        const int sib = b ? P + 1 : rax_right(rP.right_ax);
-        chain_piece<T>(a.TR, rP, P, dd, sib, tc, gc, tP, gP, c, emit);
-        tP = tc;
-        gP = gc;
-      }
+    double tc = ((double)rP.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
+    int gc = ax;
+    if (tc < 0.0) {
+      tc = 0.0;
+      gc = -1;
+    }
+    if (tc < tP) {
+      const int sib = b ? P + 1 : rax_right(rP.right_ax);
+      chain_piece<T>(a.TR, rP, P, dd, sib, tc, gc, tP, gP, c, emit);
+      tP = tc;
+      gP = gc;
     }
   }
   {
@@ -313,25 +334,25 @@ __device__ void trace_pieces(const FluxArgs<T> &a, const int32_t *s_path, int C,
   // source side, [tQ, 1]
   double tQ = tA;
   int gQ = gA;
-  for (int dd = ad + 1; dd < depthC; ++dd) {
+  while (mC) {
+    const int pos = 63 - __clzll((long long)mC);
+    mC &= ~(1ull << pos);
+    const int dd = 62 - pos;
     const int Q = s_path[dd];
     const TraceRecT<T> rQ = a.TR[Q];
     const int b = (int)((keyC >> (62 - dd)) & 1);
     const int ax = rax_axis(rQ.right_ax);
-    const double dax = sel3(c.d, ax);
-    if (dax != 0.0 && (b ? dax > 0.0 : dax < 0.0)) {
-      double tc = ((double)rQ.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
-      int gc = ax;
-      if (tc > 1.0) {
-        tc = 1.0;
-        gc = -1;
-      }
-      if (tc > tQ) {
-        const int sib = b ? Q + 1 : rax_right(rQ.right_ax);
-        chain_piece<T>(a.TR, rQ, Q, kSlotSrc + dd, sib, tQ, gQ, tc, gc, c, emit);
-        tQ = tc;
-        gQ = gc;
-      }
+    double tc = ((double)rQ.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
+    int gc = ax;
+    if (tc > 1.0) {
+      tc = 1.0;
+      gc = -1;
+    }
+    if (tc > tQ) {
+      const int sib = b ? Q + 1 : rax_right(rQ.right_ax);
+      chain_piece<T>(a.TR, rQ, Q, kSlotSrc + dd, sib, tQ, gQ, tc, gc, c, emit);
+      tQ = tc;
+      gQ = gc;
     }
   }
   refine<T>(a.TR, C, kSlotSrc + depthC, tQ, gQ, 1.0, -1, c, emit);
@@ -412,7 +433,11 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     sk.keyS = a.key[sk.S];
     sk.depthS = a.ndepth[sk.S];
     sk.alphaS = (double)a.TR[sk.S].alpha;
-    const int my_root = a.box_root[a.pbox[k]];
+    const int my_box = a.pbox[k];
+    const int my_root = a.box_root[my_box];
+    sk.axm[0] = a.axmask[3 * my_box + 0];
+    sk.axm[1] = a.axmask[3 * my_box + 1];
+    sk.axm[2] = a.axmask[3 * my_box + 2];
     {  // the ancestors of the sink's bucket, by depth
       int node = my_root;
       for (int dd = 0; dd <= sk.depthS; ++dd) {
@@ -711,6 +736,7 @@ static FluxArgs<T> make_args(const trevr_tree *t, double theta, double tau_ref,
   a.leaf = t->leaf.as<int32_t>();
   a.pbox = t->pbox.as<int32_t>();
   a.box_root = t->box_root.as<int32_t>();
+  a.axmask = t->axmask.as<uint64_t>();
   a.sinks = sinks;
   a.n_sinks = n_sinks;
   a.n = t->n;

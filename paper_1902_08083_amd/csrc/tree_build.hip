@@ -430,6 +430,12 @@ static int build_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
       w[a] *= 0.5;
     }
   }
+  std::vector<uint64_t> axm(3 * nbox, 0);
+  for (int b = 0; b < nbox; ++b)
+    for (int d = 0; d < kDmax; ++d) axm[3 * b + axes[64 * b + d]] |= 1ull << (62 - d);
+  TREVR_HIP(t->axmask.ensure(sizeof(uint64_t) * 3 * nbox));
+  TREVR_HIP(hipMemcpyAsync(t->axmask.p, axm.data(), sizeof(uint64_t) * 3 * nbox,
+                           hipMemcpyHostToDevice, s));
   TREVR_HIP(t->box_off.ensure(sizeof(int64_t) * (nbox + 1)));
   TREVR_HIP(t->box_lo.ensure(sizeof(double) * 3 * nbox));
   TREVR_HIP(t->box_hi.ensure(sizeof(double) * 3 * nbox));

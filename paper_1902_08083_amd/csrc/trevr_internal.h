@@ -135,6 +135,7 @@ struct trevr_tree {
   trevr::DevBuf perm, inv, leaf, pbox, pmass, prho;
   // per box
   trevr::DevBuf box_root, box_off, box_lo, box_hi, axis_tab;
+  trevr::DevBuf axmask;  // per box: 3 u64, bit (62 - depth) set where that depth splits axis a
   std::vector<int32_t> h_box_root;
   std::vector<int64_t> h_box_off;
   // binary64 cell data (build, export, adjoint)
@@ -147,7 +148,7 @@ struct trevr_tree {
   std::vector<int64_t> level_off, level_cnt;
   // work queue (one counter per XCD) and adjoint scratch
   trevr::DevBuf queue;
-  trevr::DevBuf adj_node, adj_part;
+  trevr::DevBuf adj_node, adj_part, adj_heap;
 
   ~trevr_tree();
 };
