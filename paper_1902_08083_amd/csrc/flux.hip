@@ -33,6 +33,7 @@
 namespace trevr {
 
 constexpr int kXcd = 8;
+constexpr int kChunkP = 32;  // bucket particles whose rays are dealt out together
 
 template <typename T>
 struct FluxArgs {
@@ -65,9 +66,38 @@ struct FluxArgs {
   int64_t m;
 };
 
-__device__ __forceinline__ double sel3(const double v[3], int a) {
-  return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]);
+// v[a] for a in {0, 1, 2} as two selects: the three values are passed
+// separately so that the ray's per-axis arrays stay in registers.
+__device__ __forceinline__ double pick3(int a, double v0, double v1, double v2) {
+  const double v01 = a == 0 ? v0 : v1;
+  return a == 2 ? v2 : v01;
 }
+#define sel3(v, a) pick3((a), (v)[0], (v)[1], (v)[2])
+
+// A trace record in one vector load (16 B in binary32, 32 B in binary64).
+__device__ __forceinline__ TraceRecT<float> load_tr(const TraceRecT<float> *TR, int i) {
+  const uint4 u = *reinterpret_cast<const uint4 *>(TR + i);
+  TraceRecT<float> r;
+  r.split = __uint_as_float(u.x);
+  r.alpha = __uint_as_float(u.y);
+  r.dalpha = __uint_as_float(u.z);
+  r.right_ax = (int32_t)u.w;
+  return r;
+}
+__device__ __forceinline__ TraceRecT<double> load_tr(const TraceRecT<double> *TR, int i) {
+  const uint4 u = reinterpret_cast<const uint4 *>(TR + i)[0];
+  const uint4 w = reinterpret_cast<const uint4 *>(TR + i)[1];
+  TraceRecT<double> r;
+  r.split = __hiloint2double((int)u.y, (int)u.x);
+  r.alpha = __hiloint2double((int)u.w, (int)u.z);
+  r.dalpha = __hiloint2double((int)w.y, (int)w.x);
+  r.right_ax = (int32_t)w.z;
+  r.pad = 0;
+  return r;
+}
+
+typedef __attribute__((address_space(3))) int32_t lds_i32;
+typedef __attribute__((address_space(3))) double lds_d;
 
 // Atomic adds with an explicit address space: LDS accumulators through
 // ds_add_f64, device memory through global_atomic_add_f64 (never FLAT).
@@ -90,6 +120,11 @@ struct RayCtx {
   double r, r2;
   double tau_ref;
   int n_seg, n_trace;
+  // the lane's refinement stack in LDS (stride 64): kr entries, deeper ones
+  // spill to private memory
+  int32_t *stn;  // pending cell | (tag + 1) << 30
+  double *stb;   // its exit parameter
+  int kr;
 };
 
 struct StackEntry {
@@ -116,7 +151,7 @@ struct Scatter {
   double g;        // weight * flux contribution of the ray
   double dtdy[3];  // d tau / d y
   double r;
-  const double *inv;
+  double inv[3];
   double *abar;
   double *acc_s, *acc_p;  // LDS, per wave
   int d_common;           // sink-chain depths <= this are shared by the wave
@@ -147,13 +182,13 @@ struct Scatter {
 template <typename T, typename Emit>
 __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, double ta,
                        int ga, double tb, int gb, RayCtx &c, Emit &emit) {
-  StackEntry stk[kRefineStack];
+  StackEntry ovf[kRefineStack];  // entries beyond the LDS part (rarely reached)
   int sp = 0;
   int cur = X;
   double cta = ta, ctb = tb;
   int cga = ga, cgb = gb;
   for (;;) {
-    const TraceRecT<T> rec = TR[cur];
+    const TraceRecT<T> rec = load_tr(TR, cur);
     const double l = c.r * (ctb - cta);
     c.n_trace++;
     const int right = rax_right(rec.right_ax);
@@ -162,11 +197,18 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
       emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb);
       if (sp == 0) return;
       --sp;
-      cur = stk[sp].node;
       cta = ctb;
       cga = cgb;
-      ctb = stk[sp].tb;
-      cgb = stk[sp].tag;
+      if (sp < c.kr) {
+        const uint32_t e = (uint32_t)((lds_i32 *)c.stn)[sp * kWave];
+        cur = (int)(e & 0x3fffffffu);
+        cgb = (int)(e >> 30) - 1;
+        ctb = ((lds_d *)c.stb)[sp * kWave];
+      } else {
+        cur = ovf[sp - c.kr].node;
+        ctb = ovf[sp - c.kr].tb;
+        cgb = ovf[sp - c.kr].tag;
+      }
       continue;
     }
     const int ax = rax_axis(rec.right_ax);
@@ -194,9 +236,14 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
     const bool has_near = t1 > cta, has_far = ctb > t0;
     if (has_near) {
       if (has_far) {
-        stk[sp].node = farc;
-        stk[sp].tag = cgb;
-        stk[sp].tb = ctb;
+        if (sp < c.kr) {
+          ((lds_i32 *)c.stn)[sp * kWave] = (int32_t)((uint32_t)farc | ((uint32_t)(cgb + 1) << 30));
+          ((lds_d *)c.stb)[sp * kWave] = ctb;
+        } else {
+          ovf[sp - c.kr].node = farc;
+          ovf[sp - c.kr].tag = cgb;
+          ovf[sp - c.kr].tb = ctb;
+        }
         ++sp;
       }
       cur = nearc;
@@ -229,14 +276,34 @@ __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
   emit(P, slot, (double)rP.alpha, l, ta, ga, tb, gb);
 }
 
+// The sink's bucket and where its ancestors are kept: depths <= dpre are
+// shared by the wave (LDS `pre`), the deepest ks depths above the bucket sit
+// in the lane's LDS window (stride 64; slot = depth - depthS + ks), and the
+// rare depths in between are found again by descending from the shared part.
 struct SinkCtx {
   int S;
   uint64_t keyS;
   int depthS;
   double alphaS;
-  uint64_t axm[3];     // the box's split axis masks over path-bit positions
-  int anc[kDmax + 1];  // ancestors of S by depth
+  uint64_t axm[3];  // the box's split axis masks over path-bit positions
+  int root;
+  int dpre;
+  int ks;
+  const int32_t *pre;
+  int32_t *win;
 };
+
+template <typename T>
+__device__ __forceinline__ int sink_anc(const TraceRecT<T> *__restrict__ TR, const SinkCtx &sk,
+                                        int dd) {
+  if (dd <= sk.dpre) return ((const lds_i32 *)sk.pre)[dd];
+  const int slot = dd - sk.depthS + sk.ks;
+  if (slot >= 0) return ((const lds_i32 *)sk.win)[slot * kWave];
+  int node = sk.dpre >= 0 ? ((const lds_i32 *)sk.pre)[sk.dpre] : sk.root;
+  for (int j = sk.dpre > 0 ? sk.dpre : 0; j < dd; ++j)
+    node = ((sk.keyS >> (62 - j)) & 1) ? rax_right(load_tr(TR, node).right_ax) : node + 1;
+  return node;
+}
 
 __device__ __forceinline__ void ray_setup(RayCtx &c, double y0, double y1, double y2) {
   c.d[0] = y0 - c.xi[0];
@@ -262,7 +329,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, const int32_t *s_path, int C,
   }
   const int ad = __clzll((long long)(sk.keyS ^ keyC)) - 1;  // depth of the meeting cell
   const int A = s_path[ad];
-  const TraceRecT<T> rA = a.TR[A];
+  const TraceRecT<T> rA = load_tr(a.TR, A);
   const int axA = rax_axis(rA.right_ax);
   const int sr = (int)((sk.keyS >> (62 - ad)) & 1);
   const double dA = sel3(c.d, axA);
@@ -308,8 +375,8 @@ __device__ void trace_pieces(const FluxArgs<T> &a, const int32_t *s_path, int C,
     const int pos = 63 - __clzll((long long)mS);
     mS &= ~(1ull << pos);
     const int dd = 62 - pos;
-    const int P = sk.anc[dd];
-    const TraceRecT<T> rP = a.TR[P];
+    const int P = sink_anc<T>(a.TR, sk, dd);
+    const TraceRecT<T> rP = load_tr(a.TR, P);
     const int b = (int)((sk.keyS >> (62 - dd)) & 1);
     const int ax = rax_axis(rP.right_ax);
     double tc = ((double)rP.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
@@ -339,7 +406,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, const int32_t *s_path, int C,
     mC &= ~(1ull << pos);
     const int dd = 62 - pos;
     const int Q = s_path[dd];
-    const TraceRecT<T> rQ = a.TR[Q];
+    const TraceRecT<T> rQ = load_tr(a.TR, Q);
     const int b = (int)((keyC >> (62 - dd)) & 1);
     const int ax = rax_axis(rQ.right_ax);
     double tc = ((double)rQ.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
@@ -375,26 +442,86 @@ __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
   return -1;
 }
 
-// Per-wave LDS: open masks, walk path, and (adjoint) two accumulator rows.
+// LDS per wave, binary64 items first: open masks (64 x u64), the adjoint's
+// two accumulator rows (64 x f64 each), the refinement stacks (kr x 64 lanes x
+// (f64 + i32)), the ray results of a round (64 x f64, 2 x 64 x i32), the
+// particle-use masks of a bucket chunk and their prefix counts (32 each), the
+// sink-ancestor windows (ks x 64 lanes x i32), the walk path, the shared
+// sink-chain prefix and the ray list of a round (64 x i32 each).
 template <bool ADJ>
-__host__ __device__ constexpr size_t lds_per_wave() {
-  return 64 * 8 + 64 * 4 + (ADJ ? 2 * 64 * 8 : 0);
+__host__ __device__ constexpr size_t lds_per_wave(int ks, int kr) {
+  return (size_t)64 * 8 + (ADJ ? 2 * 64 * 8 : 0) + (size_t)kr * 64 * 12 + 64 * 8 + 2 * 64 * 4 +
+         kChunkP * (8 + 4) + (size_t)ks * 64 * 4 + 3 * 64 * 4;
 }
 
-template <typename T, bool ADJ>
+// Window and stack depth per occupancy variant (waves per SIMD), chosen so
+// that that many waves fit the CU's 160 KiB of LDS.
+__host__ __device__ constexpr int occ_ks(int wps, bool adj) {
+  return wps <= 3 ? (adj ? 14 : 18)
+                  : wps == 4 ? (adj ? 10 : 11)
+                             : wps == 5 ? (adj ? 8 : 9) : wps <= 7 ? (adj ? 6 : 7) : (adj ? 2 : 3);
+}
+__host__ __device__ constexpr int occ_kr(int wps, bool adj) {
+  return wps <= 3 ? 8
+                  : wps == 4 ? (adj ? 5 : 6)
+                             : wps == 5 ? (adj ? 3 : 4) : wps <= 7 ? (adj ? 2 : 3) : (adj ? 1 : 2);
+}
+template <bool ADJ>
+__host__ __device__ constexpr size_t occ_lds(int wps) {
+  return lds_per_wave<ADJ>(occ_ks(wps, ADJ), occ_kr(wps, ADJ));
+}
+constexpr size_t kLdsPerCu = 160 * 1024;
+static_assert(occ_lds<false>(3) * 12 <= kLdsPerCu && occ_lds<true>(3) * 12 <= kLdsPerCu, "");
+static_assert(occ_lds<false>(4) * 16 <= kLdsPerCu && occ_lds<true>(4) * 16 <= kLdsPerCu, "");
+static_assert(occ_lds<false>(5) * 20 <= kLdsPerCu && occ_lds<true>(5) * 20 <= kLdsPerCu, "");
+static_assert(occ_lds<false>(6) * 24 <= kLdsPerCu && occ_lds<true>(6) * 24 <= kLdsPerCu, "");
+static_assert(occ_lds<false>(8) * 32 <= kLdsPerCu && occ_lds<true>(8) * 32 <= kLdsPerCu, "");
+
+// Orders a wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, bool ADJ, int KS, int KR>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  unsigned char *base = smem + wv * lds_per_wave<ADJ>();
+  const uint64_t below = (1ull << lane) - 1;  // the lanes below this one
+  unsigned char *base = smem + wv * lds_per_wave<ADJ>(KS, KR);
   uint64_t *s_open = reinterpret_cast<uint64_t *>(base);
-  int32_t *s_path = reinterpret_cast<int32_t *>(base + 64 * 8);
-  double *acc_s = reinterpret_cast<double *>(base + 64 * 12);
+  base += 64 * 8;
+  double *acc_s = reinterpret_cast<double *>(base);
   double *acc_p = acc_s + 64;
+  if (ADJ) base += 2 * 64 * 8;
+  double *s_stb = reinterpret_cast<double *>(base);
+  base += KR * 64 * 8;
+  double *s_f = reinterpret_cast<double *>(base);
+  base += 64 * 8;
+  uint64_t *s_usem = reinterpret_cast<uint64_t *>(base);
+  base += kChunkP * 8;
+  int32_t *s_stn = reinterpret_cast<int32_t *>(base);
+  base += KR * 64 * 4;
+  int32_t *s_seg = reinterpret_cast<int32_t *>(base);
+  int32_t *s_trc = s_seg + 64;
+  int32_t *s_upre = s_trc + 64;
+  base += 2 * 64 * 4 + kChunkP * 4;
+  int32_t *s_anc = reinterpret_cast<int32_t *>(base);
+  base += KS * 64 * 4;
+  int32_t *s_path = reinterpret_cast<int32_t *>(base);
+  int32_t *s_pre = s_path + 64;
+  int32_t *s_pair = s_pre + 64;
   if (ADJ) {
     acc_s[lane] = 0.0;
     acc_p[lane] = 0.0;
   }
+  RayCtx c;
+  c.tau_ref = a.tau_ref;
+  c.stn = s_stn + lane;
+  c.stb = s_stb + lane;
+  c.kr = KR;
   int chunk = -1, sub = a.group;
   for (;;) {
     if (sub == a.group) {
@@ -420,15 +547,10 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       }
     }
     const bool valid = in_list && !bad;
+    // this lane's sink: it owns the opening tests and the sums of its rays
     const P4<T> me = a.ps[k];
+    const double xo[3] = {(double)me.x, (double)me.y, (double)me.z};
     SinkCtx sk;
-    RayCtx c;
-    c.xi[0] = (double)me.x;
-    c.xi[1] = (double)me.y;
-    c.xi[2] = (double)me.z;
-    c.tau_ref = a.tau_ref;
-    c.n_seg = 0;
-    c.n_trace = 0;
     sk.S = a.leaf[k];
     sk.keyS = a.key[sk.S];
     sk.depthS = a.ndepth[sk.S];
@@ -438,35 +560,49 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     sk.axm[0] = a.axmask[3 * my_box + 0];
     sk.axm[1] = a.axmask[3 * my_box + 1];
     sk.axm[2] = a.axmask[3 * my_box + 2];
-    {  // the ancestors of the sink's bucket, by depth
+    const uint64_t vmask = __ballot(valid);
+    const int lead0 = vmask ? __ffsll((unsigned long long)vmask) - 1 : 0;
+    // Sink-chain depths whose cell is the same for every valid lane: same box
+    // and path bits above that depth, and not below any lane's bucket.
+    int d_common;
+    {
+      const uint64_t keyL = __shfl(sk.keyS, lead0);
+      const int rootL = __shfl(my_root, lead0);
+      int dc = kDmax;
+      if (valid) {
+        const uint64_t x = sk.keyS ^ keyL;
+        dc = x ? __clzll((long long)x) - 1 : kDmax;
+        if (sk.depthS < dc) dc = sk.depthS;
+        if (my_root != rootL) dc = -1;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const int other = __shfl_xor(dc, o);
+        dc = other < dc ? other : dc;
+      }
+      d_common = vmask ? dc : -1;
+    }
+    sk.root = my_root;
+    sk.dpre = d_common;
+    sk.ks = KS;
+    sk.pre = s_pre;
+    sk.win = s_anc + lane;
+    {  // the ancestors of the sink's bucket, by depth, into the LDS tables
       int node = my_root;
       for (int dd = 0; dd <= sk.depthS; ++dd) {
-        sk.anc[dd] = node;
-        if (dd < sk.depthS) {
-          const int right = rax_right(a.TR[node].right_ax);
-          node = ((sk.keyS >> (62 - dd)) & 1) ? right : node + 1;
-        }
+        if (dd <= d_common && lane == lead0) s_pre[dd] = node;
+        if (dd == sk.depthS) break;
+        const int slot = dd - sk.depthS + KS;
+        if (slot >= 0) sk.win[slot * kWave] = node;
+        const int right = rax_right(a.TR[node].right_ax);
+        node = ((sk.keyS >> (62 - dd)) & 1) ? right : node + 1;
       }
     }
-    const uint64_t vmask = __ballot(valid);
-    const int lead0 = __ffsll((unsigned long long)vmask) - 1;
-    // sink-chain depths whose cell is the same for every valid lane
-    int d_common = -1;
+    wave_sync();
     double wgt = 0.0;
-    if (ADJ) {
-      // grad_flux is indexed like flux: by list position, or by particle
-      if (valid) wgt = (double)a.grad_flux[a.sinks ? q : (int64_t)a.perm[k]];
-      const int dmin = __shfl(valid ? sk.depthS : 1000, lead0);
-      for (int dd = 0; dd <= kDmax; ++dd) {
-        const int mine_node = (dd <= sk.depthS) ? sk.anc[dd] : -1;
-        const int ref = __shfl(mine_node, lead0);
-        const bool differs = valid && (mine_node != ref || ref < 0);
-        if (__ballot(differs) != 0 || dd > dmin) break;
-        d_common = dd;
-      }
-    }
+    // grad_flux is indexed like flux: by list position, or by particle
+    if (ADJ && valid) wgt = (double)a.grad_flux[a.sinks ? q : (int64_t)a.perm[k]];
     double F = 0.0;
-    int n_open = 0, n_rays = 0, n_psrc = 0;
+    int n_open = 0, n_rays = 0, n_psrc = 0, n_seg = 0, n_trace = 0;
     uint64_t pending = vmask;
     while (pending) {
       const int lead = __ffsll((unsigned long long)pending) - 1;
@@ -495,7 +631,6 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         }
         depth_prev = depth;
         const bool mine = (active >> lane) & 1;
-        bool descend = false;
         uint64_t openm = 0;
         if (w.L != (T)0) {
           bool acc = false;
@@ -503,8 +638,8 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
             n_open++;
             double g[3];
             for (int q3 = 0; q3 < 3; ++q3) {
-              const double u = (double)w.lo[q3] - c.xi[q3];
-              const double v = c.xi[q3] - (double)w.hi[q3];
+              const double u = (double)w.lo[q3] - xo[q3];
+              const double v = xo[q3] - (double)w.hi[q3];
               const double gg = u > v ? u : v;
               g[q3] = gg > 0.0 ? gg : 0.0;
             }
@@ -513,86 +648,163 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
             acc = lf * lf < a.theta2 * r2;
           }
           const uint64_t accm = __ballot(acc);
-          const uint64_t keyC = a.key[n];
-          double cl = 0.0, cx0 = 0.0, cx1 = 0.0, cx2 = 0.0;
-          if (acc) {
-            n_rays++;
-            ray_setup(c, (double)w.xl[0], (double)w.xl[1], (double)w.xl[2]);
-            TauSum ts;
-            trace_pieces<T>(a, s_path, n, keyC, depth, sk, c, ts);
-            const double f = ((double)w.L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
-            if (!ADJ) {
-              F += f;
-            } else {
-              Scatter sc;
-              sc.g = wgt * f;
-              for (int q3 = 0; q3 < 3; ++q3) sc.dtdy[q3] = (ts.tau / c.r) * (c.d[q3] / c.r);
-              sc.r = c.r;
-              sc.inv = c.inv;
-              sc.abar = a.abar;
-              sc.acc_s = acc_s;
-              sc.acc_p = acc_p;
-              sc.d_common = d_common;
-              trace_pieces<T>(a, s_path, n, keyC, depth, sk, c, sc);
-              cl = sc.g / (double)w.L;
-              cx0 = sc.g * (-2.0 * c.d[0] / c.r2 - sc.dtdy[0]);
-              cx1 = sc.g * (-2.0 * c.d[1] / c.r2 - sc.dtdy[1]);
-              cx2 = sc.g * (-2.0 * c.d[2] / c.r2 - sc.dtdy[2]);
-            }
-          }
-          if (ADJ && accm) {  // d loss / d L_C and d loss / d x_L of this cell
-            const double s0 = wave_sum(cl), s1 = wave_sum(cx0), s2 = wave_sum(cx1),
-                         s3 = wave_sum(cx2);
-            if (lane == 0) {
-              gbl_add(&a.lbar[n], s0);
-              gbl_add(&a.xbar[n], s1);
-              gbl_add(&a.xbar[a.m + n], s2);
-              gbl_add(&a.xbar[2 * a.m + n], s3);
-            }
-          }
           openm = active & ~accm;
-          if (openm) {
-            if (rax_right(w.right_ax) == 0) {  // bucket: its particles one by one
-              const bool op = (openm >> lane) & 1;
-              for (int kk = w.first; kk < w.first + w.count; ++kk) {
-                const P4<T> pj = a.ps[kk];
-                const bool use = op && pj.L > (T)0 && kk != k &&
-                                 !(pj.x == me.x && pj.y == me.y && pj.z == me.z);
-                double dl = 0.0;
-                if (use) {
-                  n_rays++;
-                  n_psrc++;
-                  ray_setup(c, (double)pj.x, (double)pj.y, (double)pj.z);
-                  TauSum ts;
-                  trace_pieces<T>(a, s_path, n, keyC, depth, sk, c, ts);
-                  const double f = ((double)pj.L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
-                  if (!ADJ) {
-                    F += f;
+          if (acc) n_rays++;
+          const bool bucket = rax_right(w.right_ax) == 0;
+          const uint64_t keyC = a.key[n];
+          // The rays of this cell: the accepting sinks' (in lane order), then
+          // for an opened bucket each particle's (particle-major), handed out
+          // 64 at a time to all lanes.
+          const int nA = __popcll(accm);
+          const int kend = (bucket && openm) ? w.first + w.count : w.first;
+          int kk0 = w.first;
+          bool with_cell = nA > 0;
+          const bool op = (openm >> lane) & 1;
+          while (with_cell || kk0 < kend) {
+            const int kcnt = kend - kk0 < kChunkP ? kend - kk0 : kChunkP;
+            uint32_t myuse = 0;
+            int nB = 0;
+            for (int i = 0; i < kcnt; ++i) {
+              const P4<T> pj = a.ps[kk0 + i];
+              const bool use = op && pj.L > (T)0 && kk0 + i != k &&
+                               !(pj.x == me.x && pj.y == me.y && pj.z == me.z);
+              const uint64_t um = __ballot(use);
+              if (lane == 0) {
+                s_usem[i] = um;
+                s_upre[i] = nB;
+              }
+              nB += __popcll(um);
+              if (use) {
+                myuse |= 1u << i;
+                n_rays++;
+                n_psrc++;
+              }
+            }
+            const int nC = with_cell ? nA : 0;
+            const int nP = nC + nB;
+            for (int r0 = 0; r0 < nP; r0 += 64) {
+              wave_sync();
+              // each owner posts its rays that fall in this round
+              if (with_cell && acc) {
+                const int idx = __popcll(accm & below) - r0;
+                if (idx >= 0 && idx < 64) s_pair[idx] = lane;
+              }
+              for (uint32_t bits = myuse; bits; bits &= bits - 1) {
+                const int i = __ffs(bits) - 1;
+                const int idx = nC + s_upre[i] + __popcll(s_usem[i] & below) - r0;
+                if (idx >= 0 && idx < 64) s_pair[idx] = lane | ((i + 1) << 8);
+              }
+              wave_sync();
+              const bool busy = r0 + lane < nP;
+              const int e = busy ? s_pair[lane] : 0;
+              const int owner = e & 63;
+              const int src = e >> 8;  // 0: the cell itself, i > 0: particle kk0 + i - 1
+              // the owner's sink
+              const T ox = __shfl(me.x, owner), oy = __shfl(me.y, owner), oz = __shfl(me.z, owner);
+              SinkCtx tk;
+              tk.S = __shfl(sk.S, owner);
+              tk.keyS = __shfl(sk.keyS, owner);
+              tk.depthS = __shfl(sk.depthS, owner);
+              tk.alphaS = __shfl(sk.alphaS, owner);
+              tk.axm[0] = __shfl(sk.axm[0], owner);
+              tk.axm[1] = __shfl(sk.axm[1], owner);
+              tk.axm[2] = __shfl(sk.axm[2], owner);
+              tk.root = __shfl(sk.root, owner);
+              tk.dpre = d_common;
+              tk.ks = KS;
+              tk.pre = s_pre;
+              tk.win = s_anc + owner;
+              const double wg = ADJ ? __shfl(wgt, owner) : 0.0;
+              double f = 0.0, cl = 0.0, cx0 = 0.0, cx1 = 0.0, cx2 = 0.0, dl = 0.0;
+              c.n_seg = 0;
+              c.n_trace = 0;
+              if (busy) {
+                c.xi[0] = (double)ox;
+                c.xi[1] = (double)oy;
+                c.xi[2] = (double)oz;
+                T yx = w.xl[0], yy = w.xl[1], yz = w.xl[2], L = w.L;
+                if (src > 0) {
+                  const P4<T> pj = a.ps[kk0 + src - 1];
+                  yx = pj.x;
+                  yy = pj.y;
+                  yz = pj.z;
+                  L = pj.L;
+                }
+                ray_setup(c, (double)yx, (double)yy, (double)yz);
+                TauSum ts;
+                trace_pieces<T>(a, s_path, n, keyC, depth, tk, c, ts);
+                f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
+                if (ADJ) {
+                  Scatter sc;
+                  sc.g = wg * f;
+                  for (int q3 = 0; q3 < 3; ++q3)
+                    sc.dtdy[q3] = src == 0 ? (ts.tau / c.r) * (c.d[q3] / c.r) : 0.0;
+                  sc.r = c.r;
+                  sc.inv[0] = c.inv[0];
+                  sc.inv[1] = c.inv[1];
+                  sc.inv[2] = c.inv[2];
+                  sc.abar = a.abar;
+                  sc.acc_s = acc_s;
+                  sc.acc_p = acc_p;
+                  sc.d_common = d_common;
+                  trace_pieces<T>(a, s_path, n, keyC, depth, tk, c, sc);
+                  if (src == 0) {
+                    cl = sc.g / (double)L;
+                    cx0 = sc.g * (-2.0 * c.d[0] / c.r2 - sc.dtdy[0]);
+                    cx1 = sc.g * (-2.0 * c.d[1] / c.r2 - sc.dtdy[1]);
+                    cx2 = sc.g * (-2.0 * c.d[2] / c.r2 - sc.dtdy[2]);
                   } else {
-                    Scatter sc;
-                    sc.g = wgt * f;
-                    sc.dtdy[0] = sc.dtdy[1] = sc.dtdy[2] = 0.0;
-                    sc.r = c.r;
-                    sc.inv = c.inv;
-                    sc.abar = a.abar;
-                    sc.acc_s = acc_s;
-                    sc.acc_p = acc_p;
-                    sc.d_common = d_common;
-                    trace_pieces<T>(a, s_path, n, keyC, depth, sk, c, sc);
-                    dl = sc.g / (double)pj.L;
+                    dl = sc.g / (double)L;
                   }
                 }
-                if (ADJ && __ballot(use)) {
-                  const double s0 = wave_sum(dl);
-                  if (lane == 0) gbl_add(&a.direct[kk], s0);
+              }
+              if (ADJ) {
+                if (r0 < nC) {  // d loss / d L_C and d loss / d x_L of this cell
+                  const double s0 = wave_sum(cl), s1 = wave_sum(cx0), s2 = wave_sum(cx1),
+                               s3 = wave_sum(cx2);
+                  if (lane == 0) {
+                    gbl_add(&a.lbar[n], s0);
+                    gbl_add(&a.xbar[n], s1);
+                    gbl_add(&a.xbar[a.m + n], s2);
+                    gbl_add(&a.xbar[2 * a.m + n], s3);
+                  }
+                }
+                for (int i = 0; i < kcnt; ++i) {  // d loss / d L_j of the particle sources
+                  const bool hit = busy && src == i + 1;
+                  if (__ballot(hit) == 0) continue;
+                  const double s0 = wave_sum(hit ? dl : 0.0);
+                  if (lane == 0) gbl_add(&a.direct[kk0 + i], s0);
+                }
+              } else {
+                s_f[lane] = f;
+                s_seg[lane] = c.n_seg;
+                s_trc[lane] = c.n_trace;
+                wave_sync();
+                // each owner adds its rays in particle order
+                if (with_cell && acc) {
+                  const int idx = __popcll(accm & below) - r0;
+                  if (idx >= 0 && idx < 64) {
+                    F += s_f[idx];
+                    n_seg += s_seg[idx];
+                    n_trace += s_trc[idx];
+                  }
+                }
+                for (uint32_t bits = myuse; bits; bits &= bits - 1) {
+                  const int i = __ffs(bits) - 1;
+                  const int idx = nC + s_upre[i] + __popcll(s_usem[i] & below) - r0;
+                  if (idx >= 0 && idx < 64) {
+                    F += s_f[idx];
+                    n_seg += s_seg[idx];
+                    n_trace += s_trc[idx];
+                  }
                 }
               }
-            } else {
-              descend = true;
             }
+            with_cell = false;
+            kk0 += kcnt;
           }
         }
-        if (descend) {
+        if (openm && rax_right(w.right_ax) != 0) {
           s_open[depth] = openm;
           active = openm;
           n = n + 1;
@@ -616,7 +828,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       if (lane == lead0) {
         for (int dd = 0; dd <= d_common; ++dd) {
           const double v = acc_s[dd];
-          if (v != 0.0) gbl_add(&a.abar[sk.anc[dd]], v);
+          if (v != 0.0) gbl_add(&a.abar[s_pre[dd]], v);
           acc_s[dd] = 0.0;
         }
       }
@@ -628,8 +840,8 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         o[0] = bad ? -1 : n_open;
         o[1] = bad ? -1 : n_rays;
         o[2] = bad ? -1 : n_psrc;
-        o[3] = bad ? -1 : c.n_seg;
-        o[4] = bad ? -1 : c.n_trace;
+        o[3] = bad ? -1 : n_seg;
+        o[4] = bad ? -1 : n_trace;
       }
     }
   }
@@ -640,28 +852,29 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
 // shape picks one (waves per SIMD = workgroups per CU x waves per workgroup
 // / 4, at least 3).
 template <typename T, bool ADJ>
-__global__ __launch_bounds__(256) void k_walk(FluxArgs<T> a) {
-  walk_body<T, ADJ>(a);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk(
+    FluxArgs<T> a) {
+  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ)>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
     FluxArgs<T> a) {
-  walk_body<T, ADJ>(a);
+  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ)>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
     FluxArgs<T> a) {
-  walk_body<T, ADJ>(a);
+  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ)>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_walk6(
     FluxArgs<T> a) {
-  walk_body<T, ADJ>(a);
+  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ)>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_walk8(
     FluxArgs<T> a) {
-  walk_body<T, ADJ>(a);
+  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ)>(a);
 }
 
 __global__ void k_zero_i32(int32_t *p, int n) {
@@ -757,15 +970,18 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   int64_t blocks = (int64_t)t->launch.blocks_per_cu * t->num_cu;
   const int64_t need = (a.n_chunks + waves - 1) / waves;
   if (blocks > need) blocks = need;
-  const size_t shmem = (size_t)waves * lds_per_wave<ADJ>();
   const int per_simd = (t->launch.blocks_per_cu * waves + 3) / 4;
-  if (per_simd >= 8)
+  const int wps = per_simd >= 8 ? 8 : per_simd >= 6 ? 6 : per_simd == 5 ? 5 : per_simd == 4 ? 4 : 3;
+  // waves per workgroup <= 4 x wps, so the workgroup fits the CU's LDS
+  const size_t shmem = (size_t)waves * occ_lds<ADJ>(wps);
+  if (shmem > kLdsPerCu) return fail(TREVR_E_ARG, "launch shape needs more LDS than a CU has");
+  if (wps == 8)
     k_walk8<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
-  else if (per_simd >= 6)
+  else if (wps == 6)
     k_walk6<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
-  else if (per_simd == 5)
+  else if (wps == 5)
     k_walk5<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
-  else if (per_simd == 4)
+  else if (wps == 4)
     k_walk4<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
   else
     k_walk<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
