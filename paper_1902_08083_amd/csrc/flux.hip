@@ -178,7 +178,8 @@ struct Scatter {
 
 // Refinement of cell X on [ta, tb]: the cell's own average unless it is not a
 // bucket and (alpha_max - alpha_min) l > tau_ref; then the near and far
-// halves in ray order (an explicit stack replaces the recursion).
+// halves in ray order (an explicit stack replaces the recursion).  A ray in
+// the split plane lies in the upper half only.
 template <typename T, typename Emit>
 __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, double ta,
                        int ga, double tb, int gb, RayCtx &c, Emit &emit) {
@@ -192,7 +193,9 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
     const double l = c.r * (ctb - cta);
     c.n_trace++;
     const int right = rax_right(rec.right_ax);
-    if (right == 0 || !((double)rec.dalpha * l > c.tau_ref)) {
+    // both operands evaluated: the whole record is used on every step
+    const bool split_it = (right != 0) & ((double)rec.dalpha * l > c.tau_ref);
+    if (!split_it) {
       if (l > 0) c.n_seg++;
       emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb);
       if (sp == 0) return;
@@ -214,38 +217,31 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
     const int ax = rax_axis(rec.right_ax);
     const double s = (double)rec.split;
     const double dax = sel3(c.d, ax), xax = sel3(c.xi, ax);
-    if (dax == 0.0) {  // parallel to the plane: one side only
-      cur = xax >= s ? right : cur + 1;
-      continue;
-    }
     const double ts = (s - xax) * sel3(c.inv, ax);
-    const int nearc = dax > 0 ? cur + 1 : right;
-    const int farc = dax > 0 ? right : cur + 1;
-    double t1 = ctb;
-    int g1 = cgb;
-    if (ts < ctb) {
-      t1 = ts;
-      g1 = ax;
-    }
-    double t0 = cta;
-    int g0 = cga;
-    if (ts > cta) {
-      t0 = ts;
-      g0 = ax;
-    }
-    const bool has_near = t1 > cta, has_far = ctb > t0;
-    if (has_near) {
-      if (has_far) {
-        if (sp < c.kr) {
-          ((lds_i32 *)c.stn)[sp * kWave] = (int32_t)((uint32_t)farc | ((uint32_t)(cgb + 1) << 30));
-          ((lds_d *)c.stb)[sp * kWave] = ctb;
-        } else {
-          ovf[sp - c.kr].node = farc;
-          ovf[sp - c.kr].tag = cgb;
-          ovf[sp - c.kr].tb = ctb;
-        }
-        ++sp;
+    const bool par = dax == 0.0;                   // parallel to the plane: one side only
+    const bool up = par ? xax >= s : dax < 0.0;    // the near half is the upper child
+    const int nearc = up ? right : cur + 1;
+    const int farc = up ? cur + 1 : right;
+    const bool cut_b = !par && ts < ctb;           // the plane ends the near part
+    const bool cut_a = !par && ts > cta;           // the plane starts the far part
+    const double t1 = cut_b ? ts : ctb;
+    const int g1 = cut_b ? ax : cgb;
+    const double t0 = cut_a ? ts : cta;
+    const int g0 = cut_a ? ax : cga;
+    const bool has_near = par || t1 > cta;
+    const bool has_far = !par && ctb > t0;
+    if (has_near && has_far) {
+      if (sp < c.kr) {
+        ((lds_i32 *)c.stn)[sp * kWave] = (int32_t)((uint32_t)farc | ((uint32_t)(cgb + 1) << 30));
+        ((lds_d *)c.stb)[sp * kWave] = ctb;
+      } else {
+        ovf[sp - c.kr].node = farc;
+        ovf[sp - c.kr].tag = cgb;
+        ovf[sp - c.kr].tb = ctb;
       }
+      ++sp;
+    }
+    if (has_near) {
       cur = nearc;
       ctb = t1;
       cgb = g1;
