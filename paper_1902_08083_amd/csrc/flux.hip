@@ -76,7 +76,11 @@ __device__ __forceinline__ double pick3(int a, double v0, double v1, double v2) 
 
 // A trace record in one vector load (16 B in binary32, 32 B in binary64).
 __device__ __forceinline__ TraceRecT<float> load_tr(const TraceRecT<float> *TR, int i) {
-  const uint4 u = *reinterpret_cast<const uint4 *>(TR + i);
+  uint4 u = *reinterpret_cast<const uint4 *>(TR + i);
+  // Pin the four words so that the record stays one 16-byte load: the
+  // compiler would otherwise split it into dependent loads of the fields
+  // each branch uses.
+  asm volatile("" : "+v"(u.x), "+v"(u.y), "+v"(u.z), "+v"(u.w));
   TraceRecT<float> r;
   r.split = __uint_as_float(u.x);
   r.alpha = __uint_as_float(u.y);
@@ -85,8 +89,10 @@ __device__ __forceinline__ TraceRecT<float> load_tr(const TraceRecT<float> *TR, 
   return r;
 }
 __device__ __forceinline__ TraceRecT<double> load_tr(const TraceRecT<double> *TR, int i) {
-  const uint4 u = reinterpret_cast<const uint4 *>(TR + i)[0];
-  const uint4 w = reinterpret_cast<const uint4 *>(TR + i)[1];
+  uint4 u = reinterpret_cast<const uint4 *>(TR + i)[0];
+  uint4 w = reinterpret_cast<const uint4 *>(TR + i)[1];
+  asm volatile("" : "+v"(u.x), "+v"(u.y), "+v"(u.z), "+v"(u.w));
+  asm volatile("" : "+v"(w.x), "+v"(w.y), "+v"(w.z));
   TraceRecT<double> r;
   r.split = __hiloint2double((int)u.y, (int)u.x);
   r.alpha = __hiloint2double((int)u.w, (int)u.z);
