@@ -171,6 +171,15 @@ def cpu_baseline(w, target_s=10.0):
                       "scaled to all sinks" % (t_build, ns, n, t_flux)}
 
 
+def walk_kernel_name(launch):
+    """The walk kernel variant a launch shape selects: waves per SIMD =
+    ceil(workgroups per CU x waves per workgroup (at most 4) / 4)."""
+    waves = min(launch["waves_per_block"], 4)
+    per_simd = (launch["blocks_per_cu"] * waves + 3) // 4
+    wps = 8 if per_simd >= 8 else 6 if per_simd >= 6 else per_simd if per_simd >= 4 else 3
+    return "trevr::k_walk%s<float, false>" % ("" if wps == 3 else str(wps))
+
+
 def recorded_traffic(launch_key):
     """HBM bytes per flux launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source and launch."""
@@ -261,7 +270,7 @@ def main():
                      "n_seg": n_seg / n, "n_trace": n_trace / n},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "trevr::k_walk<float, false>",
+                     "kernel": walk_kernel_name(launch),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
     if not args.no_adjoint:
