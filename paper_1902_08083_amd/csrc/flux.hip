@@ -74,32 +74,50 @@ __device__ __forceinline__ double pick3(int a, double v0, double v1, double v2) 
 }
 #define sel3(v, a) pick3((a), (v)[0], (v)[1], (v)[2])
 
-// A trace record in one vector load (16 B in binary32, 32 B in binary64).
-__device__ __forceinline__ TraceRecT<float> load_tr(const TraceRecT<float> *TR, int i) {
-  uint4 u = *reinterpret_cast<const uint4 *>(TR + i);
-  // Pin the four words so that the record stays one 16-byte load: the
-  // compiler would otherwise split it into dependent loads of the fields
-  // each branch uses.
-  asm volatile("" : "+v"(u.x), "+v"(u.y), "+v"(u.z), "+v"(u.w));
+// A trace record as one vector load (16 B in binary32, 32 B in binary64):
+// tr_fetch issues it, tr_open waits for it and unpacks the fields.  The
+// loaded words are pinned by an empty asm statement; otherwise the compiler
+// splits the load into dependent loads of the fields each branch uses.
+template <typename T>
+struct TrRaw;
+template <>
+struct TrRaw<float> {
+  uint4 u;
+};
+template <>
+struct TrRaw<double> {
+  uint4 u, w;
+};
+__device__ __forceinline__ TrRaw<float> tr_fetch(const TraceRecT<float> *TR, int i) {
+  return TrRaw<float>{*reinterpret_cast<const uint4 *>(TR + i)};
+}
+__device__ __forceinline__ TrRaw<double> tr_fetch(const TraceRecT<double> *TR, int i) {
+  return TrRaw<double>{reinterpret_cast<const uint4 *>(TR + i)[0],
+                       reinterpret_cast<const uint4 *>(TR + i)[1]};
+}
+__device__ __forceinline__ TraceRecT<float> tr_open(TrRaw<float> v) {
+  asm volatile("" : "+v"(v.u.x), "+v"(v.u.y), "+v"(v.u.z), "+v"(v.u.w));
   TraceRecT<float> r;
-  r.split = __uint_as_float(u.x);
-  r.alpha = __uint_as_float(u.y);
-  r.dalpha = __uint_as_float(u.z);
-  r.right_ax = (int32_t)u.w;
+  r.split = __uint_as_float(v.u.x);
+  r.alpha = __uint_as_float(v.u.y);
+  r.dalpha = __uint_as_float(v.u.z);
+  r.right_ax = (int32_t)v.u.w;
   return r;
 }
-__device__ __forceinline__ TraceRecT<double> load_tr(const TraceRecT<double> *TR, int i) {
-  uint4 u = reinterpret_cast<const uint4 *>(TR + i)[0];
-  uint4 w = reinterpret_cast<const uint4 *>(TR + i)[1];
-  asm volatile("" : "+v"(u.x), "+v"(u.y), "+v"(u.z), "+v"(u.w));
-  asm volatile("" : "+v"(w.x), "+v"(w.y), "+v"(w.z));
+__device__ __forceinline__ TraceRecT<double> tr_open(TrRaw<double> v) {
+  asm volatile("" : "+v"(v.u.x), "+v"(v.u.y), "+v"(v.u.z), "+v"(v.u.w));
+  asm volatile("" : "+v"(v.w.x), "+v"(v.w.y), "+v"(v.w.z));
   TraceRecT<double> r;
-  r.split = __hiloint2double((int)u.y, (int)u.x);
-  r.alpha = __hiloint2double((int)u.w, (int)u.z);
-  r.dalpha = __hiloint2double((int)w.y, (int)w.x);
-  r.right_ax = (int32_t)w.z;
+  r.split = __hiloint2double((int)v.u.y, (int)v.u.x);
+  r.alpha = __hiloint2double((int)v.u.w, (int)v.u.z);
+  r.dalpha = __hiloint2double((int)v.w.y, (int)v.w.x);
+  r.right_ax = (int32_t)v.w.z;
   r.pad = 0;
   return r;
+}
+template <typename T>
+__device__ __forceinline__ TraceRecT<T> load_tr(const TraceRecT<T> *TR, int i) {
+  return tr_open(tr_fetch(TR, i));
 }
 
 typedef __attribute__((address_space(3))) int32_t lds_i32;
@@ -194,8 +212,11 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
   int cur = X;
   double cta = ta, ctb = tb;
   int cga = ga, cgb = gb;
+  // The next cell's record is requested before the current piece is
+  // emitted: an emit that writes device memory then does not delay it.
+  TrRaw<T> raw = tr_fetch(TR, cur);
   for (;;) {
-    const TraceRecT<T> rec = load_tr(TR, cur);
+    const TraceRecT<T> rec = tr_open(raw);
     const double l = c.r * (ctb - cta);
     c.n_trace++;
     const int right = rax_right(rec.right_ax);
@@ -203,21 +224,28 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
     const bool split_it = (right != 0) & ((double)rec.dalpha * l > c.tau_ref);
     if (!split_it) {
       if (l > 0) c.n_seg++;
-      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb);
-      if (sp == 0) return;
-      --sp;
-      cta = ctb;
-      cga = cgb;
-      if (sp < c.kr) {
-        const uint32_t e = (uint32_t)((lds_i32 *)c.stn)[sp * kWave];
-        cur = (int)(e & 0x3fffffffu);
-        cgb = (int)(e >> 30) - 1;
-        ctb = ((lds_d *)c.stb)[sp * kWave];
-      } else {
-        cur = ovf[sp - c.kr].node;
-        ctb = ovf[sp - c.kr].tb;
-        cgb = ovf[sp - c.kr].tag;
+      const int node = cur;
+      const double pa = cta, pb = ctb;
+      const int pga = cga, pgb = cgb;
+      const bool more = sp > 0;
+      if (more) {
+        --sp;
+        cta = ctb;
+        cga = cgb;
+        if (sp < c.kr) {
+          const uint32_t e = (uint32_t)((lds_i32 *)c.stn)[sp * kWave];
+          cur = (int)(e & 0x3fffffffu);
+          cgb = (int)(e >> 30) - 1;
+          ctb = ((lds_d *)c.stb)[sp * kWave];
+        } else {
+          cur = ovf[sp - c.kr].node;
+          ctb = ovf[sp - c.kr].tb;
+          cgb = ovf[sp - c.kr].tag;
+        }
+        raw = tr_fetch(TR, cur);
       }
+      emit(node, node == X ? top_slot : -1, (double)rec.alpha, l, pa, pga, pb, pgb);
+      if (!more) return;
       continue;
     }
     const int ax = rax_axis(rec.right_ax);
@@ -258,6 +286,7 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
     } else {
       return;  // empty interval (only at the top call)
     }
+    raw = tr_fetch(TR, cur);
   }
 }
 
