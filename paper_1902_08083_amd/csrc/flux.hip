@@ -33,7 +33,6 @@
 namespace trevr {
 
 constexpr int kXcd = 8;
-constexpr int kChunkP = 32;  // bucket particles whose rays are dealt out together
 
 template <typename T>
 struct FluxArgs {
@@ -179,13 +178,18 @@ struct Scatter {
   double *abar;
   double *acc_s, *acc_p;  // LDS, per wave
   int d_common;           // sink-chain depths <= this are shared by the wave
-  int nodes_s_unused;
+  const int32_t *path;    // the walk's current path (LDS) ...
+  int live;               // ... valid at depths <= live
   __device__ __forceinline__ void operator()(int node, int slot, double alpha, double l,
                                              double ta, int ga, double tb, int gb) {
     const double v = -(g * l);
-    if (slot >= kSlotSrc)
-      lds_add(&acc_p[slot - kSlotSrc], v);
-    else if (slot >= 0 && slot <= d_common)
+    if (slot >= kSlotSrc) {  // a source-side cell: pooled while it is on the walk's path
+      const int dd = slot - kSlotSrc;
+      if (dd <= live && path[dd] == node)
+        lds_add(&acc_p[dd], v);
+      else
+        gbl_add(&abar[node], v);
+    } else if (slot >= 0 && slot <= d_common)
       lds_add(&acc_s[slot], v);
     else
       gbl_add(&abar[node], v);
@@ -349,8 +353,8 @@ __device__ __forceinline__ void ray_setup(RayCtx &c, double y0, double y1, doubl
 // handing every piece to `emit` in a fixed order: sink chain (from the
 // meeting cell down), the sink's bucket, source chain, the source cell.
 template <typename T, typename Emit>
-__device__ void trace_pieces(const FluxArgs<T> &a, const int32_t *s_path, int C, uint64_t keyC,
-                             int depthC, const SinkCtx &sk, RayCtx &c, Emit &emit) {
+__device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int depthC,
+                             const SinkCtx &sk, RayCtx &c, Emit &emit) {
   if (C == sk.S) {
     c.n_trace++;
     const double l = c.r * (1.0 - 0.0);
@@ -359,7 +363,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, const int32_t *s_path, int C,
     return;
   }
   const int ad = __clzll((long long)(sk.keyS ^ keyC)) - 1;  // depth of the meeting cell
-  const int A = s_path[ad];
+  const int A = sink_anc<T>(a.TR, sk, ad);
   const TraceRecT<T> rA = load_tr(a.TR, A);
   const int axA = rax_axis(rA.right_ax);
   const int sr = (int)((sk.keyS >> (62 - ad)) & 1);
@@ -429,29 +433,39 @@ __device__ void trace_pieces(const FluxArgs<T> &a, const int32_t *s_path, int C,
     if (l > 0) c.n_seg++;
     emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, tP, gP);
   }
-  // source side, [tQ, 1]
+  // source side, [tQ, 1]: C's ancestors below A are found walking down from
+  // A along C's path bits.  A lower child is the next cell in depth-first
+  // order, so only the levels where the path turns to the upper child, or
+  // where the ray crosses, need their record.
   double tQ = tA;
   int gQ = gA;
-  while (mC) {
-    const int pos = 63 - __clzll((long long)mC);
-    mC &= ~(1ull << pos);
+  uint64_t stops = (keyC & below_A & ~((1ull << (63 - depthC)) - 1)) | mC;
+  int Q = ((keyC >> (62 - ad)) & 1) ? rax_right(rA.right_ax) : A + 1;  // at depth ad + 1
+  int dq = ad + 1;
+  while (stops) {
+    const int pos = 63 - __clzll((long long)stops);
+    stops &= ~(1ull << pos);
     const int dd = 62 - pos;
-    const int Q = s_path[dd];
+    Q += dd - dq;  // lower children in between
     const TraceRecT<T> rQ = load_tr(a.TR, Q);
     const int b = (int)((keyC >> (62 - dd)) & 1);
-    const int ax = rax_axis(rQ.right_ax);
-    double tc = ((double)rQ.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
-    int gc = ax;
-    if (tc > 1.0) {
-      tc = 1.0;
-      gc = -1;
+    if ((mC >> pos) & 1) {
+      const int ax = rax_axis(rQ.right_ax);
+      double tc = ((double)rQ.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
+      int gc = ax;
+      if (tc > 1.0) {
+        tc = 1.0;
+        gc = -1;
+      }
+      if (tc > tQ) {
+        const int sib = b ? Q + 1 : rax_right(rQ.right_ax);
+        chain_piece<T>(a.TR, rQ, Q, kSlotSrc + dd, sib, tQ, gQ, tc, gc, c, emit);
+        tQ = tc;
+        gQ = gc;
+      }
     }
-    if (tc > tQ) {
-      const int sib = b ? Q + 1 : rax_right(rQ.right_ax);
-      chain_piece<T>(a.TR, rQ, Q, kSlotSrc + dd, sib, tQ, gQ, tc, gc, c, emit);
-      tQ = tc;
-      gQ = gc;
-    }
+    Q = b ? rax_right(rQ.right_ax) : Q + 1;
+    dq = dd + 1;
   }
   refine<T>(a.TR, C, kSlotSrc + depthC, tQ, gQ, 1.0, -1, c, emit);
 }
@@ -475,27 +489,26 @@ __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
 
 // LDS per wave, binary64 items first: open masks (64 x u64), the adjoint's
 // two accumulator rows (64 x f64 each), the refinement stacks (kr x 64 lanes x
-// (f64 + i32)), the ray results of a round (64 x f64, 2 x 64 x i32), the
-// particle-use masks of a bucket chunk and their prefix counts (32 each), the
-// sink-ancestor windows (ks x 64 lanes x i32), the walk path, the shared
-// sink-chain prefix and the ray list of a round (64 x i32 each).
+// (f64 + i32)), the ray queue (kQueue x (i32 + u8)), the per-sink counts of
+// traced pieces and steps (2 x 64 x i32, forward only), the sink-ancestor
+// windows (ks x 64 lanes x i32), the walk path and the shared sink-chain
+// prefix (64 x i32 each).
+constexpr int kQueue = 128;  // ray queue slots per wave (a power of two)
 template <bool ADJ>
 __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr) {
-  return (size_t)64 * 8 + (ADJ ? 2 * 64 * 8 : 0) + (size_t)kr * 64 * 12 + 64 * 8 + 2 * 64 * 4 +
-         kChunkP * (8 + 4) + (size_t)ks * 64 * 4 + 3 * 64 * 4;
+  return (size_t)64 * 8 + (ADJ ? 2 * 64 * 8 : 0) + (size_t)kr * 64 * 12 + kQueue * 5 +
+         (ADJ ? 0 : 2 * 64 * 4) + (size_t)ks * 64 * 4 + 2 * 64 * 4;
 }
 
 // Window and stack depth per occupancy variant (waves per SIMD), chosen so
 // that that many waves fit the CU's 160 KiB of LDS.
 __host__ __device__ constexpr int occ_ks(int wps, bool adj) {
-  return wps <= 3 ? (adj ? 14 : 18)
-                  : wps == 4 ? (adj ? 10 : 11)
-                             : wps == 5 ? (adj ? 8 : 9) : wps <= 7 ? (adj ? 6 : 7) : (adj ? 2 : 3);
+  return wps <= 3 ? (adj ? 18 : 20)
+                  : wps == 4 ? (adj ? 11 : 13)
+                             : wps == 5 ? (adj ? 9 : 8) : wps <= 7 ? (adj ? 7 : 6) : (adj ? 3 : 5);
 }
 __host__ __device__ constexpr int occ_kr(int wps, bool adj) {
-  return wps <= 3 ? 8
-                  : wps == 4 ? (adj ? 5 : 6)
-                             : wps == 5 ? (adj ? 3 : 4) : wps <= 7 ? (adj ? 2 : 3) : (adj ? 1 : 2);
+  return wps <= 3 ? 8 : wps == 4 ? 6 : wps == 5 ? (adj ? 4 : 5) : wps <= 7 ? (adj ? 3 : 4) : 2;
 }
 template <bool ADJ>
 __host__ __device__ constexpr size_t occ_lds(int wps) {
@@ -515,6 +528,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source, not a cell
+
+// The source walk of 64 sinks, one per lane, shared by the wave (Sec. 2.2.1).
+// The rays it produces go, in walk order, into one queue per wave: at each
+// visited cell the accepting sinks' rays (in lane order), then for an opened
+// bucket each (sink, particle) pair (particle-major).  Whenever 64 rays are
+// queued they are traced as one round, one ray per lane, and what is left at
+// the end of a box is traced in shorter rounds.  Rays of consecutive cells are
+// alike, so a round's lanes run for similar times.  A tracing lane takes the
+// owning sink's context by lane shuffles; each owner adds its results in
+// queue order, so a sink's sum is in its own walk order whatever the other
+// sinks of the wave are.
 template <typename T, bool ADJ, int KS, int KR>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
@@ -529,21 +554,17 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   if (ADJ) base += 2 * 64 * 8;
   double *s_stb = reinterpret_cast<double *>(base);
   base += KR * 64 * 8;
-  double *s_f = reinterpret_cast<double *>(base);
-  base += 64 * 8;
-  uint64_t *s_usem = reinterpret_cast<uint64_t *>(base);
-  base += kChunkP * 8;
   int32_t *s_stn = reinterpret_cast<int32_t *>(base);
   base += KR * 64 * 4;
-  int32_t *s_seg = reinterpret_cast<int32_t *>(base);
-  int32_t *s_trc = s_seg + 64;
-  int32_t *s_upre = s_trc + 64;
-  base += 2 * 64 * 4 + kChunkP * 4;
+  lds_i32 *s_qe = (lds_i32 *)reinterpret_cast<int32_t *>(base);  // entry: cell or particle
+  base += kQueue * 4;
+  int32_t *s_cnt = reinterpret_cast<int32_t *>(base);  // forward: pieces, steps per sink
+  if (!ADJ) base += 2 * 64 * 4;
   int32_t *s_anc = reinterpret_cast<int32_t *>(base);
   base += KS * 64 * 4;
   int32_t *s_path = reinterpret_cast<int32_t *>(base);
   int32_t *s_pre = s_path + 64;
-  int32_t *s_pair = s_pre + 64;
+  uint8_t *s_qo = reinterpret_cast<uint8_t *>(s_pre + 64);  // entry's owning lane
   if (ADJ) {
     acc_s[lane] = 0.0;
     acc_p[lane] = 0.0;
@@ -624,16 +645,125 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         if (dd == sk.depthS) break;
         const int slot = dd - sk.depthS + KS;
         if (slot >= 0) sk.win[slot * kWave] = node;
-        const int right = rax_right(a.TR[node].right_ax);
+        const int right = rax_right(load_tr(a.TR, node).right_ax);
         node = ((sk.keyS >> (62 - dd)) & 1) ? right : node + 1;
       }
+    }
+    if (!ADJ) {
+      s_cnt[lane] = 0;
+      s_cnt[64 + lane] = 0;
     }
     wave_sync();
     double wgt = 0.0;
     // grad_flux is indexed like flux: by list position, or by particle
     if (ADJ && valid) wgt = (double)a.grad_flux[a.sinks ? q : (int64_t)a.perm[k]];
     double F = 0.0;
-    int n_open = 0, n_rays = 0, n_psrc = 0, n_seg = 0, n_trace = 0;
+    int n_open = 0, n_rays = 0, n_psrc = 0;
+    int qh = 0, qn = 0;  // the queue: first entry, entries (wave-uniform)
+    int live = -1;       // the walk's path is s_path[0 .. live]
+
+    // One round: the first min(qn, 64) queued rays, one per lane.
+    auto round = [&]() {
+      wave_sync();
+      const int nb = qn < 64 ? qn : 64;
+      const bool busy = lane < nb;
+      uint32_t e = 0;
+      int owner = 0;
+      if (busy) {
+        const int slot = (qh + lane) & (kQueue - 1);
+        e = (uint32_t)s_qe[slot];
+        owner = s_qo[slot];
+      }
+      qh = (qh + nb) & (kQueue - 1);
+      qn -= nb;
+      // the owner's sink
+      const T ox = __shfl(me.x, owner), oy = __shfl(me.y, owner), oz = __shfl(me.z, owner);
+      SinkCtx tk;
+      tk.S = __shfl(sk.S, owner);
+      tk.keyS = __shfl(sk.keyS, owner);
+      tk.depthS = __shfl(sk.depthS, owner);
+      tk.alphaS = __shfl(sk.alphaS, owner);
+      tk.axm[0] = __shfl(sk.axm[0], owner);
+      tk.axm[1] = __shfl(sk.axm[1], owner);
+      tk.axm[2] = __shfl(sk.axm[2], owner);
+      tk.root = __shfl(sk.root, owner);
+      tk.dpre = d_common;
+      tk.ks = KS;
+      tk.pre = s_pre;
+      tk.win = s_anc + owner;
+      const double wg = ADJ ? __shfl(wgt, owner) : 0.0;
+      double f = 0.0;
+      if (busy) {
+        const bool psrc = (e & kQParticle) != 0;
+        const int id = (int)(e & ~kQParticle);
+        int C;
+        T yx, yy, yz, L;
+        if (psrc) {
+          const P4<T> pj = a.ps[id];
+          C = a.leaf[id];
+          yx = pj.x;
+          yy = pj.y;
+          yz = pj.z;
+          L = pj.L;
+        } else {
+          C = id;
+          yx = a.W[id].xl[0];
+          yy = a.W[id].xl[1];
+          yz = a.W[id].xl[2];
+          L = a.W[id].L;
+        }
+        const uint64_t keyC = a.key[C];
+        const int depthC = a.ndepth[C];
+        c.xi[0] = (double)ox;
+        c.xi[1] = (double)oy;
+        c.xi[2] = (double)oz;
+        c.n_seg = 0;
+        c.n_trace = 0;
+        ray_setup(c, (double)yx, (double)yy, (double)yz);
+        TauSum ts;
+        trace_pieces<T>(a, C, keyC, depthC, tk, c, ts);
+        f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
+        if (!ADJ) {
+          __hip_atomic_fetch_add(&s_cnt[owner], c.n_seg, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
+          __hip_atomic_fetch_add(&s_cnt[64 + owner], c.n_trace, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
+        } else {
+          Scatter sc;
+          sc.g = wg * f;
+          for (int q3 = 0; q3 < 3; ++q3)
+            sc.dtdy[q3] = psrc ? 0.0 : (ts.tau / c.r) * (c.d[q3] / c.r);
+          sc.r = c.r;
+          sc.inv[0] = c.inv[0];
+          sc.inv[1] = c.inv[1];
+          sc.inv[2] = c.inv[2];
+          sc.abar = a.abar;
+          sc.acc_s = acc_s;
+          sc.acc_p = acc_p;
+          sc.d_common = d_common;
+          sc.path = s_path;
+          sc.live = live;
+          trace_pieces<T>(a, C, keyC, depthC, tk, c, sc);
+          if (psrc) {  // d loss / d L_j of the particle source
+            gbl_add(&a.direct[id], sc.g / (double)L);
+          } else {  // d loss / d L_C and d loss / d x_L of the cell
+            gbl_add(&a.lbar[C], sc.g / (double)L);
+            gbl_add(&a.xbar[C], sc.g * (-2.0 * c.d[0] / c.r2 - sc.dtdy[0]));
+            gbl_add(&a.xbar[a.m + C], sc.g * (-2.0 * c.d[1] / c.r2 - sc.dtdy[1]));
+            gbl_add(&a.xbar[2 * a.m + C], sc.g * (-2.0 * c.d[2] / c.r2 - sc.dtdy[2]));
+          }
+        }
+      }
+      if (!ADJ) {  // each owner adds its rays' fluxes in queue order
+        for (int j = 0; j < nb; ++j) {
+          const int oj = __builtin_amdgcn_readlane(owner, j);
+          const double fj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(f), j),
+                                             __builtin_amdgcn_readlane(__double2loint(f), j));
+          if (lane == oj) F += fj;
+        }
+      }
+    };
+
     uint64_t pending = vmask;
     while (pending) {
       const int lead = __ffsll((unsigned long long)pending) - 1;
@@ -661,6 +791,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           s_path[depth] = n;
         }
         depth_prev = depth;
+        live = depth;
         const bool mine = (active >> lane) & 1;
         uint64_t openm = 0;
         if (w.L != (T)0) {
@@ -680,159 +811,32 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           }
           const uint64_t accm = __ballot(acc);
           openm = active & ~accm;
-          if (acc) n_rays++;
-          const bool bucket = rax_right(w.right_ax) == 0;
-          const uint64_t keyC = a.key[n];
-          // The rays of this cell: the accepting sinks' (in lane order), then
-          // for an opened bucket each particle's (particle-major), handed out
-          // 64 at a time to all lanes.
-          const int nA = __popcll(accm);
-          const int kend = (bucket && openm) ? w.first + w.count : w.first;
-          int kk0 = w.first;
-          bool with_cell = nA > 0;
-          const bool op = (openm >> lane) & 1;
-          while (with_cell || kk0 < kend) {
-            const int kcnt = kend - kk0 < kChunkP ? kend - kk0 : kChunkP;
-            uint32_t myuse = 0;
-            int nB = 0;
-            for (int i = 0; i < kcnt; ++i) {
-              const P4<T> pj = a.ps[kk0 + i];
-              const bool use = op && pj.L > (T)0 && kk0 + i != k &&
+          // queue invariant: qn < 64 here, so a visit's cell rays fit
+          if (acc) {
+            n_rays++;
+            const int slot = (qh + qn + __popcll(accm & below)) & (kQueue - 1);
+            s_qe[slot] = n;
+            s_qo[slot] = (uint8_t)lane;
+          }
+          qn += __popcll(accm);
+          if (qn >= 64) round();
+          if (openm && rax_right(w.right_ax) == 0) {  // bucket: its particles one by one
+            const bool op = (openm >> lane) & 1;
+            for (int kk = w.first; kk < w.first + w.count; ++kk) {
+              const P4<T> pj = a.ps[kk];
+              const bool use = op && pj.L > (T)0 && kk != k &&
                                !(pj.x == me.x && pj.y == me.y && pj.z == me.z);
               const uint64_t um = __ballot(use);
-              if (lane == 0) {
-                s_usem[i] = um;
-                s_upre[i] = nB;
-              }
-              nB += __popcll(um);
               if (use) {
-                myuse |= 1u << i;
                 n_rays++;
                 n_psrc++;
+                const int slot = (qh + qn + __popcll(um & below)) & (kQueue - 1);
+                s_qe[slot] = (int32_t)((uint32_t)kk | kQParticle);
+                s_qo[slot] = (uint8_t)lane;
               }
+              qn += __popcll(um);
+              if (qn >= 64) round();
             }
-            const int nC = with_cell ? nA : 0;
-            const int nP = nC + nB;
-            for (int r0 = 0; r0 < nP; r0 += 64) {
-              wave_sync();
-              // each owner posts its rays that fall in this round
-              if (with_cell && acc) {
-                const int idx = __popcll(accm & below) - r0;
-                if (idx >= 0 && idx < 64) s_pair[idx] = lane;
-              }
-              for (uint32_t bits = myuse; bits; bits &= bits - 1) {
-                const int i = __ffs(bits) - 1;
-                const int idx = nC + s_upre[i] + __popcll(s_usem[i] & below) - r0;
-                if (idx >= 0 && idx < 64) s_pair[idx] = lane | ((i + 1) << 8);
-              }
-              wave_sync();
-              const bool busy = r0 + lane < nP;
-              const int e = busy ? s_pair[lane] : 0;
-              const int owner = e & 63;
-              const int src = e >> 8;  // 0: the cell itself, i > 0: particle kk0 + i - 1
-              // the owner's sink
-              const T ox = __shfl(me.x, owner), oy = __shfl(me.y, owner), oz = __shfl(me.z, owner);
-              SinkCtx tk;
-              tk.S = __shfl(sk.S, owner);
-              tk.keyS = __shfl(sk.keyS, owner);
-              tk.depthS = __shfl(sk.depthS, owner);
-              tk.alphaS = __shfl(sk.alphaS, owner);
-              tk.axm[0] = __shfl(sk.axm[0], owner);
-              tk.axm[1] = __shfl(sk.axm[1], owner);
-              tk.axm[2] = __shfl(sk.axm[2], owner);
-              tk.root = __shfl(sk.root, owner);
-              tk.dpre = d_common;
-              tk.ks = KS;
-              tk.pre = s_pre;
-              tk.win = s_anc + owner;
-              const double wg = ADJ ? __shfl(wgt, owner) : 0.0;
-              double f = 0.0, cl = 0.0, cx0 = 0.0, cx1 = 0.0, cx2 = 0.0, dl = 0.0;
-              c.n_seg = 0;
-              c.n_trace = 0;
-              if (busy) {
-                c.xi[0] = (double)ox;
-                c.xi[1] = (double)oy;
-                c.xi[2] = (double)oz;
-                T yx = w.xl[0], yy = w.xl[1], yz = w.xl[2], L = w.L;
-                if (src > 0) {
-                  const P4<T> pj = a.ps[kk0 + src - 1];
-                  yx = pj.x;
-                  yy = pj.y;
-                  yz = pj.z;
-                  L = pj.L;
-                }
-                ray_setup(c, (double)yx, (double)yy, (double)yz);
-                TauSum ts;
-                trace_pieces<T>(a, s_path, n, keyC, depth, tk, c, ts);
-                f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
-                if (ADJ) {
-                  Scatter sc;
-                  sc.g = wg * f;
-                  for (int q3 = 0; q3 < 3; ++q3)
-                    sc.dtdy[q3] = src == 0 ? (ts.tau / c.r) * (c.d[q3] / c.r) : 0.0;
-                  sc.r = c.r;
-                  sc.inv[0] = c.inv[0];
-                  sc.inv[1] = c.inv[1];
-                  sc.inv[2] = c.inv[2];
-                  sc.abar = a.abar;
-                  sc.acc_s = acc_s;
-                  sc.acc_p = acc_p;
-                  sc.d_common = d_common;
-                  trace_pieces<T>(a, s_path, n, keyC, depth, tk, c, sc);
-                  if (src == 0) {
-                    cl = sc.g / (double)L;
-                    cx0 = sc.g * (-2.0 * c.d[0] / c.r2 - sc.dtdy[0]);
-                    cx1 = sc.g * (-2.0 * c.d[1] / c.r2 - sc.dtdy[1]);
-                    cx2 = sc.g * (-2.0 * c.d[2] / c.r2 - sc.dtdy[2]);
-                  } else {
-                    dl = sc.g / (double)L;
-                  }
-                }
-              }
-              if (ADJ) {
-                if (r0 < nC) {  // d loss / d L_C and d loss / d x_L of this cell
-                  const double s0 = wave_sum(cl), s1 = wave_sum(cx0), s2 = wave_sum(cx1),
-                               s3 = wave_sum(cx2);
-                  if (lane == 0) {
-                    gbl_add(&a.lbar[n], s0);
-                    gbl_add(&a.xbar[n], s1);
-                    gbl_add(&a.xbar[a.m + n], s2);
-                    gbl_add(&a.xbar[2 * a.m + n], s3);
-                  }
-                }
-                for (int i = 0; i < kcnt; ++i) {  // d loss / d L_j of the particle sources
-                  const bool hit = busy && src == i + 1;
-                  if (__ballot(hit) == 0) continue;
-                  const double s0 = wave_sum(hit ? dl : 0.0);
-                  if (lane == 0) gbl_add(&a.direct[kk0 + i], s0);
-                }
-              } else {
-                s_f[lane] = f;
-                s_seg[lane] = c.n_seg;
-                s_trc[lane] = c.n_trace;
-                wave_sync();
-                // each owner adds its rays in particle order
-                if (with_cell && acc) {
-                  const int idx = __popcll(accm & below) - r0;
-                  if (idx >= 0 && idx < 64) {
-                    F += s_f[idx];
-                    n_seg += s_seg[idx];
-                    n_trace += s_trc[idx];
-                  }
-                }
-                for (uint32_t bits = myuse; bits; bits &= bits - 1) {
-                  const int i = __ffs(bits) - 1;
-                  const int idx = nC + s_upre[i] + __popcll(s_usem[i] & below) - r0;
-                  if (idx >= 0 && idx < 64) {
-                    F += s_f[idx];
-                    n_seg += s_seg[idx];
-                    n_trace += s_trc[idx];
-                  }
-                }
-              }
-            }
-            with_cell = false;
-            kk0 += kcnt;
           }
         }
         if (openm && rax_right(w.right_ax) != 0) {
@@ -847,6 +851,9 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         if (n >= end) break;
         from_skip = true;
       }
+      // the rest of this box's rays, while its last path is still valid
+      while (qn > 0) round();
+      live = -1;
       if (ADJ && lane == 0) {
         for (int dd = 0; dd <= depth_prev; ++dd) {
           const double v = acc_p[dd];
@@ -863,16 +870,19 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           acc_s[dd] = 0.0;
         }
       }
-    } else if (in_list) {
-      const int64_t out = a.sinks ? q : (int64_t)a.perm[k];
-      a.flux[out] = bad ? (T)NAN : (T)F;
-      if (a.counters) {
-        int32_t *o = a.counters + 5 * out;
-        o[0] = bad ? -1 : n_open;
-        o[1] = bad ? -1 : n_rays;
-        o[2] = bad ? -1 : n_psrc;
-        o[3] = bad ? -1 : n_seg;
-        o[4] = bad ? -1 : n_trace;
+    } else {
+      wave_sync();
+      if (in_list) {
+        const int64_t out = a.sinks ? q : (int64_t)a.perm[k];
+        a.flux[out] = bad ? (T)NAN : (T)F;
+        if (a.counters) {
+          int32_t *o = a.counters + 5 * out;
+          o[0] = bad ? -1 : n_open;
+          o[1] = bad ? -1 : n_rays;
+          o[2] = bad ? -1 : n_psrc;
+          o[3] = bad ? -1 : s_cnt[lane];
+          o[4] = bad ? -1 : s_cnt[64 + lane];
+        }
       }
     }
   }
