@@ -74,10 +74,12 @@ typedef struct {
   int32_t bucket_size;         /* N_B >= 1: most particles per leaf (Sec. 2.2) */
 } trevr_particles;
 
-/* Launch knobs of the flux and adjoint kernels (set by the autotuner). */
+/* Launch knobs of the flux and adjoint kernels (set by the autotuner; a new
+ * tree starts at {3, 4, 64}).  Waves per SIMD, ceil(blocks_per_cu x
+ * min(waves_per_block, 4) / 4), pick the kernel's register budget. */
 typedef struct {
   int32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..32   */
-  int32_t waves_per_block; /* 1..16 wavefronts (64 lanes) per workgroup        */
+  int32_t waves_per_block; /* 1..16 accepted; at most 4 wavefronts are used   */
   int32_t chunk;           /* sinks per work-queue grab, a multiple of 64      */
 } trevr_launch;
 

@@ -154,6 +154,40 @@ struct StackEntry {
   int32_t node, tag;
   double tb;
 };
+// The deeper part of the lane's stack (rarely reached), in private memory.
+struct StackSpill {
+  StackEntry e[kRefineStack];
+};
+
+// A stack entry whose cell is kMark opens a deferred refinement job: its tag
+// and parameter are the job's entry crossing; the entry below it holds the
+// cell and the exit.  Cell indices stay below kMark (the build checks).
+constexpr int kMark = 0x3fffffff;
+
+__device__ __forceinline__ void stack_push(RayCtx &c, StackSpill &ovf, int k, int node, int tag,
+                                           double t) {
+  if (k < c.kr) {
+    ((lds_i32 *)c.stn)[k * kWave] = (int32_t)((uint32_t)node | ((uint32_t)(tag + 1) << 30));
+    ((lds_d *)c.stb)[k * kWave] = t;
+  } else {
+    ovf.e[k - c.kr].node = node;
+    ovf.e[k - c.kr].tag = tag;
+    ovf.e[k - c.kr].tb = t;
+  }
+}
+__device__ __forceinline__ void stack_pop(const RayCtx &c, const StackSpill &ovf, int k, int &node,
+                                          int &tag, double &t) {
+  if (k < c.kr) {
+    const uint32_t e = (uint32_t)((lds_i32 *)c.stn)[k * kWave];
+    node = (int)(e & 0x3fffffffu);
+    tag = (int)(e >> 30) - 1;
+    t = ((lds_d *)c.stb)[k * kWave];
+  } else {
+    node = ovf.e[k - c.kr].node;
+    tag = ovf.e[k - c.kr].tag;
+    t = ovf.e[k - c.kr].tb;
+  }
+}
 
 // A piece's accumulator slot in the adjoint: [0, 64) the sink chain at that
 // depth, [64, 128) the walk path at that depth, -1 the cell itself.
@@ -207,12 +241,14 @@ struct Scatter {
 // Refinement of cell X on [ta, tb]: the cell's own average unless it is not a
 // bucket and (alpha_max - alpha_min) l > tau_ref; then the near and far
 // halves in ray order (an explicit stack replaces the recursion).  A ray in
-// the split plane lies in the upper half only.
+// the split plane lies in the upper half only.  The lane's stack holds sp0
+// entries, deferred jobs (a marker over a cell); those above depth base are
+// refined after X, those below are left for a later call.
 template <typename T, typename Emit>
 __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, double ta,
-                       int ga, double tb, int gb, RayCtx &c, Emit &emit) {
-  StackEntry ovf[kRefineStack];  // entries beyond the LDS part (rarely reached)
-  int sp = 0;
+                       int ga, double tb, int gb, RayCtx &c, StackSpill &ovf, int sp0, int base,
+                       Emit &emit) {
+  int sp = sp0;
   int cur = X;
   double cta = ta, ctb = tb;
   int cga = ga, cgb = gb;
@@ -231,21 +267,22 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
       const int node = cur;
       const double pa = cta, pb = ctb;
       const int pga = cga, pgb = cgb;
-      const bool more = sp > 0;
+      const bool more = sp > base;
       if (more) {
-        --sp;
-        cta = ctb;
-        cga = cgb;
-        if (sp < c.kr) {
-          const uint32_t e = (uint32_t)((lds_i32 *)c.stn)[sp * kWave];
-          cur = (int)(e & 0x3fffffffu);
-          cgb = (int)(e >> 30) - 1;
-          ctb = ((lds_d *)c.stb)[sp * kWave];
+        int nd, tg;
+        double tt;
+        stack_pop(c, ovf, --sp, nd, tg, tt);
+        if (nd == kMark) {  // a deferred job: its entry, then its cell and exit
+          cta = tt;
+          cga = tg;
+          stack_pop(c, ovf, --sp, nd, tg, tt);
         } else {
-          cur = ovf[sp - c.kr].node;
-          ctb = ovf[sp - c.kr].tb;
-          cgb = ovf[sp - c.kr].tag;
+          cta = ctb;
+          cga = cgb;
         }
+        cur = nd;
+        ctb = tt;
+        cgb = tg;
         raw = tr_fetch(TR, cur);
       }
       emit(node, node == X ? top_slot : -1, (double)rec.alpha, l, pa, pga, pb, pgb);
@@ -268,17 +305,7 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
     const int g0 = cut_a ? ax : cga;
     const bool has_near = par || t1 > cta;
     const bool has_far = !par && ctb > t0;
-    if (has_near && has_far) {
-      if (sp < c.kr) {
-        ((lds_i32 *)c.stn)[sp * kWave] = (int32_t)((uint32_t)farc | ((uint32_t)(cgb + 1) << 30));
-        ((lds_d *)c.stb)[sp * kWave] = ctb;
-      } else {
-        ovf[sp - c.kr].node = farc;
-        ovf[sp - c.kr].tag = cgb;
-        ovf[sp - c.kr].tb = ctb;
-      }
-      ++sp;
-    }
+    if (has_near && has_far) stack_push(c, ovf, sp++, farc, cgb, ctb);
     if (has_near) {
       cur = nearc;
       ctb = t1;
@@ -295,16 +322,23 @@ __device__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
 }
 
 // A piece of the ray in chain cell P but outside P's child on the path: P's
-// own average, or the sibling X refined.
+// own average, or, if P fails the refinement test, the sibling X to be
+// refined later -- a job (X on [ta, tb]) is left on the lane's stack, so
+// that all of a ray's refinement runs in one loop after its chains.
 template <typename T, typename Emit>
 __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
                                             const TraceRecT<T> &rP, int P, int slot, int X,
                                             double ta, int ga, double tb, int gb, RayCtx &c,
-                                            Emit &emit) {
+                                            StackSpill &ovf, int &sp, Emit &emit) {
   const double l = c.r * (tb - ta);
   c.n_trace++;
   if ((double)rP.dalpha * l > c.tau_ref) {
-    refine<T>(TR, X, -1, ta, ga, tb, gb, c, emit);
+    if (sp + 2 <= c.kr - 2) {  // room in the LDS part, two entries kept for refinement
+      stack_push(c, ovf, sp++, X, gb, tb);
+      stack_push(c, ovf, sp++, kMark, ga, ta);
+    } else {
+      refine<T>(TR, X, -1, ta, ga, tb, gb, c, ovf, sp, sp, emit);
+    }
     return;
   }
   if (l > 0) c.n_seg++;
@@ -362,6 +396,8 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, 1.0, -1);
     return;
   }
+  StackSpill ovf;
+  int sp = 0;  // deferred refinement jobs on the lane's stack
   const int ad = __clzll((long long)(sk.keyS ^ keyC)) - 1;  // depth of the meeting cell
   const int A = sink_anc<T>(a.TR, sk, ad);
   const TraceRecT<T> rA = load_tr(a.TR, A);
@@ -422,7 +458,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     }
     if (tc < tP) {
       const int sib = b ? P + 1 : rax_right(rP.right_ax);
-      chain_piece<T>(a.TR, rP, P, dd, sib, tc, gc, tP, gP, c, emit);
+      chain_piece<T>(a.TR, rP, P, dd, sib, tc, gc, tP, gP, c, ovf, sp, emit);
       tP = tc;
       gP = gc;
     }
@@ -459,7 +495,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
       }
       if (tc > tQ) {
         const int sib = b ? Q + 1 : rax_right(rQ.right_ax);
-        chain_piece<T>(a.TR, rQ, Q, kSlotSrc + dd, sib, tQ, gQ, tc, gc, c, emit);
+        chain_piece<T>(a.TR, rQ, Q, kSlotSrc + dd, sib, tQ, gQ, tc, gc, c, ovf, sp, emit);
         tQ = tc;
         gQ = gc;
       }
@@ -467,7 +503,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     Q = b ? rax_right(rQ.right_ax) : Q + 1;
     dq = dd + 1;
   }
-  refine<T>(a.TR, C, kSlotSrc + depthC, tQ, gQ, 1.0, -1, c, emit);
+  refine<T>(a.TR, C, kSlotSrc + depthC, tQ, gQ, 1.0, -1, c, ovf, sp, 0, emit);
 }
 
 __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
@@ -503,12 +539,12 @@ __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr) {
 // Window and stack depth per occupancy variant (waves per SIMD), chosen so
 // that that many waves fit the CU's 160 KiB of LDS.
 __host__ __device__ constexpr int occ_ks(int wps, bool adj) {
-  return wps <= 3 ? (adj ? 18 : 20)
-                  : wps == 4 ? (adj ? 11 : 13)
-                             : wps == 5 ? (adj ? 9 : 8) : wps <= 7 ? (adj ? 7 : 6) : (adj ? 3 : 5);
+  return wps <= 3 ? (adj ? 12 : 14)
+                  : wps == 4 ? (adj ? 5 : 7)
+                             : wps == 5 ? (adj ? 3 : 5) : wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
 }
 __host__ __device__ constexpr int occ_kr(int wps, bool adj) {
-  return wps <= 3 ? 8 : wps == 4 ? 6 : wps == 5 ? (adj ? 4 : 5) : wps <= 7 ? (adj ? 3 : 4) : 2;
+  return wps <= 3 ? 10 : wps == 4 ? 8 : wps == 5 ? (adj ? 6 : 6) : wps <= 7 ? (adj ? 4 : 5) : (adj ? 2 : 3);
 }
 template <bool ADJ>
 __host__ __device__ constexpr size_t occ_lds(int wps) {

@@ -569,7 +569,7 @@ static int build_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
     }
     cnt = 2 * (int64_t)(*hsplits);
     total += cnt;
-    if (total >= (1 << 30)) return fail(TREVR_E_CAPACITY, "more than 2^30 tree cells");
+    if (total >= (1 << 30) - 1) return fail(TREVR_E_CAPACITY, "more than 2^30 - 2 tree cells");
     ++depth;
   }
   const int nlev = (int)t->level_cnt.size();

@@ -127,7 +127,7 @@ struct trevr_tree {
   int32_t max_depth = 0;
   int device = 0;
   int num_cu = 256;
-  trevr_launch launch{4, 4, 64};
+  trevr_launch launch{3, 4, 64};
 
   // transport
   trevr::DevBuf walk, trace, key, psrc;

@@ -191,7 +191,7 @@ class Tree:
         return {"n": i.n, "m": i.m, "n_boxes": i.n_boxes, "max_depth": i.max_depth,
                 "prec": i.prec, "bucket_size": i.bucket_size}
 
-    def set_launch(self, blocks_per_cu=2, waves_per_block=4, chunk=64):
+    def set_launch(self, blocks_per_cu=3, waves_per_block=4, chunk=64):
         c = _Launch(int(blocks_per_cu), int(waves_per_block), int(chunk))
         _check(lib().trevr_set_launch(self._h, ctypes.byref(c)))
 
