@@ -214,6 +214,31 @@ struct Scatter {
   int d_common;           // sink-chain depths <= this are shared by the wave
   const int32_t *path;    // the walk's current path (LDS) ...
   int live;               // ... valid at depths <= live
+  int32_t *hk;            // per-wave LDS table of other cells: keys (-1: free) ...
+  double *hv;             // ... and their sums, written out after each round
+  int hmask;              // table slots - 1 (a power of two minus one)
+  // Other cells go to the table (a few probes from a hash of the cell), so
+  // that no device-memory atomic waits among the trace's loads; a cell that
+  // finds no slot goes straight to device memory.
+  __device__ __forceinline__ void pool(int node, double v) {
+    const uint32_t h = ((uint32_t)node * 2654435761u) >> 16;
+#pragma clang loop unroll(disable)
+    for (int i = 0; i < 4; ++i) {
+      const int sl = (int)((h + (uint32_t)i) & (uint32_t)hmask);
+      int k = ((lds_i32 *)hk)[sl];
+      if (k == -1) {
+        int expect = -1;
+        __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &expect, node, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        k = expect == -1 ? node : expect;
+      }
+      if (k == node) {
+        lds_add(&hv[sl], v);
+        return;
+      }
+    }
+    gbl_add(&abar[node], v);
+  }
   __device__ __forceinline__ void operator()(int node, int slot, double alpha, double l,
                                              double ta, int ga, double tb, int gb) {
     const double v = -(g * l);
@@ -222,11 +247,12 @@ struct Scatter {
       if (dd <= live && path[dd] == node)
         lds_add(&acc_p[dd], v);
       else
-        gbl_add(&abar[node], v);
+        pool(node, v);
     } else if (slot >= 0 && slot <= d_common)
       lds_add(&acc_s[slot], v);
     else
-      gbl_add(&abar[node], v);
+      pool(node, v);
+
     if (gb >= 0) {
       const double q = r * alpha * (-tb * sel3(inv, gb));
       if (gb == 0) dtdy[0] += q; else if (gb == 1) dtdy[1] += q; else dtdy[2] += q;
@@ -531,24 +557,30 @@ __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
 // prefix (64 x i32 each).
 constexpr int kQueue = 128;  // ray queue slots per wave (a power of two)
 template <bool ADJ>
-__host__ __device__ constexpr size_t lds_per_wave(int ks, int kr) {
-  return (size_t)64 * 8 + (ADJ ? 2 * 64 * 8 : 0) + (size_t)kr * 64 * 12 + kQueue * 5 +
-         (ADJ ? 0 : 2 * 64 * 4) + (size_t)ks * 64 * 4 + 2 * 64 * 4;
+__host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
+  return (size_t)64 * 8 + (ADJ ? 2 * 64 * 8 + (size_t)hn * 12 : 0) + (size_t)kr * 64 * 12 +
+         kQueue * 5 + (ADJ ? 0 : 2 * 64 * 4) + (size_t)ks * 64 * 4 + 2 * 64 * 4;
 }
 
 // Window and stack depth per occupancy variant (waves per SIMD), chosen so
 // that that many waves fit the CU's 160 KiB of LDS.
 __host__ __device__ constexpr int occ_ks(int wps, bool adj) {
-  return wps <= 3 ? (adj ? 12 : 14)
+  return wps <= 3 ? (adj ? 6 : 14)
                   : wps == 4 ? (adj ? 5 : 7)
                              : wps == 5 ? (adj ? 3 : 5) : wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
 }
 __host__ __device__ constexpr int occ_kr(int wps, bool adj) {
-  return wps <= 3 ? 10 : wps == 4 ? 8 : wps == 5 ? (adj ? 6 : 6) : wps <= 7 ? (adj ? 4 : 5) : (adj ? 2 : 3);
+  return wps <= 3 ? (adj ? 8 : 10)
+                  : wps == 4 ? (adj ? 6 : 8)
+                             : wps == 5 ? (adj ? 5 : 6) : wps <= 7 ? (adj ? 3 : 5) : (adj ? 1 : 3);
+}
+// adjoint: slots of the per-wave table of d loss / d alpha (a power of two)
+__host__ __device__ constexpr int occ_hn(int wps, bool adj) {
+  return !adj ? 0 : wps <= 3 ? 256 : wps == 4 ? 128 : 64;
 }
 template <bool ADJ>
 __host__ __device__ constexpr size_t occ_lds(int wps) {
-  return lds_per_wave<ADJ>(occ_ks(wps, ADJ), occ_kr(wps, ADJ));
+  return lds_per_wave<ADJ>(occ_ks(wps, ADJ), occ_kr(wps, ADJ), occ_hn(wps, ADJ));
 }
 constexpr size_t kLdsPerCu = 160 * 1024;
 static_assert(occ_lds<false>(3) * 12 <= kLdsPerCu && occ_lds<true>(3) * 12 <= kLdsPerCu, "");
@@ -576,18 +608,21 @@ constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source,
 // owning sink's context by lane shuffles; each owner adds its results in
 // queue order, so a sink's sum is in its own walk order whatever the other
 // sinks of the wave are.
-template <typename T, bool ADJ, int KS, int KR>
+template <typename T, bool ADJ, int KS, int KR, int HN>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const uint64_t below = (1ull << lane) - 1;  // the lanes below this one
-  unsigned char *base = smem + wv * lds_per_wave<ADJ>(KS, KR);
+  unsigned char *base = smem + wv * lds_per_wave<ADJ>(KS, KR, HN);
   uint64_t *s_open = reinterpret_cast<uint64_t *>(base);
   base += 64 * 8;
   double *acc_s = reinterpret_cast<double *>(base);
   double *acc_p = acc_s + 64;
-  if (ADJ) base += 2 * 64 * 8;
+  double *s_hv = acc_p + 64;  // adjoint table: sums, then keys
+  if (ADJ) base += 2 * 64 * 8 + HN * 8;
+  int32_t *s_hk = reinterpret_cast<int32_t *>(base);
+  if (ADJ) base += HN * 4;
   double *s_stb = reinterpret_cast<double *>(base);
   base += KR * 64 * 8;
   int32_t *s_stn = reinterpret_cast<int32_t *>(base);
@@ -604,6 +639,10 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   if (ADJ) {
     acc_s[lane] = 0.0;
     acc_p[lane] = 0.0;
+    for (int j = lane; j < HN; j += 64) {
+      s_hk[j] = -1;
+      s_hv[j] = 0.0;
+    }
   }
   RayCtx c;
   c.tau_ref = a.tau_ref;
@@ -779,6 +818,9 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           sc.d_common = d_common;
           sc.path = s_path;
           sc.live = live;
+          sc.hk = s_hk;
+          sc.hv = s_hv;
+          sc.hmask = HN - 1;
           trace_pieces<T>(a, C, keyC, depthC, tk, c, sc);
           if (psrc) {  // d loss / d L_j of the particle source
             gbl_add(&a.direct[id], sc.g / (double)L);
@@ -789,6 +831,18 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
             gbl_add(&a.xbar[2 * a.m + C], sc.g * (-2.0 * c.d[2] / c.r2 - sc.dtdy[2]));
           }
         }
+      }
+      if (ADJ) {  // write the round's table out to device memory and clear it
+        wave_sync();
+        for (int j = lane; j < HN; j += 64) {
+          const int key = s_hk[j];
+          if (key != -1) {
+            gbl_add(&a.abar[key], s_hv[j]);
+            s_hk[j] = -1;
+            s_hv[j] = 0.0;
+          }
+        }
+        wave_sync();
       }
       if (!ADJ) {  // each owner adds its rays' fluxes in queue order
         for (int j = 0; j < nb; ++j) {
@@ -931,27 +985,27 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ), occ_hn(3, ADJ)>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ), occ_hn(4, ADJ)>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ), occ_hn(5, ADJ)>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_walk6(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ), occ_hn(6, ADJ)>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_walk8(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ), occ_hn(8, ADJ)>(a);
 }
 
 __global__ void k_zero_i32(int32_t *p, int n) {
