@@ -203,10 +203,13 @@ struct TauSum {
 };
 
 // Adjoint policy: d loss / d alpha_cell += -g l, and d tau / d y gets
-// r alpha (d tb/dy - d ta/dy) with d t/d y_a = -t / d_a for a plane crossing.
+// r alpha (d tb/dy - d ta/dy) with d t/d y_a = -t / d_a for a plane crossing:
+// per axis a the sums of alpha t over the crossings of that axis (entries
+// minus exits) are kept in u, and d tau / d y_a += r u_a / d_a once per ray.
 struct Scatter {
   double g;        // weight * flux contribution of the ray
   double dtdy[3];  // d tau / d y
+  double u[3];     // per axis: sum of alpha t over entry crossings minus exit crossings
   double r;
   double inv[3];
   double *abar;
@@ -217,27 +220,22 @@ struct Scatter {
   int32_t *hk;            // per-wave LDS table of other cells: keys (-1: free) ...
   double *hv;             // ... and their sums, written out after each round
   int hmask;              // table slots - 1 (a power of two minus one)
-  // Other cells go to the table (a few probes from a hash of the cell), so
-  // that no device-memory atomic waits among the trace's loads; a cell that
-  // finds no slot goes straight to device memory.
+  // Other cells go to the table (the slot a hash of the cell picks), so
+  // that no device-memory atomic waits among the trace's loads; a cell whose
+  // slot holds another cell goes straight to device memory.
   __device__ __forceinline__ void pool(int node, double v) {
-    const uint32_t h = ((uint32_t)node * 2654435761u) >> 16;
-#pragma clang loop unroll(disable)
-    for (int i = 0; i < 4; ++i) {
-      const int sl = (int)((h + (uint32_t)i) & (uint32_t)hmask);
-      int k = ((lds_i32 *)hk)[sl];
-      if (k == -1) {
-        int expect = -1;
-        __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &expect, node, __ATOMIC_RELAXED,
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        k = expect == -1 ? node : expect;
-      }
-      if (k == node) {
-        lds_add(&hv[sl], v);
-        return;
-      }
+    const int sl = (int)((((uint32_t)node * 2654435761u) >> 16) & (uint32_t)hmask);
+    int k = ((lds_i32 *)hk)[sl];
+    if (k == -1) {
+      int expect = -1;
+      __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &expect, node, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      k = expect == -1 ? node : expect;
     }
-    gbl_add(&abar[node], v);
+    if (k == node)
+      lds_add(&hv[sl], v);
+    else
+      gbl_add(&abar[node], v);
   }
   __device__ __forceinline__ void operator()(int node, int slot, double alpha, double l,
                                              double ta, int ga, double tb, int gb) {
@@ -253,14 +251,10 @@ struct Scatter {
     else
       pool(node, v);
 
-    if (gb >= 0) {
-      const double q = r * alpha * (-tb * sel3(inv, gb));
-      if (gb == 0) dtdy[0] += q; else if (gb == 1) dtdy[1] += q; else dtdy[2] += q;
-    }
-    if (ga >= 0) {
-      const double q = r * alpha * (-ta * sel3(inv, ga));
-      if (ga == 0) dtdy[0] -= q; else if (ga == 1) dtdy[1] -= q; else dtdy[2] -= q;
-    }
+    const double xb = alpha * tb, xa = alpha * ta;
+    u[0] += (ga == 0 ? xa : 0.0) - (gb == 0 ? xb : 0.0);
+    u[1] += (ga == 1 ? xa : 0.0) - (gb == 1 ? xb : 0.0);
+    u[2] += (ga == 2 ? xa : 0.0) - (gb == 2 ? xb : 0.0);
   }
 };
 
@@ -821,7 +815,9 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           sc.hk = s_hk;
           sc.hv = s_hv;
           sc.hmask = HN - 1;
+          sc.u[0] = sc.u[1] = sc.u[2] = 0.0;
           trace_pieces<T>(a, C, keyC, depthC, tk, c, sc);
+          for (int q3 = 0; q3 < 3; ++q3) sc.dtdy[q3] += c.r * c.inv[q3] * sc.u[q3];
           if (psrc) {  // d loss / d L_j of the particle source
             gbl_add(&a.direct[id], sc.g / (double)L);
           } else {  // d loss / d L_C and d loss / d x_L of the cell
