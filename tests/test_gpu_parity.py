@@ -166,6 +166,43 @@ def test_flux_limits_fp64(theta, tau_ref):
     _parity(w, theta, tau_ref)
 
 
+# Launch shapes selecting each register-budget variant of the walk kernel
+# (waves per SIMD 3, 4, 5, 6, 8); their refinement stacks hold 10..2 entries
+# in LDS, so full refinement (tau_ref < 0) runs past them into the private
+# spill and, on the smallest, refines chain pieces at once instead of
+# deferring them.
+VARIANT_LAUNCHES = [(3, 4, 64), (4, 4, 64), (5, 4, 64), (6, 4, 64), (8, 4, 64)]
+
+
+@pytest.mark.parametrize("launch", VARIANT_LAUNCHES)
+def test_flux_every_kernel_variant_full_refinement_fp64(launch):
+    _note("flux variant %s, full refinement, fp64" % (launch,))
+    w = small_lognormal(1 << 13, 300, 8.0, 21, prec="f64")
+    tg = gpu_tree(w)
+    tg.set_launch(*launch)
+    Fg, Cg = tg.flux(0.75, -1.0, counters=True)
+    to = oracle_tree(w)
+    Fo, Co = to.flux(0.75, -1.0, nthreads=NTHREADS)
+    assert_flux_close(Fg.cpu().numpy(), Fo, "f64", ("variant", launch))
+    assert np.array_equal(Cg.cpu().numpy().astype(np.int64), Co)
+
+
+@pytest.mark.parametrize("launch", [(3, 4, 64), (8, 4, 64)])
+def test_adjoint_kernel_variants_full_refinement_fp64(launch):
+    _note("adjoint variant %s, full refinement, fp64" % (launch,))
+    w = small_lognormal(1 << 12, 200, 8.0, 22, prec="f64")
+    gF = np.random.default_rng(23).standard_normal(w["pos"].shape[0])
+    tg = gpu_tree(w)
+    tg.set_launch(*launch)
+    gr, gk, gl = tg.adjoint(0.75, -1.0, torch.as_tensor(gF, dtype=torch.float64, device="cuda"))
+    orr, ok, ol = oracle_tree(w).adjoint(0.75, -1.0, gF, nthreads=NTHREADS)
+    for name, g, o in (("rho", gr, orr), ("kappa", gk, ok), ("lum", gl, ol)):
+        g = g.cpu().numpy()
+        scale = np.max(np.abs(o))
+        err = np.abs(g - o) / (np.abs(o) + 1e-6 * scale)
+        assert err.max() <= 1e-10, (name, launch, float(err.max()))
+
+
 def test_flux_sink_subset_and_order():
     _note("flux sink subset")
     w = small_lognormal(40000, 2000, 5.0, 13)
