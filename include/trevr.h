@@ -116,8 +116,9 @@ void trevr_tree_destroy(trevr_tree *tree);
  *    distance from it to the furthest vertex (Sec. 2.2.1).
  * The tree copies what it needs from the particle arrays.  Waits on
  * `stream`.  Errors: TREVR_E_ARG, _RANGE, _NONFINITE, _VALUE, _CAPACITY
- * (n >= 2^31 particles, or more than 2^30 - 2 cells), _HIP; on error the
- * handle holds no tree. */
+ * (n >= 2^31 particles, more than 2^30 - 2 cells, or trace records beyond
+ * 4 GiB: more than 2^28 cells in binary32, 2^27 in binary64), _HIP; on error
+ * the handle holds no tree. */
 int trevr_build_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream);
 
 int trevr_tree_info(const trevr_tree *tree, trevr_tree_info_t *info);

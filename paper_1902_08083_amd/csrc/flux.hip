@@ -74,10 +74,12 @@ __device__ __forceinline__ double pick3(int a, double v0, double v1, double v2) 
 }
 #define sel3(v, a) pick3((a), (v)[0], (v)[1], (v)[2])
 
-// A trace record as one vector load (16 B in binary32, 32 B in binary64):
-// tr_fetch issues it, tr_open waits for it and unpacks the fields.  The
-// loaded words are pinned by an empty asm statement; otherwise the compiler
-// splits the load into dependent loads of the fields each branch uses.
+// A trace record as one 16-byte buffer load (two in binary64): tr_fetch
+// issues it, tr_open unpacks the fields.  The buffer resource spans the
+// record array from its base with 32-bit byte offsets (the build keeps the
+// records within 4 GiB); a buffer-load intrinsic is never split into
+// dependent loads of the fields that each branch uses, and its offset costs
+// one shift instead of 64-bit address arithmetic.
 template <typename T>
 struct TrRaw;
 template <>
@@ -88,15 +90,22 @@ template <>
 struct TrRaw<double> {
   uint4 u, w;
 };
+// Raw buffer (stride 0), no range limit, gfx9 data format word.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tr_rsrc(const void *TR) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(TR), (short)0, -1, 0x00020000);
+}
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
 __device__ __forceinline__ TrRaw<float> tr_fetch(const TraceRecT<float> *TR, int i) {
-  return TrRaw<float>{*reinterpret_cast<const uint4 *>(TR + i)};
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(tr_rsrc(TR), (unsigned)i * 16u, 0, 0);
+  return TrRaw<float>{make_uint4(v.x, v.y, v.z, v.w)};
 }
 __device__ __forceinline__ TrRaw<double> tr_fetch(const TraceRecT<double> *TR, int i) {
-  return TrRaw<double>{reinterpret_cast<const uint4 *>(TR + i)[0],
-                       reinterpret_cast<const uint4 *>(TR + i)[1]};
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(tr_rsrc(TR), (unsigned)i * 32u, 0, 0);
+  const u32x4 w =
+      __builtin_amdgcn_raw_buffer_load_b128(tr_rsrc(TR), (unsigned)i * 32u + 16u, 0, 0);
+  return TrRaw<double>{make_uint4(v.x, v.y, v.z, v.w), make_uint4(w.x, w.y, w.z, w.w)};
 }
 __device__ __forceinline__ TraceRecT<float> tr_open(TrRaw<float> v) {
-  asm volatile("" : "+v"(v.u.x), "+v"(v.u.y), "+v"(v.u.z), "+v"(v.u.w));
   TraceRecT<float> r;
   r.split = __uint_as_float(v.u.x);
   r.alpha = __uint_as_float(v.u.y);
@@ -105,8 +114,6 @@ __device__ __forceinline__ TraceRecT<float> tr_open(TrRaw<float> v) {
   return r;
 }
 __device__ __forceinline__ TraceRecT<double> tr_open(TrRaw<double> v) {
-  asm volatile("" : "+v"(v.u.x), "+v"(v.u.y), "+v"(v.u.z), "+v"(v.u.w));
-  asm volatile("" : "+v"(v.w.x), "+v"(v.w.y), "+v"(v.w.z));
   TraceRecT<double> r;
   r.split = __hiloint2double((int)v.u.y, (int)v.u.x);
   r.alpha = __hiloint2double((int)v.u.w, (int)v.u.z);
@@ -144,6 +151,7 @@ struct RayCtx {
   double r, r2;
   double tau_ref;
   int n_seg, n_trace;
+  int pm;  // per axis a: bit a set if d_a == 0, bit a + 4 if d_a < 0
   // the lane's refinement stack in LDS (stride 64): kr entries, deeper ones
   // spill to private memory
   int32_t *stn;  // pending cell | (tag + 1) << 30
@@ -275,11 +283,13 @@ struct Scatter {
 // refined after X, those below are left for a later call.
 //
 // Two forms of one step, with identical arithmetic and emit order.  The
-// branching form takes either the split or the emit-and-pop path; the light
-// form evaluates the split on every lane, writes the free slot above the
-// stack top and reads the two top slots unconditionally, and selects the next
-// state.  Measured on this hardware, the light form is the faster one in the
-// adjoint kernel (both passes), the branching form in the forward kernel.
+// branching form takes either the split or the emit-and-pop path and leaves
+// the loop at one place, after the next record is requested (a finished lane
+// requests its last cell again); the light form evaluates the split on every
+// lane, writes the free slot above the stack top and reads the two top slots
+// unconditionally, and selects the next state.  Measured on this hardware,
+// the light form is the faster one in the adjoint kernel (both passes), the
+// branching form in the forward kernel.
 template <typename T, typename Emit>
 __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
                                double ta, int ga, double tb, int gb, RayCtx &c, StackSpill &ovf,
@@ -288,23 +298,20 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
   int cur = X;
   double cta = ta, ctb = tb;
   int cga = ga, cgb = gb;
-  // The next cell's record is requested before the current piece is
-  // emitted: an emit that writes device memory then does not delay it.
   TrRaw<T> raw = tr_fetch(TR, cur);
-  for (;;) {
+  bool go = true;
+  do {
     const TraceRecT<T> rec = tr_open(raw);
     const double l = c.r * (ctb - cta);
     c.n_trace++;
     const int right = rax_right(rec.right_ax);
-    // both operands evaluated: the whole record is used on every step
     const bool split_it = (right != 0) & ((double)rec.dalpha * l > c.tau_ref);
+    int ncur = cur;
     if (!split_it) {
       if (l > 0) c.n_seg++;
-      const int node = cur;
-      const double pa = cta, pb = ctb;
-      const int pga = cga, pgb = cgb;
-      const bool more = sp > base;
-      if (more) {
+      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb);
+      go = sp > base;
+      if (go) {
         int nd, tg;
         double tt;
         stack_pop(c, ovf, --sp, nd, tg, tt);
@@ -316,47 +323,39 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
           cta = ctb;
           cga = cgb;
         }
-        cur = nd;
+        ncur = nd;
         ctb = tt;
         cgb = tg;
-        raw = tr_fetch(TR, cur);
       }
-      emit(node, node == X ? top_slot : -1, (double)rec.alpha, l, pa, pga, pb, pgb);
-      if (!more) return;
-      continue;
-    }
-    const int ax = rax_axis(rec.right_ax);
-    const double s = (double)rec.split;
-    const double dax = sel3(c.d, ax), xax = sel3(c.xi, ax);
-    const double ts = (s - xax) * sel3(c.inv, ax);
-    const bool par = dax == 0.0;                   // parallel to the plane: one side only
-    const bool up = par ? xax >= s : dax < 0.0;    // the near half is the upper child
-    const int nearc = up ? right : cur + 1;
-    const int farc = up ? cur + 1 : right;
-    const bool cut_b = !par && ts < ctb;           // the plane ends the near part
-    const bool cut_a = !par && ts > cta;           // the plane starts the far part
-    const double t1 = cut_b ? ts : ctb;
-    const int g1 = cut_b ? ax : cgb;
-    const double t0 = cut_a ? ts : cta;
-    const int g0 = cut_a ? ax : cga;
-    const bool has_near = par || t1 > cta;
-    const bool has_far = !par && ctb > t0;
-    if (has_near && has_far) stack_push(c, ovf, sp++, farc, cgb, ctb);
-    if (has_near) {
-      cur = nearc;
-      ctb = t1;
-      cgb = g1;
-    } else if (has_far) {
-      cur = farc;
-      cta = t0;
-      cga = g0;
     } else {
-      return;  // empty interval (only at the top call)
+      const int ax = rax_axis(rec.right_ax);
+      const double s = (double)rec.split;
+      const double xax = sel3(c.xi, ax);
+      const double ts = (s - xax) * sel3(c.inv, ax);
+      const bool par = (c.pm >> ax) & 1;                        // parallel to the plane
+      const bool up = par ? xax >= s : (c.pm >> (ax + 4)) & 1;  // near half is the upper child
+      const int nearc = up ? right : cur + 1;
+      const int farc = up ? cur + 1 : right;
+      const bool cut_b = !par && ts < ctb;  // the plane ends the near part
+      const bool cut_a = !par && ts > cta;  // the plane starts the far part
+      const double t1 = cut_b ? ts : ctb;
+      const int g1 = cut_b ? ax : cgb;
+      const double t0 = cut_a ? ts : cta;
+      const int g0 = cut_a ? ax : cga;
+      const bool has_near = par || t1 > cta;
+      const bool has_far = !par && ctb > t0;
+      if (has_near && has_far) stack_push(c, ovf, sp++, farc, cgb, ctb);
+      go = has_near || has_far;  // neither: an empty interval (only at the top call)
+      ncur = has_near ? nearc : farc;
+      cta = has_near ? cta : t0;
+      cga = has_near ? cga : g0;
+      ctb = has_near ? t1 : ctb;
+      cgb = has_near ? g1 : cgb;
     }
+    cur = ncur;
     raw = tr_fetch(TR, cur);
-  }
+  } while (go);
 }
-
 template <typename T, typename Emit>
 __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, double ta,
                              int ga, double tb, int gb, RayCtx &c, StackSpill &ovf, int sp0,
@@ -375,10 +374,10 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
     // Every lane evaluates the split; the next state is selected below.
     const int ax = rax_axis(rec.right_ax);
     const double s = (double)rec.split;
-    const double dax = sel3(c.d, ax), xax = sel3(c.xi, ax);
+    const double xax = sel3(c.xi, ax);
     const double ts = (s - xax) * sel3(c.inv, ax);
-    const bool par = dax == 0.0;                   // parallel to the plane: one side only
-    const bool up = par ? xax >= s : dax < 0.0;    // the near half is the upper child
+    const bool par = (c.pm >> ax) & 1;                        // parallel to the plane
+    const bool up = par ? xax >= s : (c.pm >> (ax + 4)) & 1;  // near half is the upper child
     const bool cut_b = !par && ts < ctb;           // the plane ends the near part
     const bool cut_a = !par && ts > cta;           // the plane starts the far part
     const double t1 = cut_b ? ts : ctb;
@@ -531,6 +530,8 @@ __device__ __forceinline__ void ray_setup(RayCtx &c, double y0, double y1, doubl
   for (int q = 0; q < 3; ++q) c.inv[q] = c.d[q] != 0.0 ? 1.0 / c.d[q] : 0.0;
   c.r2 = (c.d[0] * c.d[0] + c.d[1] * c.d[1]) + c.d[2] * c.d[2];
   c.r = sqrt(c.r2);
+  c.pm = 0;
+  for (int q = 0; q < 3; ++q) c.pm |= (c.d[q] == 0.0 ? 1 << q : 0) | (c.d[q] < 0.0 ? 16 << q : 0);
 }
 
 // Reverse ray trace from the sink (t = 0) to the source in cell C (t = 1),

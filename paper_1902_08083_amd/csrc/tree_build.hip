@@ -570,6 +570,10 @@ static int build_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
     cnt = 2 * (int64_t)(*hsplits);
     total += cnt;
     if (total >= (1 << 30) - 1) return fail(TREVR_E_CAPACITY, "more than 2^30 - 2 tree cells");
+    // the walk addresses trace records with 32-bit byte offsets
+    if ((uint64_t)total * sizeof(TraceRecT<T>) > ((uint64_t)1 << 32))
+      return fail(TREVR_E_CAPACITY,
+                  "trace records beyond 4 GiB (2^28 cells in binary32, 2^27 in binary64)");
     ++depth;
   }
   const int nlev = (int)t->level_cnt.size();
