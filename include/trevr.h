@@ -74,9 +74,11 @@ typedef struct {
   int32_t bucket_size;         /* N_B >= 1: most particles per leaf (Sec. 2.2) */
 } trevr_particles;
 
-/* Launch knobs of the flux and adjoint kernels (set by the autotuner; a new
- * tree starts at {3, 4, 64}).  Waves per SIMD, ceil(blocks_per_cu x
- * min(waves_per_block, 4) / 4), pick the kernel's register budget. */
+/* Launch knobs of the flux kernel and, separately, of the adjoint kernel
+ * (set by the autotuner; a new tree starts at {4, 4, 64} for the flux and
+ * {3, 4, 64} for the adjoint, the faster shapes measured on MI355X).  Waves
+ * per SIMD, ceil(blocks_per_cu x min(waves_per_block, 4) / 4), pick the
+ * kernel's register budget. */
 typedef struct {
   int32_t blocks_per_cu;   /* persistent workgroups per compute unit, 1..32   */
   int32_t waves_per_block; /* 1..16 accepted; at most 4 wavefronts are used   */
@@ -162,9 +164,14 @@ int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_r
                                void *grad_rho, void *grad_kappa, void *grad_lum,
                                hipStream_t stream);
 
-/* Launch knobs for later flux / adjoint calls on this tree (autotuning). */
+/* Launch knobs for later flux calls on this tree (autotuning).  Errors:
+ * TREVR_E_ARG (NULL, or a field out of the ranges trevr_launch states). */
 int trevr_set_launch(trevr_tree *tree, const trevr_launch *cfg);
 int trevr_get_launch(const trevr_tree *tree, trevr_launch *cfg);
+
+/* The same for later adjoint calls on this tree. */
+int trevr_set_adjoint_launch(trevr_tree *tree, const trevr_launch *cfg);
+int trevr_get_adjoint_launch(const trevr_tree *tree, trevr_launch *cfg);
 
 /* Copy the tree to host memory for inspection (all host pointers, any may be
  * NULL):

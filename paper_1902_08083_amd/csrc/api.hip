@@ -159,7 +159,7 @@ int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_r
                              grad_kappa, grad_lum, stream);
 }
 
-int trevr_set_launch(trevr_tree *tree, const trevr_launch *cfg) {
+static int set_launch_checked(trevr_tree *tree, const trevr_launch *cfg, trevr_launch &dst) {
   if (!tree || !cfg) return trevr::fail(TREVR_E_ARG, "NULL argument");
   if (cfg->blocks_per_cu < 1 || cfg->blocks_per_cu > 32)
     return trevr::fail(TREVR_E_ARG, "blocks_per_cu must be 1..32");
@@ -167,13 +167,29 @@ int trevr_set_launch(trevr_tree *tree, const trevr_launch *cfg) {
     return trevr::fail(TREVR_E_ARG, "waves_per_block must be 1..16");
   if (cfg->chunk < 64 || cfg->chunk % 64 != 0 || cfg->chunk > 4096)
     return trevr::fail(TREVR_E_ARG, "chunk must be a multiple of 64 in 64..4096");
-  tree->launch = *cfg;
+  dst = *cfg;
   return TREVR_OK;
+}
+
+int trevr_set_launch(trevr_tree *tree, const trevr_launch *cfg) {
+  return tree ? set_launch_checked(tree, cfg, tree->launch)
+              : trevr::fail(TREVR_E_ARG, "NULL argument");
 }
 
 int trevr_get_launch(const trevr_tree *tree, trevr_launch *cfg) {
   if (!tree || !cfg) return trevr::fail(TREVR_E_ARG, "NULL argument");
   *cfg = tree->launch;
+  return TREVR_OK;
+}
+
+int trevr_set_adjoint_launch(trevr_tree *tree, const trevr_launch *cfg) {
+  return tree ? set_launch_checked(tree, cfg, tree->launch_adj)
+              : trevr::fail(TREVR_E_ARG, "NULL argument");
+}
+
+int trevr_get_adjoint_launch(const trevr_tree *tree, trevr_launch *cfg) {
+  if (!tree || !cfg) return trevr::fail(TREVR_E_ARG, "NULL argument");
+  *cfg = tree->launch_adj;
   return TREVR_OK;
 }
 

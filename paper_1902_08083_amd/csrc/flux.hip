@@ -1193,7 +1193,7 @@ __global__ void k_adj_particles(int64_t n, int64_t m, const int32_t *perm, const
 
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-template <typename T>
+template <typename T, bool ADJ>
 static FluxArgs<T> make_args(const trevr_tree *t, double theta, double tau_ref,
                              const int32_t *sinks, int64_t n_sinks) {
   FluxArgs<T> a{};
@@ -1211,7 +1211,7 @@ static FluxArgs<T> make_args(const trevr_tree *t, double theta, double tau_ref,
   a.sinks = sinks;
   a.n_sinks = n_sinks;
   a.n = t->n;
-  a.group = t->launch.chunk / 64;
+  a.group = (ADJ ? t->launch_adj : t->launch).chunk / 64;
   a.n_chunks = (int32_t)((n_sinks + 64 * a.group - 1) / (64 * a.group));
   a.theta2 = theta * theta;
   a.tau_ref = tau_ref;
@@ -1223,12 +1223,13 @@ static FluxArgs<T> make_args(const trevr_tree *t, double theta, double tau_ref,
 template <typename T, bool ADJ>
 static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s) {
   k_zero_i32<<<1, 64, 0, s>>>(a.queue, kXcd);
-  const int waves = t->launch.waves_per_block > 4 ? 4 : t->launch.waves_per_block;
+  const trevr_launch &L = ADJ ? t->launch_adj : t->launch;
+  const int waves = L.waves_per_block > 4 ? 4 : L.waves_per_block;
   const int threads = 64 * waves;
-  int64_t blocks = (int64_t)t->launch.blocks_per_cu * t->num_cu;
+  int64_t blocks = (int64_t)L.blocks_per_cu * t->num_cu;
   const int64_t need = (a.n_chunks + waves - 1) / waves;
   if (blocks > need) blocks = need;
-  const int per_simd = (t->launch.blocks_per_cu * waves + 3) / 4;
+  const int per_simd = (L.blocks_per_cu * waves + 3) / 4;
   const int wps = per_simd >= 8 ? 8 : per_simd >= 6 ? 6 : per_simd == 5 ? 5 : per_simd == 4 ? 4 : 3;
   // waves per workgroup <= 4 x wps, so the workgroup fits the CU's LDS
   const size_t shmem = (size_t)waves * occ_lds<ADJ>(wps);
@@ -1251,7 +1252,7 @@ template <typename T>
 static int flux_typed(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                       int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s) {
   if (n_sinks == 0) return TREVR_OK;
-  FluxArgs<T> a = make_args<T>(t, theta, tau_ref, sinks, n_sinks);
+  FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
   a.flux = static_cast<T *>(flux);
   a.counters = counters;
   return launch_walk<T, false>(t, a, s);
@@ -1277,7 +1278,7 @@ static int adjoint_typed(trevr_tree *t, double theta, double tau_ref, const int3
   k_zero_f64<<<nblk(5 * m), 256, 0, s>>>(abar, 5 * m);
   if (n > 0) k_zero_f64<<<nblk(n), 256, 0, s>>>(direct, n);
   if (n_sinks > 0) {
-    FluxArgs<T> a = make_args<T>(t, theta, tau_ref, sinks, n_sinks);
+    FluxArgs<T> a = make_args<T, true>(t, theta, tau_ref, sinks, n_sinks);
     a.grad_flux = static_cast<const T *>(grad_flux);
     a.abar = abar;
     a.lbar = lbar;

@@ -127,7 +127,8 @@ struct trevr_tree {
   int32_t max_depth = 0;
   int device = 0;
   int num_cu = 256;
-  trevr_launch launch{3, 4, 64};
+  trevr_launch launch{4, 4, 64};      // flux kernel
+  trevr_launch launch_adj{3, 4, 64};  // adjoint kernel
 
   // transport
   trevr::DevBuf walk, trace, key, psrc;

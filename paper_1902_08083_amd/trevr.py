@@ -63,7 +63,8 @@ _lib = None
 EXPORTED = (
     "trevr_status_string", "trevr_last_error", "trevr_tree_create", "trevr_tree_destroy",
     "trevr_build_tree", "trevr_tree_info", "trevr_compute_flux", "trevr_compute_flux_adjoint",
-    "trevr_set_launch", "trevr_get_launch", "trevr_export_tree",
+    "trevr_set_launch", "trevr_get_launch", "trevr_set_adjoint_launch",
+    "trevr_get_adjoint_launch", "trevr_export_tree",
 )
 
 
@@ -97,6 +98,10 @@ def lib():
     L.trevr_set_launch.argtypes = [P, ctypes.POINTER(_Launch)]
     L.trevr_get_launch.restype = I
     L.trevr_get_launch.argtypes = [P, ctypes.POINTER(_Launch)]
+    L.trevr_set_adjoint_launch.restype = I
+    L.trevr_set_adjoint_launch.argtypes = [P, ctypes.POINTER(_Launch)]
+    L.trevr_get_adjoint_launch.restype = I
+    L.trevr_get_adjoint_launch.argtypes = [P, ctypes.POINTER(_Launch)]
     L.trevr_export_tree.restype = I
     L.trevr_export_tree.argtypes = [P, P, P, P, P, P, P]
     _lib = L
@@ -191,13 +196,16 @@ class Tree:
         return {"n": i.n, "m": i.m, "n_boxes": i.n_boxes, "max_depth": i.max_depth,
                 "prec": i.prec, "bucket_size": i.bucket_size}
 
-    def set_launch(self, blocks_per_cu=3, waves_per_block=4, chunk=64):
+    def set_launch(self, blocks_per_cu=4, waves_per_block=4, chunk=64, adjoint=False):
+        """Launch shape of later flux calls, or of adjoint calls if `adjoint`."""
         c = _Launch(int(blocks_per_cu), int(waves_per_block), int(chunk))
-        _check(lib().trevr_set_launch(self._h, ctypes.byref(c)))
+        fn = lib().trevr_set_adjoint_launch if adjoint else lib().trevr_set_launch
+        _check(fn(self._h, ctypes.byref(c)))
 
-    def get_launch(self):
+    def get_launch(self, adjoint=False):
         c = _Launch()
-        _check(lib().trevr_get_launch(self._h, ctypes.byref(c)))
+        fn = lib().trevr_get_adjoint_launch if adjoint else lib().trevr_get_launch
+        _check(fn(self._h, ctypes.byref(c)))
         return {"blocks_per_cu": c.blocks_per_cu, "waves_per_block": c.waves_per_block,
                 "chunk": c.chunk}
 

@@ -187,13 +187,15 @@ def test_flux_every_kernel_variant_full_refinement_fp64(launch):
     assert np.array_equal(Cg.cpu().numpy().astype(np.int64), Co)
 
 
-@pytest.mark.parametrize("launch", [(3, 4, 64), (8, 4, 64)])
+@pytest.mark.parametrize("launch", [(3, 4, 64), (4, 4, 64), (8, 4, 64)])
 def test_adjoint_kernel_variants_full_refinement_fp64(launch):
     _note("adjoint variant %s, full refinement, fp64" % (launch,))
     w = small_lognormal(1 << 12, 200, 8.0, 22, prec="f64")
     gF = np.random.default_rng(23).standard_normal(w["pos"].shape[0])
     tg = gpu_tree(w)
-    tg.set_launch(*launch)
+    tg.set_launch(*launch, adjoint=True)
+    assert tg.get_launch(adjoint=True) == dict(zip(("blocks_per_cu", "waves_per_block", "chunk"),
+                                                   launch))
     gr, gk, gl = tg.adjoint(0.75, -1.0, torch.as_tensor(gF, dtype=torch.float64, device="cuda"))
     orr, ok, ol = oracle_tree(w).adjoint(0.75, -1.0, gF, nthreads=NTHREADS)
     for name, g, o in (("rho", gr, orr), ("kappa", gk, ok), ("lum", gl, ol)):
