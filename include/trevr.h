@@ -164,6 +164,32 @@ int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_r
                                void *grad_rho, void *grad_kappa, void *grad_lum,
                                hipStream_t stream);
 
+/* The flux and its adjoint with the traversal recorded once.  The recording
+ * flux computes exactly what trevr_compute_flux computes (same arguments and
+ * errors) and in addition stores every ray's optical depth tau (binary64, in
+ * a tape owned by the tree: 8 B per ray in blocks of 64); the taped adjoint
+ * computes what trevr_compute_flux_adjoint computes for the arguments of the
+ * last recording call on this tree, taking each ray's tau from the tape, so
+ * each ray is traced once (for the scatter of Sec. 2.2.3's pieces) instead
+ * of twice.  The sink array of the recording call must be unchanged until
+ * the taped adjoint has run, and both run on one stream (or are ordered).
+ * Tape size: the last recording's block count plus a quarter, a first guess
+ * of 1024 rays per sink within half the free device memory, or what
+ * trevr_reserve_tape set.  A recording that outgrows its tape is incomplete:
+ * the taped adjoint then traces every ray twice (same result, checked on the
+ * device, no host synchronisation), and the next recording is sized from the
+ * count.  The recording call allocates (not graph-capturable).  Errors: as
+ * trevr_compute_flux; the taped adjoint: TREVR_E_STATE (no recording since
+ * the tree was built), _ARG, _HIP. */
+int trevr_compute_flux_taped(trevr_tree *tree, double theta_open, double tau_ref,
+                             const int32_t *sinks, int64_t n_sinks, void *flux,
+                             int32_t *counters, hipStream_t stream);
+int trevr_compute_flux_adjoint_taped(trevr_tree *tree, const void *grad_flux, void *grad_rho,
+                                     void *grad_kappa, void *grad_lum, hipStream_t stream);
+/* Tape capacity of later recordings in blocks (one block per round of up to
+ * 64 rays); 0 restores automatic sizing.  Errors: TREVR_E_ARG. */
+int trevr_reserve_tape(trevr_tree *tree, int64_t blocks);
+
 /* Launch knobs for later flux calls on this tree (autotuning).  Errors:
  * TREVR_E_ARG (NULL, or a field out of the ranges trevr_launch states). */
 int trevr_set_launch(trevr_tree *tree, const trevr_launch *cfg);

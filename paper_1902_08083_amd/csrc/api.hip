@@ -69,8 +69,9 @@ trevr_tree::~trevr_tree() {
                           &n_amax, &n_alpha_min, &n_alpha_max, &n_dalpha, &n_xl, &n_lc,
                           &n_lfar, &keys_in, &keys_out, &vals_in, &vals_out, &sort_tmp, &bfs,
                           &flags, &scan, &err, &box_key, &skeys, &small, &queue, &adj_node,
-                          &adj_part, &adj_heap};
+                          &adj_part, &adj_heap, &tape, &tape_next, &tape_head, &tape_ctr};
   for (auto *b : all) b->release();
+  if (tape_used_h) (void)hipHostFree(tape_used_h);
 }
 
 extern "C" {
@@ -144,6 +145,35 @@ int trevr_compute_flux(const trevr_tree *tree, double theta_open, double tau_ref
   if (rc != TREVR_OK) return rc;
   if (n_sinks > 0 && !flux) return trevr::fail(TREVR_E_ARG, "flux is NULL");
   return trevr::flux_impl(tree, theta_open, tau_ref, sinks, n_sinks, flux, counters, stream);
+}
+
+int trevr_compute_flux_taped(trevr_tree *tree, double theta_open, double tau_ref,
+                             const int32_t *sinks, int64_t n_sinks, void *flux,
+                             int32_t *counters, hipStream_t stream) {
+  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (n_sinks > 0 && !flux) return trevr::fail(TREVR_E_ARG, "flux is NULL");
+  return trevr::flux_taped_impl(tree, theta_open, tau_ref, sinks, n_sinks, flux, counters,
+                                stream);
+}
+
+int trevr_compute_flux_adjoint_taped(trevr_tree *tree, const void *grad_flux, void *grad_rho,
+                                     void *grad_kappa, void *grad_lum, hipStream_t stream) {
+  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
+  if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");
+  if (!tree->tape_ok) return trevr::fail(TREVR_E_STATE, "no recording flux call on this tree");
+  if (tree->n > 0 && (!grad_rho || !grad_kappa || !grad_lum))
+    return trevr::fail(TREVR_E_ARG, "a gradient output is NULL");
+  if (tree->tape_n_sinks > 0 && !grad_flux) return trevr::fail(TREVR_E_ARG, "grad_flux is NULL");
+  return trevr::adjoint_taped_impl(tree, grad_flux, grad_rho, grad_kappa, grad_lum, stream);
+}
+
+int trevr_reserve_tape(trevr_tree *tree, int64_t blocks) {
+  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
+  if (blocks < 0 || blocks > INT32_MAX - 65536)
+    return trevr::fail(TREVR_E_ARG, "blocks must be 0..2^31 - 65537");
+  tree->tape_reserve = blocks;
+  return TREVR_OK;
 }
 
 int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_ref,

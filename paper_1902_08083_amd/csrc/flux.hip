@@ -57,6 +57,15 @@ struct FluxArgs {
   T *flux;
   int32_t *counters;
   int32_t *queue;  // kXcd counters
+  // Tape of per-ray optical depths: one block of 64 per round, the blocks of
+  // one 64-sink set chained in round order.  Mode 1 (flux) writes it, mode 2
+  // (adjoint) reads it instead of tracing each ray for tau a first time.
+  double *tape;        // [tape_cap][64]
+  int32_t *tape_next;  // [tape_cap] the set's next block, -1 after its last
+  int32_t *tape_head;  // [64-sink sets] the set's first block, -1 if it has none
+  int32_t *tape_ctr;   // blocks taken; above tape_cap the tape is incomplete
+  int32_t tape_cap;
+  int32_t tape_mode;  // 0 none, 1 record, 2 replay
   // adjoint
   const T *__restrict__ grad_flux;
   double *abar;    // [m]  d loss / d alpha
@@ -774,6 +783,8 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   c.stn = s_stn + lane;
   c.stb = s_stb + lane;
   c.kr = KR;
+  // a replay needs every block of the recording
+  const bool replay = ADJ && a.tape_mode == 2 && *a.tape_ctr <= a.tape_cap;
   int chunk = -1, sub = a.group;
   for (;;) {
     if (sub == a.group) {
@@ -781,6 +792,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       if (chunk < 0) break;
       sub = 0;
     }
+    const int64_t set = (int64_t)chunk * a.group + sub;  // the 64-sink set
     const int64_t q = ((int64_t)chunk * a.group + sub++) * 64 + lane;
     if (__ballot(q < a.n_sinks) == 0) {
       sub = a.group;
@@ -861,6 +873,10 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     int n_open = 0, n_rays = 0, n_psrc = 0;
     int qh = 0, qn = 0;  // the queue: first entry, entries (wave-uniform)
     int live = -1;       // the walk's path is s_path[0 .. live]
+    int tprev = -1;      // recording: the set's last block
+    int tcur = -1;       // replay: the set's next block
+    if (!ADJ && a.tape_mode == 1 && lane == 0) a.tape_head[set] = -1;
+    if (replay) tcur = a.tape_head[set];
 
     // One round: the first min(qn, 64) queued rays, one per lane.
     auto round = [&]() {
@@ -893,6 +909,31 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       tk.win = s_anc + owner;
       const double wg = ADJ ? __shfl(wgt, owner) : 0.0;
       double f = 0.0;
+      int tblk = -1;     // this round's tape block
+      bool rp = false;   // tau from the tape
+      if (!ADJ && a.tape_mode == 1) {
+        int b = 0;
+        if (lane == 0) b = atomicAdd(a.tape_ctr, 1);
+        b = __builtin_amdgcn_readfirstlane(b);
+        if (b < a.tape_cap) {  // blocks come in increasing order, so a full tape stays full
+          if (lane == 0) {
+            if (tprev < 0)
+              a.tape_head[set] = b;
+            else
+              a.tape_next[tprev] = b;
+            a.tape_next[b] = -1;
+          }
+          tblk = b;
+        }
+        tprev = b;
+      }
+      double tau_rec = 0.0;
+      if (replay && tcur >= 0) {
+        rp = true;
+        tblk = tcur;
+        if (busy) tau_rec = a.tape[(int64_t)tblk * 64 + lane];
+        tcur = a.tape_next[tblk];
+      }
       if (busy) {
         const bool psrc = (e & kQParticle) != 0;
         const int id = (int)(e & ~kQParticle);
@@ -921,7 +962,11 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         c.n_trace = 0;
         ray_setup(c, (double)yx, (double)yy, (double)yz);
         std::conditional_t<ADJ, TauSumA, TauSum> ts;
-        trace_pieces<T>(a, C, keyC, depthC, tk, c, ts);
+        if (rp)
+          ts.tau = tau_rec;
+        else
+          trace_pieces<T>(a, C, keyC, depthC, tk, c, ts);
+        if (!ADJ && tblk >= 0) a.tape[(int64_t)tblk * 64 + lane] = ts.tau;
         f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
         if (!ADJ) {
           __hip_atomic_fetch_add(&s_cnt[owner], c.n_seg, __ATOMIC_RELAXED,
@@ -1248,27 +1293,88 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   return TREVR_OK;
 }
 
+template <typename T, bool ADJ>
+static void set_tape(const trevr_tree *t, FluxArgs<T> &a, int mode) {
+  a.tape_mode = mode;
+  if (mode == 0) return;
+  a.tape = t->tape.as<double>();
+  a.tape_next = t->tape_next.as<int32_t>();
+  a.tape_head = t->tape_head.as<int32_t>();
+  a.tape_ctr = t->tape_ctr.as<int32_t>();
+  a.tape_cap = (int32_t)t->tape_cap;
+}
+
 template <typename T>
 static int flux_typed(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
-                      int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s) {
+                      int64_t n_sinks, void *flux, int32_t *counters, int tape_mode,
+                      hipStream_t s) {
   if (n_sinks == 0) return TREVR_OK;
   FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
   a.flux = static_cast<T *>(flux);
   a.counters = counters;
+  set_tape<T, false>(t, a, tape_mode);
   return launch_walk<T, false>(t, a, s);
 }
 
 int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
               int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s) {
   if (t->prec == TREVR_F64)
-    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
-  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
+    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s);
+  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s);
+}
+
+// The recording flux: sizes the tape (the last recording's block count plus a
+// quarter, or a first guess of 1024 rays per sink within half the free
+// memory), then records.  A recording that outgrows its tape is left
+// incomplete; the adjoint then traces twice, and the next recording is sized
+// from this one's count, which reaches the host asynchronously.
+int flux_taped_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                    int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s) {
+  t->tape_ok = false;
+  if (!t->tape_used_h) {
+    TREVR_HIP(hipHostMalloc((void **)&t->tape_used_h, sizeof(int32_t), hipHostMallocDefault));
+    *t->tape_used_h = 0;
+  }
+  const int64_t sets = (n_sinks + 63) / 64;
+  int64_t cap = t->tape_reserve;
+  if (cap <= 0) {
+    const int64_t used = *(volatile int32_t *)t->tape_used_h;
+    if (used > 0) {
+      cap = used + used / 4 + sets;
+    } else {
+      size_t free_b = 0, total_b = 0;
+      TREVR_HIP(hipMemGetInfo(&free_b, &total_b));
+      cap = sets * 1024 + sets;
+      const int64_t fit = (int64_t)(free_b / 2 / (64 * sizeof(double) + sizeof(int32_t)));
+      if (cap > fit) cap = fit;
+    }
+  }
+  if (cap > INT32_MAX - 65536) cap = INT32_MAX - 65536;
+  if (cap < 1) cap = 1;
+  TREVR_HIP(t->tape.ensure((size_t)cap * 64 * sizeof(double)));
+  TREVR_HIP(t->tape_next.ensure((size_t)cap * sizeof(int32_t)));
+  TREVR_HIP(t->tape_head.ensure((size_t)(sets > 0 ? sets : 1) * sizeof(int32_t)));
+  TREVR_HIP(t->tape_ctr.ensure(sizeof(int32_t)));
+  t->tape_cap = cap;
+  k_zero_i32<<<1, 64, 0, s>>>(t->tape_ctr.as<int32_t>(), 1);
+  int rc = t->prec == TREVR_F64
+               ? flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 1, s)
+               : flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 1, s);
+  if (rc != TREVR_OK) return rc;
+  TREVR_HIP(hipMemcpyAsync(t->tape_used_h, t->tape_ctr.p, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+  t->tape_ok = true;
+  t->tape_theta = theta;
+  t->tape_tau_ref = tau_ref;
+  t->tape_sinks = sinks;
+  t->tape_n_sinks = n_sinks;
+  return TREVR_OK;
 }
 
 template <typename T>
 static int adjoint_typed(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                          int64_t n_sinks, const void *grad_flux, void *grad_rho,
-                         void *grad_kappa, void *grad_lum, hipStream_t s) {
+                         void *grad_kappa, void *grad_lum, int tape_mode, hipStream_t s) {
   const int64_t m = t->m, n = t->n;
   TREVR_HIP(t->adj_node.ensure(sizeof(double) * 5 * (size_t)(m > 0 ? m : 1)));
   TREVR_HIP(t->adj_part.ensure(sizeof(double) * (size_t)(n > 0 ? n : 1)));
@@ -1284,6 +1390,7 @@ static int adjoint_typed(trevr_tree *t, double theta, double tau_ref, const int3
     a.lbar = lbar;
     a.xbar = xbar;
     a.direct = direct;
+    set_tape<T, true>(t, a, tape_mode);
     int rc = launch_walk<T, true>(t, a, s);
     if (rc != TREVR_OK) return rc;
   }
@@ -1309,9 +1416,19 @@ int adjoint_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sin
                  void *grad_lum, hipStream_t s) {
   if (t->prec == TREVR_F64)
     return adjoint_typed<double>(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
-                                 grad_kappa, grad_lum, s);
+                                 grad_kappa, grad_lum, 0, s);
   return adjoint_typed<float>(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
-                              grad_kappa, grad_lum, s);
+                              grad_kappa, grad_lum, 0, s);
+}
+
+int adjoint_taped_impl(trevr_tree *t, const void *grad_flux, void *grad_rho, void *grad_kappa,
+                       void *grad_lum, hipStream_t s) {
+  if (t->prec == TREVR_F64)
+    return adjoint_typed<double>(t, t->tape_theta, t->tape_tau_ref, t->tape_sinks,
+                                 t->tape_n_sinks, grad_flux, grad_rho, grad_kappa, grad_lum, 2,
+                                 s);
+  return adjoint_typed<float>(t, t->tape_theta, t->tape_tau_ref, t->tape_sinks,
+                              t->tape_n_sinks, grad_flux, grad_rho, grad_kappa, grad_lum, 2, s);
 }
 
 }  // namespace trevr

@@ -680,6 +680,7 @@ static int build_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
 
 int build_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   t->built = false;
+  t->tape_ok = false;
   if (p->prec == TREVR_F64) return build_typed<double>(t, p, s);
   return build_typed<float>(t, p, s);
 }

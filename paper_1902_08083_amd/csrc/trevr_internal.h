@@ -150,6 +150,15 @@ struct trevr_tree {
   // work queue (one counter per XCD) and adjoint scratch
   trevr::DevBuf queue;
   trevr::DevBuf adj_node, adj_part, adj_heap;
+  // tape of per-ray optical depths from the last recording flux call
+  trevr::DevBuf tape, tape_next, tape_head, tape_ctr;
+  int64_t tape_cap = 0;             // blocks of 64
+  int64_t tape_reserve = 0;         // blocks for later recordings, 0 = sized automatically
+  int32_t *tape_used_h = nullptr;   // pinned: blocks the last recording took
+  bool tape_ok = false;             // a recording exists for the arguments below
+  double tape_theta = 0.0, tape_tau_ref = 0.0;
+  const int32_t *tape_sinks = nullptr;
+  int64_t tape_n_sinks = 0;
 
   ~trevr_tree();
 };
@@ -167,6 +176,10 @@ int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *
 int adjoint_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                  int64_t n_sinks, const void *grad_flux, void *grad_rho, void *grad_kappa,
                  void *grad_lum, hipStream_t s);
+int flux_taped_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                    int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s);
+int adjoint_taped_impl(trevr_tree *t, const void *grad_flux, void *grad_rho, void *grad_kappa,
+                       void *grad_lum, hipStream_t s);
 }  // namespace trevr
 
 #define TREVR_HIP(call)                                      \

@@ -64,7 +64,8 @@ EXPORTED = (
     "trevr_status_string", "trevr_last_error", "trevr_tree_create", "trevr_tree_destroy",
     "trevr_build_tree", "trevr_tree_info", "trevr_compute_flux", "trevr_compute_flux_adjoint",
     "trevr_set_launch", "trevr_get_launch", "trevr_set_adjoint_launch",
-    "trevr_get_adjoint_launch", "trevr_export_tree",
+    "trevr_get_adjoint_launch", "trevr_export_tree", "trevr_compute_flux_taped",
+    "trevr_compute_flux_adjoint_taped", "trevr_reserve_tape",
 )
 
 
@@ -94,6 +95,12 @@ def lib():
     L.trevr_compute_flux.argtypes = [P, D, D, P, I64, P, P, P]
     L.trevr_compute_flux_adjoint.restype = I
     L.trevr_compute_flux_adjoint.argtypes = [P, D, D, P, I64, P, P, P, P, P]
+    L.trevr_compute_flux_taped.restype = I
+    L.trevr_compute_flux_taped.argtypes = [P, D, D, P, I64, P, P, P]
+    L.trevr_compute_flux_adjoint_taped.restype = I
+    L.trevr_compute_flux_adjoint_taped.argtypes = [P, P, P, P, P, P]
+    L.trevr_reserve_tape.restype = I
+    L.trevr_reserve_tape.argtypes = [P, I64]
     L.trevr_set_launch.restype = I
     L.trevr_set_launch.argtypes = [P, ctypes.POINTER(_Launch)]
     L.trevr_get_launch.restype = I
@@ -216,13 +223,36 @@ class Tree:
         s = torch.as_tensor(sinks, device=self.device).to(torch.int32).contiguous()
         return s, int(s.shape[0])
 
-    def flux(self, theta_open, tau_ref, sinks=None, counters=False, out=None):
+    def flux(self, theta_open, tau_ref, sinks=None, counters=False, out=None, tape=False):
+        """Flux at the sinks.  With `tape`, each ray's optical depth is also
+        recorded for a later adjoint_taped call."""
         s, ns = self._sinks(sinks)
         F = out if out is not None else torch.empty(ns, dtype=self.dtype, device=self.device)
         C = torch.empty((ns, 5), dtype=torch.int32, device=self.device) if counters else None
-        _check(lib().trevr_compute_flux(self._h, float(theta_open), float(tau_ref), _ptr(s), ns,
-                                        _ptr(F), _ptr(C), _stream()))
+        fn = lib().trevr_compute_flux_taped if tape else lib().trevr_compute_flux
+        _check(fn(self._h, float(theta_open), float(tau_ref), _ptr(s), ns, _ptr(F), _ptr(C),
+                  _stream()))
+        if tape:
+            self._tape_sinks = s  # the recording reads it again in adjoint_taped
+            self._tape_ns = ns
         return (F, C) if counters else F
+
+    def adjoint_taped(self, grad_flux):
+        """The adjoint for the arguments of the last flux(..., tape=True)."""
+        ns = getattr(self, "_tape_ns", None)
+        if ns is None:
+            raise TrevrError(-5, "no recording flux call on this tree")
+        g = grad_flux.to(device=self.device, dtype=self.dtype).contiguous()
+        if g.shape[0] != ns:
+            raise ValueError("grad_flux has %d entries, expected %d" % (g.shape[0], ns))
+        outs = [torch.empty(self.n, dtype=self.dtype, device=self.device) for _ in range(3)]
+        _check(lib().trevr_compute_flux_adjoint_taped(self._h, _ptr(g), _ptr(outs[0]),
+                                                      _ptr(outs[1]), _ptr(outs[2]), _stream()))
+        return tuple(outs)
+
+    def reserve_tape(self, blocks):
+        """Tape capacity of later recordings in blocks of 64 rays (0: automatic)."""
+        _check(lib().trevr_reserve_tape(self._h, int(blocks)))
 
     def adjoint(self, theta_open, tau_ref, grad_flux, sinks=None):
         s, ns = self._sinks(sinks)
@@ -273,21 +303,20 @@ def compute_flux_adjoint(tree, theta_open, tau_ref, grad_flux, sinks=None):
 
 class TrevrFlux(torch.autograd.Function):
     """F = flux(rho, kappa, lum) at fixed positions; backward runs the adjoint
-    kernel over the same traversal (decisions held fixed)."""
+    kernel over the same traversal (decisions held fixed), with each ray's
+    optical depth taken from the forward's recording."""
 
     @staticmethod
     def forward(ctx, rho, kappa, lum, pos, mass, theta_open, tau_ref, bucket_size, sinks):
         tree = build_tree(pos, rho.detach(), kappa.detach(), lum.detach(), mass,
                           bucket_size=bucket_size, device=pos.device)
-        F = tree.flux(theta_open, tau_ref, sinks)
+        F = tree.flux(theta_open, tau_ref, sinks, tape=True)
         ctx.tree = tree
-        ctx.args = (theta_open, tau_ref, sinks)
         return F
 
     @staticmethod
     def backward(ctx, gF):
-        theta_open, tau_ref, sinks = ctx.args
-        g_rho, g_kappa, g_lum = ctx.tree.adjoint(theta_open, tau_ref, gF.contiguous(), sinks)
+        g_rho, g_kappa, g_lum = ctx.tree.adjoint_taped(gF.contiguous())
         ctx.tree = None
         return g_rho, g_kappa, g_lum, None, None, None, None, None, None
 
