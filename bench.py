@@ -9,7 +9,8 @@ Inputs are resident in HBM before the timed region.
 
 Printed: one JSON line with the throughput (sink fluxes per second), the
 cell visits per second, the forward+adjoint / forward time ratio on the
-2^20-particle adjoint workload, the roofline of the dominant kernel (the
+2^20-particle adjoint workload (recording forward + taped adjoint over the
+plain forward; the two-pass adjoint beside it), the roofline of the dominant kernel (the
 flux walk) and the oracle's CPU throughput on a bounded sample.
 """
 from __future__ import annotations
@@ -104,9 +105,15 @@ def adjoint_ratio(torch, P, reps=3):
         return float(np.median(ms))
 
     t_f = t_of(lambda: tree.flux(w["theta"], w["tau_ref"]))
+    # the differentiable path: the forward records each ray's tau, the adjoint
+    # reads it and traces every ray once
+    t_ft = t_of(lambda: tree.flux(w["theta"], w["tau_ref"], tape=True))
+    t_at = t_of(lambda: tree.adjoint_taped(gF))
+    # the adjoint on its own, tracing every ray twice
     t_a = t_of(lambda: tree.adjoint(w["theta"], w["tau_ref"], gF))
-    return {"workload": w["name"], "fwd_ms": t_f, "adj_ms": t_a,
-            "fwd_plus_adj_over_fwd": (t_f + t_a) / t_f}
+    return {"workload": w["name"], "fwd_ms": t_f, "fwd_taped_ms": t_ft, "adj_taped_ms": t_at,
+            "fwd_plus_adj_over_fwd": (t_ft + t_at) / t_f,
+            "adj_two_pass_ms": t_a, "fwd_plus_adj_two_pass_over_fwd": (t_f + t_a) / t_f}
 
 
 def batched(torch, P, reps=5):
