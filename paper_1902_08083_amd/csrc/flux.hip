@@ -928,6 +928,9 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         tprev = b;
       }
       double tau_rec = 0.0;
+      // adjoint: the ray's terms for its source (d loss / d L, and d loss / d x_L
+      // of a cell), summed over the round's rays of one source before the atomics
+      double sv[4] = {0.0, 0.0, 0.0, 0.0};
       if (replay && tcur >= 0) {
         rp = true;
         tblk = tcur;
@@ -994,13 +997,39 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           sc.u[0] = sc.u[1] = sc.u[2] = 0.0;
           trace_pieces<T>(a, C, keyC, depthC, tk, c, sc);
           for (int q3 = 0; q3 < 3; ++q3) sc.dtdy[q3] += c.r * c.inv[q3] * sc.u[q3];
-          if (psrc) {  // d loss / d L_j of the particle source
-            gbl_add(&a.direct[id], sc.g / (double)L);
-          } else {  // d loss / d L_C and d loss / d x_L of the cell
-            gbl_add(&a.lbar[C], sc.g / (double)L);
-            gbl_add(&a.xbar[C], sc.g * (-2.0 * c.d[0] / c.r2 - sc.dtdy[0]));
-            gbl_add(&a.xbar[a.m + C], sc.g * (-2.0 * c.d[1] / c.r2 - sc.dtdy[1]));
-            gbl_add(&a.xbar[2 * a.m + C], sc.g * (-2.0 * c.d[2] / c.r2 - sc.dtdy[2]));
+          sv[0] = sc.g / (double)L;  // d loss / d L of the source
+          if (!psrc)                 // d loss / d x_L of the cell
+            for (int q3 = 0; q3 < 3; ++q3)
+              sv[1 + q3] = sc.g * (-2.0 * c.d[q3] / c.r2 - sc.dtdy[q3]);
+        }
+      }
+      if (ADJ) {
+        // Rays of one source are adjacent in the queue (a visited cell's
+        // accepting sinks; an opened bucket's particle, sink by sink), so the
+        // round's lanes form runs of one source: a segmented sum over each
+        // run, then one set of device atomics per run.
+        const uint32_t key = busy ? e : 0xffffffffu;
+        const uint32_t prev = __shfl_up(key, 1);
+        const bool head = lane == 0 || prev != key;
+        const uint64_t hm = __ballot(head);
+        const int start = 63 - __clzll(hm & ((2ull << lane) - 1));  // the run's first lane
+        for (int o = 1; o < 64; o <<= 1) {
+          const bool take = lane - o >= start;
+          for (int q3 = 0; q3 < 4; ++q3) {
+            const double t = __shfl_up(sv[q3], o);
+            if (take) sv[q3] += t;
+          }
+        }
+        const bool tail = busy && (lane == nb - 1 || (lane < 63 && ((hm >> (lane + 1)) & 1)));
+        if (tail) {
+          const int id = (int)(e & ~kQParticle);
+          if (e & kQParticle) {
+            gbl_add(&a.direct[id], sv[0]);
+          } else {
+            gbl_add(&a.lbar[id], sv[0]);
+            gbl_add(&a.xbar[id], sv[1]);
+            gbl_add(&a.xbar[a.m + id], sv[2]);
+            gbl_add(&a.xbar[2 * a.m + id], sv[3]);
           }
         }
       }
