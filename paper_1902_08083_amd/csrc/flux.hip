@@ -246,19 +246,23 @@ struct Scatter {
   int32_t *hk;            // per-wave LDS table of other cells: keys (-1: free) ...
   double *hv;             // ... and their sums, written out after each round
   int hmask;              // table slots - 1 (a power of two minus one)
-  // Other cells go to the table (the slot a hash of the cell picks), so
-  // that no device-memory atomic waits among the trace's loads; a cell whose
-  // slot holds another cell goes straight to device memory.
+  // Other cells go to the table (one of two slots picked by two hashes of
+  // the cell), so that few device-memory atomics wait among the trace's
+  // loads; a cell whose two slots hold other cells goes straight to device
+  // memory.  One compare-and-swap per probe claims a free slot or finds the
+  // cell's own.
   __device__ __forceinline__ void pool(int node, double v) {
-    const int sl = (int)((((uint32_t)node * 2654435761u) >> 16) & (uint32_t)hmask);
-    int k = ((lds_i32 *)hk)[sl];
-    if (k == -1) {
-      int expect = -1;
-      __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &expect, node, __ATOMIC_RELAXED,
+    int sl = (int)((((uint32_t)node * 2654435761u) >> 16) & (uint32_t)hmask);
+    int k = -1;  // the slot's key before: free (now ours), this cell, or another
+    __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &k, node, __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (k != -1 && k != node) {  // taken: a second slot from an independent hash
+      sl = (int)((((uint32_t)node * 0x85ebca6bu) >> 20) & (uint32_t)hmask);
+      k = -1;
+      __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &k, node, __ATOMIC_RELAXED,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      k = expect == -1 ? node : expect;
     }
-    if (k == node)
+    if (k == -1 || k == node)
       lds_add(&hv[sl], v);
     else
       gbl_add(&abar[node], v);
