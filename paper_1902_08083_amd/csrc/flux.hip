@@ -1050,11 +1050,47 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         wave_sync();
       }
       if (!ADJ) {  // each owner adds its rays' fluxes in queue order
-        for (int j = 0; j < nb; ++j) {
-          const int oj = __builtin_amdgcn_readlane(owner, j);
-          const double fj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(f), j),
-                                             __builtin_amdgcn_readlane(__double2loint(f), j));
-          if (lane == oj) F += fj;
+        // Runs: stretches of lanes with strictly increasing owners (a visited
+        // cell's accepting sinks, an opened bucket's particle for each opening
+        // sink).  An owner has at most one ray in a run, so one forward
+        // permute per run hands every ray's flux to its owner.
+        const int prev_o = __shfl_up(owner, 1);
+        uint64_t rs = __ballot(busy && (lane == 0 || owner <= prev_o));
+        if (__popcll(rs) <= 24) {
+          while (rs) {
+            const int r0 = __ffsll((unsigned long long)rs) - 1;
+            rs &= rs - 1;
+            const int r1 = rs ? __ffsll((unsigned long long)rs) - 1 : nb;
+            const bool in = lane >= r0 && lane < r1;
+            // lanes outside the run push nothing useful, to lane 63
+            const int to = (in ? owner : 63) * 4;
+            const int hi = __builtin_amdgcn_ds_permute(to, in ? __double2hiint(f) : 0);
+            const int lo = __builtin_amdgcn_ds_permute(to, in ? __double2loint(f) : 0);
+            const int got = __builtin_amdgcn_ds_permute(to, in ? 1 : 0);
+            double fj = __hiloint2double(hi, lo);
+            bool has = got != 0;
+            // a later lane outside the run can overwrite lane 63's value
+            const uint64_t m63 = __ballot(in && owner == 63);
+            if (m63) {
+              const int j63 = __ffsll((unsigned long long)m63) - 1;
+              const double f63 =
+                  __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(f), j63),
+                                   __builtin_amdgcn_readlane(__double2loint(f), j63));
+              if (lane == 63) {
+                has = true;
+                fj = f63;
+              }
+            }
+            if (has) F += fj;
+          }
+        } else {
+          for (int j = 0; j < nb; ++j) {
+            const int oj = __builtin_amdgcn_readlane(owner, j);
+            const double fj =
+                __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(f), j),
+                                 __builtin_amdgcn_readlane(__double2loint(f), j));
+            if (lane == oj) F += fj;
+          }
         }
       }
     };
