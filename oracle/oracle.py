@@ -64,6 +64,9 @@ def lib():
         L.oracle_flux.restype = ctypes.c_int
         L.oracle_flux.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
                                   ctypes.c_int, P, P, P]
+        L.oracle_flux_vec.restype = ctypes.c_int
+        L.oracle_flux_vec.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
+                                      ctypes.c_int, P, P]
         L.oracle_ray_log.restype = ctypes.c_int64
         L.oracle_ray_log.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                      ctypes.c_int64] + [P] * 6
@@ -141,6 +144,19 @@ class OracleTree:
         if rc != 0:
             raise ValueError("oracle_flux rejected its arguments")
         return (F, C, G) if with_g else (F, C)
+
+    def flux_vector(self, theta, tau_ref, sinks=None, nthreads=0):
+        """Return (F, Fv[ns, 3]): the flux and the vector flux, each ray's
+        flux along its direction of travel at the sink, summed in walk order."""
+        s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+        ns = self.n if s is None else int(s.shape[0])
+        F = np.empty(ns, np.float64)
+        Fv = np.empty((ns, 3), np.float64)
+        rc = lib().oracle_flux_vec(self._h, float(theta), float(tau_ref), _ptr(s), ns,
+                                   int(nthreads), _ptr(F), _ptr(Fv))
+        if rc != 0:
+            raise ValueError("oracle_flux_vec rejected its arguments")
+        return F, Fv
 
     def ray_log(self, theta, tau_ref, sink, cap=1 << 20):
         C = np.empty(cap, np.int64)

@@ -408,6 +408,7 @@ typedef struct {
   double xi[3];
   double theta2, tau_ref;
   double F, G;
+  double Fv[3]; /* vector flux: sum of f times the unit vector from source to sink */
   int64_t n_open, n_rays, n_psrc, n_seg, n_trace;
   /* adjoint accumulators (NULL in a forward pass) */
   double w;
@@ -600,6 +601,8 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
   double f = (L * exp(-ry.tau)) / ((4.0 * M_PI) * ry.r2);
   c->F += f;
   c->G += f * ry.tau;
+  /* the ray's direction of travel at the sink, (x_i - y) / r */
+  for (int a = 0; a < 3; ++a) c->Fv[a] += f * (-ry.d[a] / ry.r);
   if (c->log_C && c->log_n < c->log_cap) {
     int64_t k = c->log_n;
     c->log_C[k] = C;
@@ -723,6 +726,28 @@ int oracle_flux(void *h, double theta, double tau_ref, const int64_t *sinks,
       counters[5 * q + 3] = c.n_seg;
       counters[5 * q + 4] = c.n_trace;
     }
+  }
+  return 0;
+}
+
+/* Vector flux (the flux of eq. simpint carried along each ray's direction of
+ * travel, summed over rays in walk order): Fv receives 3 per sink (x, y, z).
+ * F receives the scalar flux as in oracle_flux. */
+int oracle_flux_vec(void *h, double theta, double tau_ref, const int64_t *sinks,
+                    int64_t ns, int nthreads, double *F, double *Fv) {
+  const otree *t = (const otree *)h;
+  if (!(theta >= 0)) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t q = 0; q < ns; ++q) {
+    int64_t i = sinks ? sinks[q] : q;
+    osink c;
+    sink_init(&c, t, i, theta, tau_ref);
+    walk(&c, 0);
+    F[q] = c.F;
+    for (int a = 0; a < 3; ++a) Fv[3 * q + a] = c.Fv[a];
   }
   return 0;
 }

@@ -101,6 +101,24 @@ def all_pairs_flux(pos, lum, alpha_const=0.0, sinks=None):
     return out
 
 
+def all_pairs_vector_flux(pos, lum, alpha_const=0.0, sinks=None):
+    """Fv_i = sum_{j != i, L_j > 0} L_j exp(-alpha r) (x_i - x_j) / (4 pi r^3): each
+    source's flux (eq. simpint) along its direction of travel at the sink."""
+    pos = np.asarray(pos, np.float64)
+    lum = np.asarray(lum, np.float64)
+    src = np.nonzero(lum > 0)[0]
+    sinks = np.arange(pos.shape[0]) if sinks is None else np.asarray(sinks)
+    out = np.zeros((sinks.size, 3))
+    for q, i in enumerate(sinks):
+        d = pos[i] - pos[src]
+        r2 = np.sum(d * d, axis=1)
+        ok = r2 > 0
+        r = np.sqrt(r2[ok])
+        w = lum[src][ok] * np.exp(-alpha_const * r) / (4.0 * math.pi * r2[ok] * r)
+        out[q] = np.sum(w[:, None] * d[ok], axis=0)
+    return out
+
+
 def fibonacci_sphere(m, radius, centre):
     """m points on a sphere by the golden-angle spiral."""
     k = np.arange(m) + 0.5
