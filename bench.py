@@ -82,6 +82,26 @@ def counters_run(torch, tree, w):
     return C.to(torch.int64).sum(0).cpu().numpy()
 
 
+def vector_flux(torch, tree, w, reps=3):
+    """The flux with the vector flux (radiation-pressure direction) on the
+    headline tree: HIP-event time of one call, after one untimed call."""
+    st = torch.cuda.current_stream()
+    tree.flux_vector(w["theta"], w["tau_ref"])
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        tree.flux_vector(w["theta"], w["tau_ref"])
+        b.record(st)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    t = float(np.median(ms))
+    n = int(w["pos"].shape[0])
+    return {"workload": w["name"], "ms": t, "sink_fluxes_per_s": n / (t * 1e-3)}
+
+
 def adjoint_ratio(torch, P, reps=3):
     from paper_1902_08083_amd import workloads as W
     w = W.c5()
@@ -205,6 +225,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-vector", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--n", type=int, default=1 << 21, help="particles (default: the headline 2^21)")
@@ -280,6 +301,9 @@ def main():
                      "kernel": walk_kernel_name(launch),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if not args.no_vector:
+        log("vector flux on the same workload")
+        out["vector_flux"] = vector_flux(torch, tree, w)
     if not args.no_adjoint:
         log("adjoint ratio on the 2^20 workload")
         out["adjoint"] = adjoint_ratio(torch, P)

@@ -55,6 +55,7 @@ struct FluxArgs {
   int32_t group;     // 64-sink groups per grab
   double theta2, tau_ref;
   T *flux;
+  T *flux_vec;  // [3][n_sinks]: the vector flux (kernel variant with VEC only)
   int32_t *counters;
   int32_t *queue;  // kXcd counters
   // Tape of per-ray optical depths: one block of 64 per round, the blocks of
@@ -746,7 +747,7 @@ constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source,
 // owning sink's context by lane shuffles; each owner adds its results in
 // queue order, so a sink's sum is in its own walk order whatever the other
 // sinks of the wave are.
-template <typename T, bool ADJ, int KS, int KR, int HN>
+template <typename T, bool ADJ, int KS, int KR, int HN, bool VEC = false>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
@@ -874,6 +875,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     // grad_flux is indexed like flux: by list position, or by particle
     if (ADJ && valid) wgt = (double)a.grad_flux[a.sinks ? q : (int64_t)a.perm[k]];
     double F = 0.0;
+    double FV[3] = {0.0, 0.0, 0.0};  // vector flux (VEC)
     int n_open = 0, n_rays = 0, n_psrc = 0;
     int qh = 0, qn = 0;  // the queue: first entry, entries (wave-uniform)
     int live = -1;       // the walk's path is s_path[0 .. live]
@@ -913,6 +915,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       tk.win = s_anc + owner;
       const double wg = ADJ ? __shfl(wgt, owner) : 0.0;
       double f = 0.0;
+      double fv[3] = {0.0, 0.0, 0.0};  // VEC: f along the ray's direction of travel
       int tblk = -1;     // this round's tape block
       bool rp = false;   // tau from the tape
       if (!ADJ && a.tape_mode == 1) {
@@ -975,6 +978,8 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           trace_pieces<T>(a, C, keyC, depthC, tk, c, ts);
         if (!ADJ && tblk >= 0) a.tape[(int64_t)tblk * 64 + lane] = ts.tau;
         f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
+        if (VEC)
+          for (int q3 = 0; q3 < 3; ++q3) fv[q3] = f * (-c.d[q3] / c.r);
         if (!ADJ) {
           __hip_atomic_fetch_add(&s_cnt[owner], c.n_seg, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -1068,6 +1073,12 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
             const int lo = __builtin_amdgcn_ds_permute(to, in ? __double2loint(f) : 0);
             const int got = __builtin_amdgcn_ds_permute(to, in ? 1 : 0);
             double fj = __hiloint2double(hi, lo);
+            double fvj[3] = {0.0, 0.0, 0.0};
+            if (VEC)
+              for (int q3 = 0; q3 < 3; ++q3)
+                fvj[q3] = __hiloint2double(
+                    __builtin_amdgcn_ds_permute(to, in ? __double2hiint(fv[q3]) : 0),
+                    __builtin_amdgcn_ds_permute(to, in ? __double2loint(fv[q3]) : 0));
             bool has = got != 0;
             // a later lane outside the run can overwrite lane 63's value
             const uint64_t m63 = __ballot(in && owner == 63);
@@ -1080,8 +1091,19 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                 has = true;
                 fj = f63;
               }
+              if (VEC)
+                for (int q3 = 0; q3 < 3; ++q3) {
+                  const double v63 =
+                      __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fv[q3]), j63),
+                                       __builtin_amdgcn_readlane(__double2loint(fv[q3]), j63));
+                  if (lane == 63) fvj[q3] = v63;
+                }
             }
-            if (has) F += fj;
+            if (has) {
+              F += fj;
+              if (VEC)
+                for (int q3 = 0; q3 < 3; ++q3) FV[q3] += fvj[q3];
+            }
           }
         } else {
           for (int j = 0; j < nb; ++j) {
@@ -1090,6 +1112,13 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                 __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(f), j),
                                  __builtin_amdgcn_readlane(__double2loint(f), j));
             if (lane == oj) F += fj;
+            if (VEC)
+              for (int q3 = 0; q3 < 3; ++q3) {
+                const double vj =
+                    __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fv[q3]), j),
+                                     __builtin_amdgcn_readlane(__double2loint(fv[q3]), j));
+                if (lane == oj) FV[q3] += vj;
+              }
           }
         }
       }
@@ -1206,6 +1235,9 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       if (in_list) {
         const int64_t out = a.sinks ? q : (int64_t)a.perm[k];
         a.flux[out] = bad ? (T)NAN : (T)F;
+        if (VEC)
+          for (int q3 = 0; q3 < 3; ++q3)
+            a.flux_vec[q3 * a.n_sinks + out] = bad ? (T)NAN : (T)FV[q3];
         if (a.counters) {
           int32_t *o = a.counters + 5 * out;
           o[0] = bad ? -1 : n_open;
@@ -1232,6 +1264,12 @@ template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
     FluxArgs<T> a) {
   walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ), occ_hn(4, ADJ)>(a);
+}
+// The flux with the vector flux, at the 4-wave budget.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4v(
+    FluxArgs<T> a) {
+  walk_body<T, false, occ_ks(4, false), occ_kr(4, false), occ_hn(4, false), true>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
@@ -1343,6 +1381,16 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   int64_t blocks = (int64_t)L.blocks_per_cu * t->num_cu;
   const int64_t need = (a.n_chunks + waves - 1) / waves;
   if (blocks > need) blocks = need;
+  if constexpr (!ADJ) {
+    if (a.flux_vec) {  // the vector flux: the 4-wave kernel, at most 4 waves per SIMD
+      const int bpc = L.blocks_per_cu * waves > 16 ? 16 / waves : L.blocks_per_cu;
+      int64_t vb = (int64_t)bpc * t->num_cu;
+      if (vb > need) vb = need;
+      k_walk4v<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(4), s>>>(a);
+      TREVR_HIP(hipGetLastError());
+      return TREVR_OK;
+    }
+  }
   const int per_simd = (L.blocks_per_cu * waves + 3) / 4;
   const int wps = per_simd >= 8 ? 8 : per_simd >= 6 ? 6 : per_simd == 5 ? 5 : per_simd == 4 ? 4 : 3;
   // waves per workgroup <= 4 x wps, so the workgroup fits the CU's LDS
@@ -1376,10 +1424,11 @@ static void set_tape(const trevr_tree *t, FluxArgs<T> &a, int mode) {
 template <typename T>
 static int flux_typed(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                       int64_t n_sinks, void *flux, int32_t *counters, int tape_mode,
-                      hipStream_t s) {
+                      hipStream_t s, void *flux_vec = nullptr) {
   if (n_sinks == 0) return TREVR_OK;
   FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
   a.flux = static_cast<T *>(flux);
+  a.flux_vec = static_cast<T *>(flux_vec);
   a.counters = counters;
   set_tape<T, false>(t, a, tape_mode);
   return launch_walk<T, false>(t, a, s);
@@ -1390,6 +1439,13 @@ int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *
   if (t->prec == TREVR_F64)
     return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s);
   return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s);
+}
+
+int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                  int64_t n_sinks, void *flux, void *flux_vec, int32_t *counters, hipStream_t s) {
+  if (t->prec == TREVR_F64)
+    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s, flux_vec);
+  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s, flux_vec);
 }
 
 // The recording flux: sizes the tape (the last recording's block count plus a

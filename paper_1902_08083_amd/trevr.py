@@ -65,7 +65,7 @@ EXPORTED = (
     "trevr_build_tree", "trevr_tree_info", "trevr_compute_flux", "trevr_compute_flux_adjoint",
     "trevr_set_launch", "trevr_get_launch", "trevr_set_adjoint_launch",
     "trevr_get_adjoint_launch", "trevr_export_tree", "trevr_compute_flux_taped",
-    "trevr_compute_flux_adjoint_taped", "trevr_reserve_tape",
+    "trevr_compute_flux_adjoint_taped", "trevr_reserve_tape", "trevr_compute_flux_vector",
 )
 
 
@@ -99,6 +99,8 @@ def lib():
     L.trevr_compute_flux_taped.argtypes = [P, D, D, P, I64, P, P, P]
     L.trevr_compute_flux_adjoint_taped.restype = I
     L.trevr_compute_flux_adjoint_taped.argtypes = [P, P, P, P, P, P]
+    L.trevr_compute_flux_vector.restype = I
+    L.trevr_compute_flux_vector.argtypes = [P, D, D, P, I64, P, P, P, P]
     L.trevr_reserve_tape.restype = I
     L.trevr_reserve_tape.argtypes = [P, I64]
     L.trevr_set_launch.restype = I
@@ -236,6 +238,18 @@ class Tree:
             self._tape_sinks = s  # the recording reads it again in adjoint_taped
             self._tape_ns = ns
         return (F, C) if counters else F
+
+    def flux_vector(self, theta_open, tau_ref, sinks=None, counters=False):
+        """(F, Fv): the flux and the vector flux (n_sinks x 3; each ray's flux
+        along its direction of travel at the sink)."""
+        s, ns = self._sinks(sinks)
+        F = torch.empty(ns, dtype=self.dtype, device=self.device)
+        Fv = torch.empty((3, ns), dtype=self.dtype, device=self.device)
+        C = torch.empty((ns, 5), dtype=torch.int32, device=self.device) if counters else None
+        _check(lib().trevr_compute_flux_vector(self._h, float(theta_open), float(tau_ref),
+                                               _ptr(s), ns, _ptr(F), _ptr(Fv), _ptr(C),
+                                               _stream()))
+        return (F, Fv.t(), C) if counters else (F, Fv.t())
 
     def adjoint_taped(self, grad_flux):
         """The adjoint for the arguments of the last flux(..., tape=True)."""
