@@ -164,13 +164,12 @@ int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_r
                                void *grad_rho, void *grad_kappa, void *grad_lum,
                                hipStream_t stream);
 
-/* Flux and vector flux at the sinks: everything trevr_compute_flux computes,
- * and in addition each ray's contribution L exp(-tau) / (4 pi r^2) (eq.
- * simpint) carried along the ray's direction of travel at the sink, the unit
- * vector from the source point y (a particle, or a merged cell's centre of
- * luminosity) to the sink x, summed over the sink's rays in walk order: the
- * direction of the radiation pressure (the paper names radiation pressure
- * among the vector quantities the same walk yields).
+/* Flux and net radiation flux at the sinks (Sec. 2.1, eq. simpflux):
+ * everything trevr_compute_flux computes, and in addition the vector sum over
+ * the sink's rays, in walk order, of L exp(-tau) / (4 pi r^2) n, with n the
+ * unit vector from the source point y (a particle, or a merged cell's centre
+ * of luminosity) to the sink x.  It is the first moment of the intensity,
+ * from which the radiation pressure follows.
  *   flux_vec: device, 3 x n_sinks, [component][sink] (x block, y block, z
  *   block), precision of the tree; NaN for an invalid sink index.
  * Runs the 4-wave kernel whatever the launch shape (at most 4 waves per

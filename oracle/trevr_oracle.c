@@ -730,8 +730,9 @@ int oracle_flux(void *h, double theta, double tau_ref, const int64_t *sinks,
   return 0;
 }
 
-/* Vector flux (the flux of eq. simpint carried along each ray's direction of
- * travel, summed over rays in walk order): Fv receives 3 per sink (x, y, z).
+/* Net radiation flux, eq. (simpflux): each ray's L exp(-tau)/(4 pi r^2) along
+ * the unit vector from the source point to the sink, summed over the sink's
+ * rays in walk order.  Fv receives 3 per sink (x, y, z).
  * F receives the scalar flux as in oracle_flux. */
 int oracle_flux_vec(void *h, double theta, double tau_ref, const int64_t *sinks,
                     int64_t ns, int nthreads, double *F, double *Fv) {
