@@ -704,18 +704,18 @@ __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
 // Window and stack depth per occupancy variant (waves per SIMD), chosen so
 // that that many waves fit the CU's 160 KiB of LDS.
 __host__ __device__ constexpr int occ_ks(int wps, bool adj) {
-  return wps <= 3 ? (adj ? 6 : 14)
+  return wps <= 3 ? (adj ? 2 : 14)
                   : wps == 4 ? (adj ? 5 : 7)
                              : wps == 5 ? (adj ? 3 : 5) : wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
 }
 __host__ __device__ constexpr int occ_kr(int wps, bool adj) {
-  return wps <= 3 ? (adj ? 8 : 10)
+  return wps <= 3 ? (adj ? 11 : 10)
                   : wps == 4 ? (adj ? 6 : 8)
                              : wps == 5 ? (adj ? 5 : 6) : wps <= 7 ? (adj ? 3 : 5) : (adj ? 1 : 3);
 }
 // adjoint: slots of the per-wave table of d loss / d alpha (a power of two)
 __host__ __device__ constexpr int occ_hn(int wps, bool adj) {
-  return !adj ? 0 : wps <= 3 ? 256 : wps == 4 ? 128 : 64;
+  return !adj ? 0 : wps <= 3 ? 128 : wps == 4 ? 128 : 64;
 }
 template <bool ADJ>
 __host__ __device__ constexpr size_t occ_lds(int wps) {
