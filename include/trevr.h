@@ -123,6 +123,18 @@ void trevr_tree_destroy(trevr_tree *tree);
  * the handle holds no tree. */
 int trevr_build_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream);
 
+/* Refit: recompute every cell property of the built tree (alpha, the
+ * directional alpha bounds, L_C, x_L, l_far; Sec. 2.2.1, 2.2.3) from new
+ * mass, rho, kappa and lum, keeping its topology.  The particles must be the
+ * build's: same n, precision, boxes (offsets and corners) and bucket size,
+ * and every position equal, value for value, to the one the tree was built
+ * from (checked on the device); the tree then equals a fresh build from the
+ * same arrays.  Invalidates the tape of trevr_compute_flux_taped.  Waits on
+ * `stream`.  Errors: TREVR_E_ARG (another particle set, or a moved position),
+ * _STATE, _NONFINITE, _VALUE, _HIP; after a validation error the tree keeps
+ * its previous properties, after a later one it holds no tree. */
+int trevr_refit_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream);
+
 int trevr_tree_info(const trevr_tree *tree, trevr_tree_info_t *info);
 
 /* Radiation field at the sinks (Sec. 2.1-2.2.3): for each sink a depth-first

@@ -126,6 +126,24 @@ int trevr_build_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t str
   return trevr::build_tree_impl(tree, p, stream);
 }
 
+int trevr_refit_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream) {
+  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
+  if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");
+  int rc = trevr::check_particles(p);
+  if (rc != TREVR_OK) return rc;
+  if (p->n != tree->n || p->prec != tree->prec || p->n_boxes != tree->n_boxes ||
+      p->bucket_size != tree->nb)
+    return trevr::fail(TREVR_E_ARG, "n, precision, boxes or bucket size differ from the build");
+  for (int b = 0; b <= p->n_boxes; ++b) {
+    const int64_t o = p->box_offsets ? p->box_offsets[b] : (b == 0 ? 0 : p->n);
+    if (o != tree->h_box_off[b]) return trevr::fail(TREVR_E_ARG, "box offsets differ");
+  }
+  for (int b = 0; b < 3 * p->n_boxes; ++b)
+    if (p->box_lo[b] != tree->h_box_lo[b] || p->box_hi[b] != tree->h_box_hi[b])
+      return trevr::fail(TREVR_E_ARG, "box corners differ from the build");
+  return trevr::refit_tree_impl(tree, p, stream);
+}
+
 int trevr_tree_info(const trevr_tree *tree, trevr_tree_info_t *info) {
   if (!tree || !info) return trevr::fail(TREVR_E_ARG, "NULL argument");
   if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");

@@ -23,7 +23,7 @@
 
 namespace trevr {
 
-enum : int { ERR_RANGE = 1, ERR_NONFINITE = 2, ERR_VALUE = 4 };
+enum : int { ERR_RANGE = 1, ERR_NONFINITE = 2, ERR_VALUE = 4, ERR_MOVED = 8 };
 
 template <typename T>
 struct PartIn {
@@ -402,6 +402,64 @@ __global__ void k_sorted_box(const int32_t *perm, const int64_t *box_off, int nb
 
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// Cell properties (a2) on the tree's topology: bucket and internal sums,
+// alpha, directional bounds, the transport records, and the particles in
+// sorted order.  Shared by the build and the refit.
+template <typename T>
+static int cell_props(trevr_tree *t, const PartIn<T> &in, int64_t n, int64_t m, int nbox,
+                      hipStream_t s) {
+  const size_t mm = (size_t)m, nn = (size_t)(n > 0 ? n : 1);
+  const int nlev = (int)t->level_cnt.size();
+  const BfsNode *bfs = t->bfs.as<BfsNode>();
+  const int32_t *perm = t->perm.as<int32_t>();
+  DevBuf *props[] = {&t->n_A, &t->n_B, &t->n_SL, &t->n_alpha, &t->n_alpha_min, &t->n_alpha_max,
+                     &t->n_dalpha, &t->n_lc, &t->n_lfar};
+  for (DevBuf *b : props) TREVR_HIP(b->ensure(8 * mm));
+  TREVR_HIP(t->n_SLx.ensure(24 * mm));
+  TREVR_HIP(t->n_amin.ensure(24 * mm));
+  TREVR_HIP(t->n_amax.ensure(24 * mm));
+  TREVR_HIP(t->n_xl.ensure(24 * mm));
+  Props P{t->n_A.as<double>(),         t->n_B.as<double>(),         t->n_SL.as<double>(),
+          t->n_SLx.as<double>(),       t->n_alpha.as<double>(),     t->n_amin.as<double>(),
+          t->n_amax.as<double>(),      t->n_alpha_min.as<double>(), t->n_alpha_max.as<double>(),
+          t->n_dalpha.as<double>(),    t->n_xl.as<double>(),        t->n_lc.as<double>(),
+          t->n_lfar.as<double>(),      t->n_first.as<int32_t>(),    t->n_count.as<int32_t>(),
+          t->n_right.as<int32_t>(),    t->n_parent.as<int32_t>(),   t->n_depth.as<int32_t>(),
+          t->n_axis.as<int8_t>(),      t->n_lo.as<double>(),        t->n_hi.as<double>(),
+          m};
+  for (int d = nlev - 1; d >= 0; --d) {
+    const BfsNode *lvl = bfs + t->level_off[d];
+    int c = (int)t->level_cnt[d];
+    k_bucket_sums<T><<<nblk(c), 256, 0, s>>>(lvl, c, in, perm, P);
+    k_internal_sums<<<nblk(c), 256, 0, s>>>(lvl, c, P);
+  }
+  for (int d = 0; d < nlev; ++d)
+    k_alpha<<<nblk(t->level_cnt[d]), 256, 0, s>>>(bfs + t->level_off[d], (int)t->level_cnt[d],
+                                                   P);
+  for (int d = nlev - 1; d >= 0; --d)
+    k_bounds<<<nblk(t->level_cnt[d]), 256, 0, s>>>(bfs + t->level_off[d], (int)t->level_cnt[d],
+                                                    P);
+  TREVR_HIP(t->walk.ensure(sizeof(WalkRecT<T>) * mm));
+  TREVR_HIP(t->trace.ensure(sizeof(TraceRecT<T>) * mm));
+  k_finish<T><<<nblk(m), 256, 0, s>>>(P, t->walk.as<WalkRecT<T>>(), t->trace.as<TraceRecT<T>>());
+  k_finish2<T><<<nblk(m), 256, 0, s>>>(t->n_skip.as<int32_t>(), t->n_split.as<double>(), m,
+                                       t->walk.as<WalkRecT<T>>(), t->trace.as<TraceRecT<T>>());
+
+  TREVR_HIP(t->psrc.ensure(sizeof(P4<T>) * nn));
+  TREVR_HIP(t->inv.ensure(4 * nn));
+  TREVR_HIP(t->pbox.ensure(4 * nn));
+  TREVR_HIP(t->pmass.ensure(sizeof(T) * nn));
+  TREVR_HIP(t->prho.ensure(sizeof(T) * nn));
+  if (n > 0) {
+    k_particles<T><<<nblk(n), 256, 0, s>>>(in, perm, n, t->psrc.as<P4<T>>(), t->inv.as<int32_t>(),
+                                           t->pmass.as<T>(), t->prho.as<T>());
+    k_sorted_box<<<nblk(n), 256, 0, s>>>(perm, t->box_off.as<int64_t>(), nbox, n,
+                                         t->pbox.as<int32_t>());
+  }
+  TREVR_HIP(hipGetLastError());
+  return TREVR_OK;
+}
+
 template <typename T>
 static int build_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   const int64_t n = p->n;
@@ -449,6 +507,8 @@ static int build_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
                            hipMemcpyHostToDevice, s));
   TREVR_HIP(hipMemcpyAsync(t->axis_tab.p, axes.data(), 64 * nbox, hipMemcpyHostToDevice, s));
   t->h_box_off = off;
+  t->h_box_lo.assign(p->box_lo, p->box_lo + 3 * nbox);
+  t->h_box_hi.assign(p->box_hi, p->box_hi + 3 * nbox);
 
   const size_t nn = (size_t)(n > 0 ? n : 1);
   TREVR_HIP(t->keys_in.ensure(8 * nn));
@@ -620,51 +680,10 @@ static int build_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   }
   TREVR_HIP(hipGetLastError());
 
-  DevBuf *props[] = {&t->n_A, &t->n_B, &t->n_SL, &t->n_alpha, &t->n_alpha_min, &t->n_alpha_max,
-                     &t->n_dalpha, &t->n_lc, &t->n_lfar};
-  for (DevBuf *b : props) TREVR_HIP(b->ensure(8 * mm));
-  TREVR_HIP(t->n_SLx.ensure(24 * mm));
-  TREVR_HIP(t->n_amin.ensure(24 * mm));
-  TREVR_HIP(t->n_amax.ensure(24 * mm));
-  TREVR_HIP(t->n_xl.ensure(24 * mm));
-  Props P{t->n_A.as<double>(),         t->n_B.as<double>(),         t->n_SL.as<double>(),
-          t->n_SLx.as<double>(),       t->n_alpha.as<double>(),     t->n_amin.as<double>(),
-          t->n_amax.as<double>(),      t->n_alpha_min.as<double>(), t->n_alpha_max.as<double>(),
-          t->n_dalpha.as<double>(),    t->n_xl.as<double>(),        t->n_lc.as<double>(),
-          t->n_lfar.as<double>(),      t->n_first.as<int32_t>(),    t->n_count.as<int32_t>(),
-          t->n_right.as<int32_t>(),    t->n_parent.as<int32_t>(),   t->n_depth.as<int32_t>(),
-          t->n_axis.as<int8_t>(),      t->n_lo.as<double>(),        t->n_hi.as<double>(),
-          m};
-  for (int d = nlev - 1; d >= 0; --d) {
-    const BfsNode *lvl = bfs + t->level_off[d];
-    int c = (int)t->level_cnt[d];
-    k_bucket_sums<T><<<nblk(c), 256, 0, s>>>(lvl, c, in, perm, P);
-    k_internal_sums<<<nblk(c), 256, 0, s>>>(lvl, c, P);
+  {
+    int rc = cell_props<T>(t, in, n, m, nbox, s);
+    if (rc != TREVR_OK) return rc;
   }
-  for (int d = 0; d < nlev; ++d)
-    k_alpha<<<nblk(t->level_cnt[d]), 256, 0, s>>>(bfs + t->level_off[d], (int)t->level_cnt[d],
-                                                   P);
-  for (int d = nlev - 1; d >= 0; --d)
-    k_bounds<<<nblk(t->level_cnt[d]), 256, 0, s>>>(bfs + t->level_off[d], (int)t->level_cnt[d],
-                                                    P);
-  TREVR_HIP(t->walk.ensure(sizeof(WalkRecT<T>) * mm));
-  TREVR_HIP(t->trace.ensure(sizeof(TraceRecT<T>) * mm));
-  k_finish<T><<<nblk(m), 256, 0, s>>>(P, t->walk.as<WalkRecT<T>>(), t->trace.as<TraceRecT<T>>());
-  k_finish2<T><<<nblk(m), 256, 0, s>>>(t->n_skip.as<int32_t>(), t->n_split.as<double>(), m,
-                                       t->walk.as<WalkRecT<T>>(), t->trace.as<TraceRecT<T>>());
-
-  TREVR_HIP(t->psrc.ensure(sizeof(P4<T>) * nn));
-  TREVR_HIP(t->inv.ensure(4 * nn));
-  TREVR_HIP(t->pbox.ensure(4 * nn));
-  TREVR_HIP(t->pmass.ensure(sizeof(T) * nn));
-  TREVR_HIP(t->prho.ensure(sizeof(T) * nn));
-  if (n > 0) {
-    k_particles<T><<<nblk(n), 256, 0, s>>>(in, perm, n, t->psrc.as<P4<T>>(), t->inv.as<int32_t>(),
-                                           t->pmass.as<T>(), t->prho.as<T>());
-    k_sorted_box<<<nblk(n), 256, 0, s>>>(perm, t->box_off.as<int64_t>(), nbox, n,
-                                         t->pbox.as<int32_t>());
-  }
-  TREVR_HIP(hipGetLastError());
   t->h_box_root.resize(nbox);
   TREVR_HIP(hipMemcpyAsync(t->h_box_root.data(), t->box_root.p, 4 * nbox, hipMemcpyDeviceToHost,
                            s));
@@ -676,6 +695,58 @@ static int build_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   t->prec = p->prec;
   t->built = true;
   return TREVR_OK;
+}
+
+// Refit: new mass, rho, kappa and lum on the positions of the build.  Each
+// particle's position must equal, value for value, the one the tree was built
+// from (then every key, and the whole topology, is unchanged); the values are
+// validated as in the build.
+template <typename T>
+__global__ void k_refit_check(PartIn<T> in, int64_t n, const int32_t *inv, const P4<T> *ps,
+                              int *err) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const P4<T> v = ps[inv[q]];
+  double m = in.mass ? (double)in.mass[q] : 1.0;
+  double rho = (double)in.rho[q], kap = (double)in.kappa[q], L = (double)in.lum[q];
+  int e = 0;
+  if (!(in.x[q] == v.x && in.y[q] == v.y && in.z[q] == v.z)) e |= ERR_MOVED;
+  if (!isfinite(m) || !isfinite(kap) || !isfinite(L) || (m > 0 && !isfinite(rho)))
+    e |= ERR_NONFINITE;
+  else if (m < 0 || kap < 0 || L < 0 || (m > 0 && !(rho > 0)))
+    e |= ERR_VALUE;
+  if (e) atomicOr(err, e);
+}
+
+template <typename T>
+static int refit_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
+  const int64_t n = t->n;
+  PartIn<T> in{(const T *)p->x, (const T *)p->y, (const T *)p->z, (const T *)p->mass,
+               (const T *)p->rho, (const T *)p->kappa, (const T *)p->lum};
+  TREVR_HIP(hipMemsetAsync(t->err.p, 0, 4, s));
+  if (n > 0)
+    k_refit_check<T><<<nblk(n), 256, 0, s>>>(in, n, t->inv.as<int32_t>(),
+                                             t->psrc.as<P4<T>>(), t->err.as<int>());
+  TREVR_HIP(hipGetLastError());
+  int herr = 0;
+  TREVR_HIP(hipMemcpyAsync(&herr, t->err.p, 4, hipMemcpyDeviceToHost, s));
+  TREVR_HIP(hipStreamSynchronize(s));
+  if (herr & ERR_MOVED) return fail(TREVR_E_ARG, "a position differs from the build's");
+  if (herr & ERR_NONFINITE) return fail(TREVR_E_NONFINITE, "non-finite input value");
+  if (herr & ERR_VALUE)
+    return fail(TREVR_E_VALUE, "negative mass/opacity/luminosity or density <= 0");
+  t->built = false;
+  int rc = cell_props<T>(t, in, n, t->m, t->n_boxes, s);
+  if (rc != TREVR_OK) return rc;
+  TREVR_HIP(hipStreamSynchronize(s));
+  t->built = true;
+  return TREVR_OK;
+}
+
+int refit_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
+  t->tape_ok = false;
+  if (t->prec == TREVR_F64) return refit_typed<double>(t, p, s);
+  return refit_typed<float>(t, p, s);
 }
 
 int build_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {

@@ -139,6 +139,7 @@ struct trevr_tree {
   trevr::DevBuf axmask;  // per box: 3 u64, bit (62 - depth) set where that depth splits axis a
   std::vector<int32_t> h_box_root;
   std::vector<int64_t> h_box_off;
+  std::vector<double> h_box_lo, h_box_hi;
   // binary64 cell data (build, export, adjoint)
   trevr::DevBuf n_first, n_count, n_depth, n_parent, n_right, n_skip, n_box, n_axis;
   trevr::DevBuf n_lo, n_hi, n_split, n_A, n_B, n_SL, n_SLx, n_alpha, n_amin, n_amax;
@@ -169,6 +170,7 @@ int fail(int status, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
 int build_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s);
+int refit_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s);
 int export_tree_impl(const trevr_tree *t, int64_t *perm, int64_t *leaf_of, int64_t *node_i,
                      uint64_t *node_key, double *node_f, hipStream_t s);
 int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,

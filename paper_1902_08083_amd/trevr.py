@@ -66,6 +66,7 @@ EXPORTED = (
     "trevr_set_launch", "trevr_get_launch", "trevr_set_adjoint_launch",
     "trevr_get_adjoint_launch", "trevr_export_tree", "trevr_compute_flux_taped",
     "trevr_compute_flux_adjoint_taped", "trevr_reserve_tape", "trevr_compute_flux_vector",
+    "trevr_refit_tree",
 )
 
 
@@ -99,6 +100,8 @@ def lib():
     L.trevr_compute_flux_taped.argtypes = [P, D, D, P, I64, P, P, P]
     L.trevr_compute_flux_adjoint_taped.restype = I
     L.trevr_compute_flux_adjoint_taped.argtypes = [P, P, P, P, P, P]
+    L.trevr_refit_tree.restype = I
+    L.trevr_refit_tree.argtypes = [P, ctypes.POINTER(_Particles), P]
     L.trevr_compute_flux_vector.restype = I
     L.trevr_compute_flux_vector.argtypes = [P, D, D, P, I64, P, P, P, P]
     L.trevr_reserve_tape.restype = I
@@ -162,6 +165,29 @@ class Tree:
         """pos: (n, 3) tensor; rho, kappa, lum, mass: (n,) of the same float dtype
         (float32 -> binary32 transport, float64 -> binary64).  box_lo/box_hi:
         one corner triple, or (n_boxes, 3) with box_offsets (n_boxes + 1)."""
+        p, keep = self._particles(pos, rho, kappa, lum, mass, box_lo, box_hi, bucket_size,
+                                  box_offsets, device)
+        _check(lib().trevr_build_tree(self._h, ctypes.byref(p), _stream()))
+        self._layout = (box_lo, box_hi, bucket_size, box_offsets)
+        self.n = p.n
+        self.dtype = keep[0].dtype
+        self.prec = p.prec
+        self.device = keep[0].device
+        self.n_boxes = p.n_boxes
+        return self
+
+    def refit(self, pos, rho, kappa, lum, mass=None):
+        """New rho, kappa, lum (and mass) on the positions the tree was built
+        from: the cell properties are recomputed, the topology kept."""
+        box_lo, box_hi, bucket_size, box_offsets = self._layout
+        p, keep = self._particles(pos, rho, kappa, lum, mass, box_lo, box_hi, bucket_size,
+                                  box_offsets, self.device)
+        _check(lib().trevr_refit_tree(self._h, ctypes.byref(p), _stream()))
+        return self
+
+    @staticmethod
+    def _particles(pos, rho, kappa, lum, mass, box_lo, box_hi, bucket_size, box_offsets,
+                   device):
         pos = torch.as_tensor(pos, device=device)
         dtype = pos.dtype
         if dtype not in (torch.float32, torch.float64):
@@ -191,13 +217,8 @@ class Tree:
         p.box_lo = ctypes.cast(lo.data_ptr(), ctypes.POINTER(ctypes.c_double))
         p.box_hi = ctypes.cast(hi.data_ptr(), ctypes.POINTER(ctypes.c_double))
         p.bucket_size = int(bucket_size)
-        _check(lib().trevr_build_tree(self._h, ctypes.byref(p), _stream()))
-        self.n = n
-        self.dtype = dtype
-        self.prec = p.prec
-        self.device = pos.device
-        self.n_boxes = nbox
-        return self
+        p._keep = (keep, lo, hi, off)  # alive until the call returns
+        return p, keep
 
     def info(self):
         i = _Info()
