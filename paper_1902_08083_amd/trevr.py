@@ -342,9 +342,13 @@ class TrevrFlux(torch.autograd.Function):
     optical depth taken from the forward's recording."""
 
     @staticmethod
-    def forward(ctx, rho, kappa, lum, pos, mass, theta_open, tau_ref, bucket_size, sinks):
-        tree = build_tree(pos, rho.detach(), kappa.detach(), lum.detach(), mass,
-                          bucket_size=bucket_size, device=pos.device)
+    def forward(ctx, rho, kappa, lum, pos, mass, theta_open, tau_ref, bucket_size, sinks,
+                tree=None):
+        if tree is None:
+            tree = build_tree(pos, rho.detach(), kappa.detach(), lum.detach(), mass,
+                              bucket_size=bucket_size, device=pos.device)
+        else:  # a tree built earlier on these positions: new cell properties only
+            tree.refit(pos, rho.detach(), kappa.detach(), lum.detach(), mass)
         F = tree.flux(theta_open, tau_ref, sinks, tape=True)
         ctx.tree = tree
         return F
@@ -353,13 +357,16 @@ class TrevrFlux(torch.autograd.Function):
     def backward(ctx, gF):
         g_rho, g_kappa, g_lum = ctx.tree.adjoint_taped(gF.contiguous())
         ctx.tree = None
-        return g_rho, g_kappa, g_lum, None, None, None, None, None, None
+        return g_rho, g_kappa, g_lum, None, None, None, None, None, None, None
 
 
 def flux(pos, rho, kappa, lum, mass=None, theta_open=0.75, tau_ref=0.1, bucket_size=8,
-         sinks=None):
-    """Differentiable flux at the sinks with respect to rho, kappa and lum."""
-    return TrevrFlux.apply(rho, kappa, lum, pos, mass, theta_open, tau_ref, bucket_size, sinks)
+         sinks=None, tree=None):
+    """Differentiable flux at the sinks with respect to rho, kappa and lum.  With
+    `tree` (a Tree built on the same positions and boxes), the tree is refit
+    with the new values instead of built anew; it then holds them afterwards."""
+    return TrevrFlux.apply(rho, kappa, lum, pos, mass, theta_open, tau_ref, bucket_size, sinks,
+                           tree)
 
 
 # ---------------------------------------------------------------- batching ---

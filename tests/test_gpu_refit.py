@@ -103,3 +103,20 @@ def test_refit_invalidates_the_tape():
     rc = P.lib().trevr_compute_flux_adjoint_taped(t._h, _ptr(gF), _ptr(out[0]), _ptr(out[1]),
                                                   _ptr(out[2]), _stream())
     assert rc == -5
+
+
+def test_autograd_with_a_reused_tree():
+    _note("autograd flux with a refit tree")
+    dt = torch.float64
+    pos, rho, kappa, lum, mass = _arrays(4000, 93, dt)
+    t = P.Tree().build(pos, rho, kappa, lum, mass)
+    grads = []
+    for reuse in (False, True):
+        r = (rho * 1.3).requires_grad_(True)
+        k = kappa.clone().requires_grad_(True)
+        L = lum.clone().requires_grad_(True)
+        F = P.flux(pos, r, k, L, mass, tree=t if reuse else None)
+        (F.log().sum()).backward()
+        grads.append((F.detach(), r.grad, k.grad, L.grad))
+    for a, b in zip(*grads):
+        assert torch.allclose(a, b, rtol=1e-12, atol=0), "reused tree differs"
