@@ -166,11 +166,17 @@ int trevr_compute_flux(const trevr_tree *tree, double theta_open, double tau_ref
  * returns it for the same arguments) with respect to every particle's rho,
  * kappa and lum, with every accept / open / refine decision of the forward
  * held fixed.  Merged sources contribute through their luminosity and their
- * centre of luminosity.  The traversal is recomputed, not stored.
+ * centre of luminosity.  No segment is stored.  While the tree holds no
+ * recording (trevr_compute_flux_taped) and a tape of one optical depth per
+ * ray fits in half the free device memory, a recording flux and the taped
+ * adjoint run (each ray traced once for tau and once for the scatter), using
+ * the tape as scratch; else one kernel traces every ray twice and a recording
+ * is left as it is.
  *   grad_flux: device, n_sinks.  grad_rho, grad_kappa, grad_lum: device, n
  *   each (overwritten; zero for massless particles' rho and kappa).
- * Uses scratch owned by the tree (allocated on first use, so the first call
- * is not graph-capturable).  Asynchronous.  Errors: TREVR_E_ARG, _STATE, _HIP. */
+ * Uses scratch owned by the tree, allocated on first use and when the tape
+ * grows (such a call is not graph-capturable).  Asynchronous.  Errors:
+ * TREVR_E_ARG, _STATE, _HIP. */
 int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_ref,
                                const int32_t *sinks, int64_t n_sinks, const void *grad_flux,
                                void *grad_rho, void *grad_kappa, void *grad_lum,

@@ -69,7 +69,7 @@ trevr_tree::~trevr_tree() {
                           &n_amax, &n_alpha_min, &n_alpha_max, &n_dalpha, &n_xl, &n_lc,
                           &n_lfar, &keys_in, &keys_out, &vals_in, &vals_out, &sort_tmp, &bfs,
                           &flags, &scan, &err, &box_key, &skeys, &small, &queue, &adj_node,
-                          &adj_part, &adj_heap, &tape, &tape_next, &tape_head, &tape_ctr};
+                          &adj_part, &adj_heap, &adj_flux, &tape, &tape_next, &tape_head, &tape_ctr};
   for (auto *b : all) b->release();
   if (tape_used_h) (void)hipHostFree(tape_used_h);
 }

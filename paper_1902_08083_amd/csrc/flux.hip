@@ -1448,6 +1448,27 @@ int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32
   return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s, flux_vec);
 }
 
+// Blocks for the next recording: what trevr_reserve_tape set, else the last
+// recording's count plus a quarter (and one per set), else a first guess of
+// 1024 rays per sink; `fits` tells whether that fits in half the free device
+// memory (beyond what the tape already holds), and the capacity is cut to
+// what fits.
+static int tape_blocks(trevr_tree *t, int64_t n_sinks, int64_t &cap, bool &fits) {
+  const int64_t sets = (n_sinks + 63) / 64;
+  const int64_t used = t->tape_used_h ? *(volatile int32_t *)t->tape_used_h : 0;
+  cap = t->tape_reserve > 0 ? t->tape_reserve
+                            : used > 0 ? used + used / 4 + sets : sets * 1024 + sets;
+  size_t free_b = 0, total_b = 0;
+  TREVR_HIP(hipMemGetInfo(&free_b, &total_b));
+  const size_t per = 64 * sizeof(double) + sizeof(int32_t);
+  const int64_t fit = (int64_t)((free_b / 2 + t->tape.bytes + t->tape_next.bytes) / per);
+  fits = cap <= fit;
+  if (!fits && t->tape_reserve <= 0) cap = fit;
+  if (cap > INT32_MAX - 65536) cap = INT32_MAX - 65536;
+  if (cap < 1) cap = 1;
+  return TREVR_OK;
+}
+
 // The recording flux: sizes the tape (the last recording's block count plus a
 // quarter, or a first guess of 1024 rays per sink within half the free
 // memory), then records.  A recording that outgrows its tape is left
@@ -1461,21 +1482,13 @@ int flux_taped_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *
     *t->tape_used_h = 0;
   }
   const int64_t sets = (n_sinks + 63) / 64;
-  int64_t cap = t->tape_reserve;
-  if (cap <= 0) {
-    const int64_t used = *(volatile int32_t *)t->tape_used_h;
-    if (used > 0) {
-      cap = used + used / 4 + sets;
-    } else {
-      size_t free_b = 0, total_b = 0;
-      TREVR_HIP(hipMemGetInfo(&free_b, &total_b));
-      cap = sets * 1024 + sets;
-      const int64_t fit = (int64_t)(free_b / 2 / (64 * sizeof(double) + sizeof(int32_t)));
-      if (cap > fit) cap = fit;
-    }
+  int64_t cap = 0;
+  bool fits = true;
+  {
+    int rc = tape_blocks(t, n_sinks, cap, fits);
+    if (rc != TREVR_OK) return rc;
   }
-  if (cap > INT32_MAX - 65536) cap = INT32_MAX - 65536;
-  if (cap < 1) cap = 1;
+  (void)fits;  // a short tape only makes the taped adjoint trace twice
   TREVR_HIP(t->tape.ensure((size_t)cap * 64 * sizeof(double)));
   TREVR_HIP(t->tape_next.ensure((size_t)cap * sizeof(int32_t)));
   TREVR_HIP(t->tape_head.ensure((size_t)(sets > 0 ? sets : 1) * sizeof(int32_t)));
@@ -1536,9 +1549,29 @@ static int adjoint_typed(trevr_tree *t, double theta, double tau_ref, const int3
   return TREVR_OK;
 }
 
+// The adjoint without a recording: while the tree holds no recording of the
+// caller's, a recording flux and the taped adjoint (each ray traced once for
+// tau, once for the scatter, in two kernels) when the tape fits in half the
+// free device memory; else one kernel that traces every ray twice.  A
+// recording of the caller's is left as it is.
 int adjoint_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                  int64_t n_sinks, const void *grad_flux, void *grad_rho, void *grad_kappa,
                  void *grad_lum, hipStream_t s) {
+  if (n_sinks > 0 && !t->tape_ok) {
+    int64_t cap = 0;
+    bool fits = false;
+    int rc = tape_blocks(t, n_sinks, cap, fits);
+    if (rc != TREVR_OK) return rc;
+    if (fits) {
+      const size_t elem = t->prec == TREVR_F64 ? sizeof(double) : sizeof(float);
+      TREVR_HIP(t->adj_flux.ensure(elem * (size_t)n_sinks));
+      rc = flux_taped_impl(t, theta, tau_ref, sinks, n_sinks, t->adj_flux.p, nullptr, s);
+      if (rc == TREVR_OK)
+        rc = adjoint_taped_impl(t, grad_flux, grad_rho, grad_kappa, grad_lum, s);
+      t->tape_ok = false;  // the tape served as scratch
+      return rc;
+    }
+  }
   if (t->prec == TREVR_F64)
     return adjoint_typed<double>(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
                                  grad_kappa, grad_lum, 0, s);

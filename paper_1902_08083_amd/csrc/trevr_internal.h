@@ -150,7 +150,7 @@ struct trevr_tree {
   std::vector<int64_t> level_off, level_cnt;
   // work queue (one counter per XCD) and adjoint scratch
   trevr::DevBuf queue;
-  trevr::DevBuf adj_node, adj_part, adj_heap;
+  trevr::DevBuf adj_node, adj_part, adj_heap, adj_flux;
   // tape of per-ray optical depths from the last recording flux call
   trevr::DevBuf tape, tape_next, tape_head, tape_ctr;
   int64_t tape_cap = 0;             // blocks of 64
