@@ -67,6 +67,9 @@ def lib():
         L.oracle_flux_vec.restype = ctypes.c_int
         L.oracle_flux_vec.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
                                       ctypes.c_int, P, P]
+        L.oracle_flux_moments.restype = ctypes.c_int
+        L.oracle_flux_moments.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
+                                          ctypes.c_int, P, P, P]
         L.oracle_ray_log.restype = ctypes.c_int64
         L.oracle_ray_log.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                      ctypes.c_int64] + [P] * 6
@@ -157,6 +160,20 @@ class OracleTree:
         if rc != 0:
             raise ValueError("oracle_flux_vec rejected its arguments")
         return F, Fv
+
+    def flux_moments(self, theta, tau_ref, sinks=None, nthreads=0):
+        """Return (F, Fv[ns, 3], P[ns, 6]): flux, vector flux and the second
+        moment sum f n_a n_b (xx, yy, zz, xy, xz, yz), in walk order."""
+        s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+        ns = self.n if s is None else int(s.shape[0])
+        F = np.empty(ns, np.float64)
+        Fv = np.empty((ns, 3), np.float64)
+        Pm = np.empty((ns, 6), np.float64)
+        rc = lib().oracle_flux_moments(self._h, float(theta), float(tau_ref), _ptr(s), ns,
+                                       int(nthreads), _ptr(F), _ptr(Fv), _ptr(Pm))
+        if rc != 0:
+            raise ValueError("oracle_flux_moments rejected its arguments")
+        return F, Fv, Pm
 
     def ray_log(self, theta, tau_ref, sink, cap=1 << 20):
         C = np.empty(cap, np.int64)

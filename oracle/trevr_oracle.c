@@ -409,6 +409,7 @@ typedef struct {
   double theta2, tau_ref;
   double F, G;
   double Fv[3]; /* vector flux: sum of f times the unit vector from source to sink */
+  double Pm[6]; /* second moment: sum of f n_a n_b (xx, yy, zz, xy, xz, yz) */
   int64_t n_open, n_rays, n_psrc, n_seg, n_trace;
   /* adjoint accumulators (NULL in a forward pass) */
   double w;
@@ -602,7 +603,17 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
   c->F += f;
   c->G += f * ry.tau;
   /* the ray's direction of travel at the sink, (x_i - y) / r */
-  for (int a = 0; a < 3; ++a) c->Fv[a] += f * (-ry.d[a] / ry.r);
+  double nv[3];
+  for (int a = 0; a < 3; ++a) {
+    nv[a] = -ry.d[a] / ry.r;
+    c->Fv[a] += f * nv[a];
+  }
+  c->Pm[0] += f * (nv[0] * nv[0]);
+  c->Pm[1] += f * (nv[1] * nv[1]);
+  c->Pm[2] += f * (nv[2] * nv[2]);
+  c->Pm[3] += f * (nv[0] * nv[1]);
+  c->Pm[4] += f * (nv[0] * nv[2]);
+  c->Pm[5] += f * (nv[1] * nv[2]);
   if (c->log_C && c->log_n < c->log_cap) {
     int64_t k = c->log_n;
     c->log_C[k] = C;
@@ -749,6 +760,31 @@ int oracle_flux_vec(void *h, double theta, double tau_ref, const int64_t *sinks,
     walk(&c, 0);
     F[q] = c.F;
     for (int a = 0; a < 3; ++a) Fv[3 * q + a] = c.Fv[a];
+  }
+  return 0;
+}
+
+/* Second moment of the intensity (the radiation pressure tensor times c; the
+ * paper notes that such moments follow by simple sums, Sec. 2.1): for each
+ * sink the sum over its rays, in walk order, of f n_a n_b with n the unit
+ * vector from the source point to the sink.  Pm receives 6 per sink (xx, yy,
+ * zz, xy, xz, yz); F and Fv as in oracle_flux_vec. */
+int oracle_flux_moments(void *h, double theta, double tau_ref, const int64_t *sinks,
+                        int64_t ns, int nthreads, double *F, double *Fv, double *Pm) {
+  const otree *t = (const otree *)h;
+  if (!(theta >= 0)) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t q = 0; q < ns; ++q) {
+    int64_t i = sinks ? sinks[q] : q;
+    osink c;
+    sink_init(&c, t, i, theta, tau_ref);
+    walk(&c, 0);
+    F[q] = c.F;
+    for (int a = 0; a < 3; ++a) Fv[3 * q + a] = c.Fv[a];
+    for (int a = 0; a < 6; ++a) Pm[6 * q + a] = c.Pm[a];
   }
   return 0;
 }

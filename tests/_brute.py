@@ -119,6 +119,26 @@ def all_pairs_vector_flux(pos, lum, alpha_const=0.0, sinks=None):
     return out
 
 
+def all_pairs_second_moment(pos, lum, alpha_const=0.0, sinks=None):
+    """P_i = sum_j L_j exp(-alpha r)/(4 pi r^2) n n^T with n = (x_i - x_j)/r, as
+    (xx, yy, zz, xy, xz, yz)."""
+    pos = np.asarray(pos, np.float64)
+    lum = np.asarray(lum, np.float64)
+    src = np.nonzero(lum > 0)[0]
+    sinks = np.arange(pos.shape[0]) if sinks is None else np.asarray(sinks)
+    out = np.zeros((sinks.size, 6))
+    pairs = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+    for q, i in enumerate(sinks):
+        d = pos[i] - pos[src]
+        r2 = np.sum(d * d, axis=1)
+        ok = r2 > 0
+        r = np.sqrt(r2[ok])
+        n = d[ok] / r[:, None]
+        w = lum[src][ok] * np.exp(-alpha_const * r) / (4.0 * math.pi * r2[ok])
+        out[q] = [np.sum(w * n[:, a] * n[:, b]) for a, b in pairs]
+    return out
+
+
 def fibonacci_sphere(m, radius, centre):
     """m points on a sphere by the golden-angle spiral."""
     k = np.arange(m) + 0.5

@@ -94,3 +94,40 @@ def test_merged_sources_from_the_ray_log(theta):
             acc += log["f"][k] * (d[k] / r[k])
         np.testing.assert_allclose(Fv[q], acc, rtol=1e-13, atol=1e-13 * F[q])
         assert np.linalg.norm(Fv[q]) <= F[q] * (1 + 1e-12)
+
+
+# ---- second moment (radiation pressure tensor times c) ----
+
+def test_second_moment_thin_all_pairs_and_trace():
+    pos, rho, kappa, lum, mass = _rand(1000, 66, 150)
+    t = OracleTree(pos, rho, 0 * kappa, lum, mass, bucket_size=8)
+    F, Fv, Pm = t.flux_moments(0.0, 0.1)
+    F1, Fv1 = t.flux_vector(0.0, 0.1)
+    assert np.array_equal(F, F1) and np.array_equal(Fv, Fv1)
+    ref = B.all_pairs_second_moment(pos, lum)
+    assert np.all(np.abs(Pm - ref) <= 1e-13 * F[:, None])
+
+
+@pytest.mark.parametrize("theta,tau_ref", [(0.75, 0.1), (1.0, -1.0)])
+def test_second_moment_trace_is_the_flux(theta, tau_ref):
+    # n is a unit vector: P_xx + P_yy + P_zz = F ray by ray
+    pos, rho, kappa, lum, mass = _rand(3000, 67, 500)
+    t = OracleTree(pos, rho, kappa, lum, mass, bucket_size=8)
+    F, _, Pm = t.flux_moments(theta, tau_ref)
+    assert np.all(np.abs(Pm[:, 0] + Pm[:, 1] + Pm[:, 2] - F) <= 1e-13 * F)
+    # positive semi-definite: P_aa >= 0 and P_aa P_bb >= P_ab^2
+    assert np.all(Pm[:, :3] >= 0)
+    for a, b, k in ((0, 1, 3), (0, 2, 4), (1, 2, 5)):
+        assert np.all(Pm[:, k] ** 2 <= Pm[:, a] * Pm[:, b] * (1 + 1e-12) + 1e-300)
+
+
+def test_second_moment_isotropic_sources():
+    c = np.array([0.5, 0.5, 0.5])
+    h = 0.25
+    src = np.array([c + s * h * e for e in np.eye(3) for s in (1.0, -1.0)])
+    pos = np.vstack([c, src])
+    lum = np.array([0.0] + [1.0] * 6)
+    t = OracleTree(pos, np.ones(7), np.zeros(7), lum, np.ones(7), bucket_size=1)
+    F, _, Pm = t.flux_moments(0.0, 0.1, sinks=[0])
+    np.testing.assert_allclose(Pm[0, :3], F[0] / 3.0, rtol=1e-15)
+    assert np.all(np.abs(Pm[0, 3:]) <= 1e-16 * F[0])
