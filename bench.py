@@ -83,23 +83,30 @@ def counters_run(torch, tree, w):
 
 
 def vector_flux(torch, tree, w, reps=3):
-    """The flux with the vector flux (radiation-pressure direction) on the
-    headline tree: HIP-event time of one call, after one untimed call."""
+    """The flux with the net (vector) flux, and with the vector flux and the
+    second moment (radiation pressure tensor times c), on the headline tree:
+    HIP-event time of one call, after one untimed call."""
     st = torch.cuda.current_stream()
-    tree.flux_vector(w["theta"], w["tau_ref"])
-    torch.cuda.synchronize()
-    ms = []
-    for _ in range(reps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(st)
-        tree.flux_vector(w["theta"], w["tau_ref"])
-        b.record(st)
+
+    def t_of(fn):
+        fn()
         torch.cuda.synchronize()
-        ms.append(a.elapsed_time(b))
-    t = float(np.median(ms))
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            fn()
+            b.record(st)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms))
+
     n = int(w["pos"].shape[0])
-    return {"workload": w["name"], "ms": t, "sink_fluxes_per_s": n / (t * 1e-3)}
+    tv = t_of(lambda: tree.flux_vector(w["theta"], w["tau_ref"]))
+    tm = t_of(lambda: tree.flux_moments(w["theta"], w["tau_ref"]))
+    return {"workload": w["name"], "vector_ms": tv, "vector_sink_fluxes_per_s": n / (tv * 1e-3),
+            "moments_ms": tm, "moments_sink_fluxes_per_s": n / (tm * 1e-3)}
 
 
 def adjoint_ratio(torch, P, reps=3):

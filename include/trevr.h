@@ -196,6 +196,20 @@ int trevr_compute_flux_vector(const trevr_tree *tree, double theta_open, double 
                               const int32_t *sinks, int64_t n_sinks, void *flux, void *flux_vec,
                               int32_t *counters, hipStream_t stream);
 
+/* Flux, net flux and the second moment of the intensity at the sinks: what
+ * trevr_compute_flux_vector computes, and in addition the sum over the sink's
+ * rays, in walk order, of L exp(-tau) / (4 pi r^2) n_a n_b (n as above): the
+ * radiation pressure tensor times c (Sec. 2.1 notes that such higher moments
+ * follow by simple sums).  Its trace is the flux.
+ *   flux_mom: device, 6 x n_sinks, [component][sink] with components xx, yy,
+ *   zz, xy, xz, yz; precision of the tree; NaN for an invalid sink index.
+ * Runs a 3-wave kernel whatever the launch shape (at most 3 waves per SIMD).
+ * Asynchronous, allocates nothing.  Errors: as trevr_compute_flux. */
+int trevr_compute_flux_moments(const trevr_tree *tree, double theta_open, double tau_ref,
+                               const int32_t *sinks, int64_t n_sinks, void *flux,
+                               void *flux_vec, void *flux_mom, int32_t *counters,
+                               hipStream_t stream);
+
 /* The flux and its adjoint with the traversal recorded once.  The recording
  * flux computes exactly what trevr_compute_flux computes (same arguments and
  * errors) and in addition stores every ray's optical depth tau (binary64, in

@@ -173,7 +173,19 @@ int trevr_compute_flux_vector(const trevr_tree *tree, double theta_open, double 
   if (n_sinks > 0 && (!flux || !flux_vec))
     return trevr::fail(TREVR_E_ARG, "flux or flux_vec is NULL");
   return trevr::flux_vec_impl(tree, theta_open, tau_ref, sinks, n_sinks, flux, flux_vec,
-                              counters, stream);
+                              nullptr, counters, stream);
+}
+
+int trevr_compute_flux_moments(const trevr_tree *tree, double theta_open, double tau_ref,
+                               const int32_t *sinks, int64_t n_sinks, void *flux,
+                               void *flux_vec, void *flux_mom, int32_t *counters,
+                               hipStream_t stream) {
+  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (n_sinks > 0 && (!flux || !flux_vec || !flux_mom))
+    return trevr::fail(TREVR_E_ARG, "flux, flux_vec or flux_mom is NULL");
+  return trevr::flux_vec_impl(tree, theta_open, tau_ref, sinks, n_sinks, flux, flux_vec,
+                              flux_mom, counters, stream);
 }
 
 int trevr_compute_flux_taped(trevr_tree *tree, double theta_open, double tau_ref,

@@ -55,7 +55,8 @@ struct FluxArgs {
   int32_t group;     // 64-sink groups per grab
   double theta2, tau_ref;
   T *flux;
-  T *flux_vec;  // [3][n_sinks]: the vector flux (kernel variant with VEC only)
+  T *flux_vec;  // [3][n_sinks]: the vector flux (kernels with MOM >= 1)
+  T *flux_mom;  // [6][n_sinks]: the second moment xx, yy, zz, xy, xz, yz (MOM == 2)
   int32_t *counters;
   int32_t *queue;  // kXcd counters
   // Tape of per-ray optical depths: one block of 64 per round, the blocks of
@@ -747,7 +748,7 @@ constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source,
 // owning sink's context by lane shuffles; each owner adds its results in
 // queue order, so a sink's sum is in its own walk order whatever the other
 // sinks of the wave are.
-template <typename T, bool ADJ, int KS, int KR, int HN, bool VEC = false>
+template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
@@ -875,7 +876,8 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     // grad_flux is indexed like flux: by list position, or by particle
     if (ADJ && valid) wgt = (double)a.grad_flux[a.sinks ? q : (int64_t)a.perm[k]];
     double F = 0.0;
-    double FV[3] = {0.0, 0.0, 0.0};  // vector flux (VEC)
+    double FV[3] = {0.0, 0.0, 0.0};            // vector flux (MOM >= 1)
+    double FP[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // second moment (MOM == 2)
     int n_open = 0, n_rays = 0, n_psrc = 0;
     int qh = 0, qn = 0;  // the queue: first entry, entries (wave-uniform)
     int live = -1;       // the walk's path is s_path[0 .. live]
@@ -915,7 +917,8 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       tk.win = s_anc + owner;
       const double wg = ADJ ? __shfl(wgt, owner) : 0.0;
       double f = 0.0;
-      double fv[3] = {0.0, 0.0, 0.0};  // VEC: f along the ray's direction of travel
+      double fv[3] = {0.0, 0.0, 0.0};  // f along the ray's direction of travel n
+      double fp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // f n_a n_b
       int tblk = -1;     // this round's tape block
       bool rp = false;   // tau from the tape
       if (!ADJ && a.tape_mode == 1) {
@@ -978,8 +981,21 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           trace_pieces<T>(a, C, keyC, depthC, tk, c, ts);
         if (!ADJ && tblk >= 0) a.tape[(int64_t)tblk * 64 + lane] = ts.tau;
         f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
-        if (VEC)
-          for (int q3 = 0; q3 < 3; ++q3) fv[q3] = f * (-c.d[q3] / c.r);
+        if (MOM >= 1) {
+          double nv[3];
+          for (int q3 = 0; q3 < 3; ++q3) {
+            nv[q3] = -c.d[q3] / c.r;
+            fv[q3] = f * nv[q3];
+          }
+          if (MOM == 2) {
+            fp[0] = f * (nv[0] * nv[0]);
+            fp[1] = f * (nv[1] * nv[1]);
+            fp[2] = f * (nv[2] * nv[2]);
+            fp[3] = f * (nv[0] * nv[1]);
+            fp[4] = f * (nv[0] * nv[2]);
+            fp[5] = f * (nv[1] * nv[2]);
+          }
+        }
         if (!ADJ) {
           __hip_atomic_fetch_add(&s_cnt[owner], c.n_seg, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -1074,11 +1090,17 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
             const int got = __builtin_amdgcn_ds_permute(to, in ? 1 : 0);
             double fj = __hiloint2double(hi, lo);
             double fvj[3] = {0.0, 0.0, 0.0};
-            if (VEC)
+            if (MOM >= 1)
               for (int q3 = 0; q3 < 3; ++q3)
                 fvj[q3] = __hiloint2double(
                     __builtin_amdgcn_ds_permute(to, in ? __double2hiint(fv[q3]) : 0),
                     __builtin_amdgcn_ds_permute(to, in ? __double2loint(fv[q3]) : 0));
+            double fpj[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if (MOM == 2)
+              for (int q6 = 0; q6 < 6; ++q6)
+                fpj[q6] = __hiloint2double(
+                    __builtin_amdgcn_ds_permute(to, in ? __double2hiint(fp[q6]) : 0),
+                    __builtin_amdgcn_ds_permute(to, in ? __double2loint(fp[q6]) : 0));
             bool has = got != 0;
             // a later lane outside the run can overwrite lane 63's value
             const uint64_t m63 = __ballot(in && owner == 63);
@@ -1091,18 +1113,27 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                 has = true;
                 fj = f63;
               }
-              if (VEC)
+              if (MOM >= 1)
                 for (int q3 = 0; q3 < 3; ++q3) {
                   const double v63 =
                       __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fv[q3]), j63),
                                        __builtin_amdgcn_readlane(__double2loint(fv[q3]), j63));
                   if (lane == 63) fvj[q3] = v63;
                 }
+              if (MOM == 2)
+                for (int q6 = 0; q6 < 6; ++q6) {
+                  const double v63 =
+                      __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fp[q6]), j63),
+                                       __builtin_amdgcn_readlane(__double2loint(fp[q6]), j63));
+                  if (lane == 63) fpj[q6] = v63;
+                }
             }
             if (has) {
               F += fj;
-              if (VEC)
+              if (MOM >= 1)
                 for (int q3 = 0; q3 < 3; ++q3) FV[q3] += fvj[q3];
+              if (MOM == 2)
+                for (int q6 = 0; q6 < 6; ++q6) FP[q6] += fpj[q6];
             }
           }
         } else {
@@ -1112,12 +1143,19 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                 __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(f), j),
                                  __builtin_amdgcn_readlane(__double2loint(f), j));
             if (lane == oj) F += fj;
-            if (VEC)
+            if (MOM >= 1)
               for (int q3 = 0; q3 < 3; ++q3) {
                 const double vj =
                     __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fv[q3]), j),
                                      __builtin_amdgcn_readlane(__double2loint(fv[q3]), j));
                 if (lane == oj) FV[q3] += vj;
+              }
+            if (MOM == 2)
+              for (int q6 = 0; q6 < 6; ++q6) {
+                const double vj =
+                    __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fp[q6]), j),
+                                     __builtin_amdgcn_readlane(__double2loint(fp[q6]), j));
+                if (lane == oj) FP[q6] += vj;
               }
           }
         }
@@ -1235,9 +1273,12 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       if (in_list) {
         const int64_t out = a.sinks ? q : (int64_t)a.perm[k];
         a.flux[out] = bad ? (T)NAN : (T)F;
-        if (VEC)
+        if (MOM >= 1)
           for (int q3 = 0; q3 < 3; ++q3)
             a.flux_vec[q3 * a.n_sinks + out] = bad ? (T)NAN : (T)FV[q3];
+        if (MOM == 2)
+          for (int q6 = 0; q6 < 6; ++q6)
+            a.flux_mom[q6 * a.n_sinks + out] = bad ? (T)NAN : (T)FP[q6];
         if (a.counters) {
           int32_t *o = a.counters + 5 * out;
           o[0] = bad ? -1 : n_open;
@@ -1269,7 +1310,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4v(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(4, false), occ_kr(4, false), occ_hn(4, false), true>(a);
+  walk_body<T, false, occ_ks(4, false), occ_kr(4, false), occ_hn(4, false), 1>(a);
+}
+// The flux with the vector flux and the second moment, at the 3-wave budget.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3m(
+    FluxArgs<T> a) {
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 2>(a);
 }
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
@@ -1382,6 +1429,14 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   const int64_t need = (a.n_chunks + waves - 1) / waves;
   if (blocks > need) blocks = need;
   if constexpr (!ADJ) {
+    if (a.flux_mom) {  // the moments: the 3-wave kernel, at most 3 waves per SIMD
+      const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
+      int64_t vb = (int64_t)bpc * t->num_cu;
+      if (vb > need) vb = need;
+      k_walk3m<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      TREVR_HIP(hipGetLastError());
+      return TREVR_OK;
+    }
     if (a.flux_vec) {  // the vector flux: the 4-wave kernel, at most 4 waves per SIMD
       const int bpc = L.blocks_per_cu * waves > 16 ? 16 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
@@ -1424,11 +1479,12 @@ static void set_tape(const trevr_tree *t, FluxArgs<T> &a, int mode) {
 template <typename T>
 static int flux_typed(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                       int64_t n_sinks, void *flux, int32_t *counters, int tape_mode,
-                      hipStream_t s, void *flux_vec = nullptr) {
+                      hipStream_t s, void *flux_vec = nullptr, void *flux_mom = nullptr) {
   if (n_sinks == 0) return TREVR_OK;
   FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
   a.flux = static_cast<T *>(flux);
   a.flux_vec = static_cast<T *>(flux_vec);
+  a.flux_mom = static_cast<T *>(flux_mom);
   a.counters = counters;
   set_tape<T, false>(t, a, tape_mode);
   return launch_walk<T, false>(t, a, s);
@@ -1442,10 +1498,13 @@ int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *
 }
 
 int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
-                  int64_t n_sinks, void *flux, void *flux_vec, int32_t *counters, hipStream_t s) {
+                  int64_t n_sinks, void *flux, void *flux_vec, void *flux_mom,
+                  int32_t *counters, hipStream_t s) {
   if (t->prec == TREVR_F64)
-    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s, flux_vec);
-  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s, flux_vec);
+    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s, flux_vec,
+                              flux_mom);
+  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s, flux_vec,
+                           flux_mom);
 }
 
 // Blocks for the next recording: what trevr_reserve_tape set, else the last

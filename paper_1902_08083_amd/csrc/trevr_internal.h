@@ -179,7 +179,8 @@ int adjoint_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sin
                  int64_t n_sinks, const void *grad_flux, void *grad_rho, void *grad_kappa,
                  void *grad_lum, hipStream_t s);
 int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
-                  int64_t n_sinks, void *flux, void *flux_vec, int32_t *counters, hipStream_t s);
+                  int64_t n_sinks, void *flux, void *flux_vec, void *flux_mom,
+                  int32_t *counters, hipStream_t s);
 int flux_taped_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                     int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s);
 int adjoint_taped_impl(trevr_tree *t, const void *grad_flux, void *grad_rho, void *grad_kappa,

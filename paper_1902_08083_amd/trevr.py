@@ -66,7 +66,7 @@ EXPORTED = (
     "trevr_set_launch", "trevr_get_launch", "trevr_set_adjoint_launch",
     "trevr_get_adjoint_launch", "trevr_export_tree", "trevr_compute_flux_taped",
     "trevr_compute_flux_adjoint_taped", "trevr_reserve_tape", "trevr_compute_flux_vector",
-    "trevr_refit_tree",
+    "trevr_refit_tree", "trevr_compute_flux_moments",
 )
 
 
@@ -102,6 +102,8 @@ def lib():
     L.trevr_compute_flux_adjoint_taped.argtypes = [P, P, P, P, P, P]
     L.trevr_refit_tree.restype = I
     L.trevr_refit_tree.argtypes = [P, ctypes.POINTER(_Particles), P]
+    L.trevr_compute_flux_moments.restype = I
+    L.trevr_compute_flux_moments.argtypes = [P, D, D, P, I64, P, P, P, P, P]
     L.trevr_compute_flux_vector.restype = I
     L.trevr_compute_flux_vector.argtypes = [P, D, D, P, I64, P, P, P, P]
     L.trevr_reserve_tape.restype = I
@@ -271,6 +273,20 @@ class Tree:
                                                _ptr(s), ns, _ptr(F), _ptr(Fv), _ptr(C),
                                                _stream()))
         return (F, Fv.t(), C) if counters else (F, Fv.t())
+
+    def flux_moments(self, theta_open, tau_ref, sinks=None, counters=False):
+        """(F, Fv, Pm): flux, vector flux (n_sinks x 3) and the second moment
+        sum f n_a n_b (n_sinks x 6: xx, yy, zz, xy, xz, yz)."""
+        s, ns = self._sinks(sinks)
+        F = torch.empty(ns, dtype=self.dtype, device=self.device)
+        Fv = torch.empty((3, ns), dtype=self.dtype, device=self.device)
+        Pm = torch.empty((6, ns), dtype=self.dtype, device=self.device)
+        C = torch.empty((ns, 5), dtype=torch.int32, device=self.device) if counters else None
+        _check(lib().trevr_compute_flux_moments(self._h, float(theta_open), float(tau_ref),
+                                                _ptr(s), ns, _ptr(F), _ptr(Fv), _ptr(Pm),
+                                                _ptr(C), _stream()))
+        out = (F, Fv.t(), Pm.t())
+        return out + (C,) if counters else out
 
     def adjoint_taped(self, grad_flux):
         """The adjoint for the arguments of the last flux(..., tape=True)."""

@@ -118,5 +118,7 @@ def test_autograd_with_a_reused_tree():
         F = P.flux(pos, r, k, L, mass, tree=t if reuse else None)
         (F.log().sum()).backward()
         grads.append((F.detach(), r.grad, k.grad, L.grad))
+    # gradients are sums of device atomics (order varies): compare to their scale
     for a, b in zip(*grads):
-        assert torch.allclose(a, b, rtol=1e-12, atol=0), "reused tree differs"
+        assert torch.allclose(a, b, rtol=1e-12, atol=1e-12 * float(b.abs().max())), \
+            "reused tree differs"

@@ -6,7 +6,9 @@ sink, summed over the sink's rays) through the C ABI, against the oracle.
   * the scalar flux and counters of the vector call equal the plain call's;
   * six equal sources about a sink cancel;
   * sink subsets with invalid indices (NaN), and launch shapes above four
-    waves per SIMD (the vector kernel then runs at four).
+    waves per SIMD (the vector kernel then runs at four);
+  * the second moment (sum f n_a n_b) against the oracle, its trace equal to
+    the flux, and F/3 on the diagonal for six symmetric sources.
 """
 import os
 
@@ -97,3 +99,54 @@ def test_vector_flux_subset_and_launch_shapes():
     for launch in [(8, 4, 64), (3, 4, 128), (2, 2, 64)]:
         tg.set_launch(*launch)
         assert torch.equal(tg.flux_vector(0.75, 0.1)[1], ref), launch
+
+
+# ---- second moment (radiation pressure tensor times c) ----
+
+@pytest.mark.parametrize("prec,theta,tau_ref", [("f64", 0.75, 0.1), ("f32", 0.75, 0.1),
+                                                ("f64", 0.0, -1.0)])
+def test_second_moment_matches_oracle(prec, theta, tau_ref):
+    _note("second moment %s theta %g tau_ref %g" % (prec, theta, tau_ref))
+    arrs = W.lognormal_box(1 << 13, 400, 8.0, 73)
+    w = W._pack("mom", *arrs, prec=prec)
+    tg = _tree(w)
+    F, Fv, Pm = tg.flux_moments(theta, tau_ref)
+    # another kernel variant: a refined chain piece is deferred or refined at
+    # once depending on the LDS stack room, so tau's summation order (and its
+    # last bits) may differ from the plain call's
+    rt = 1e-12 if prec == "f64" else 3e-7
+    F0 = tg.flux(theta, tau_ref)
+    assert torch.allclose(F, F0, rtol=rt, atol=0)
+    Fv0 = tg.flux_vector(theta, tau_ref)[1]
+    assert float((Fv - Fv0).abs().max(dim=1).values.div(F0).max()) <= rt
+    Fo, Fvo, Pmo = _oracle(w).flux_moments(theta, tau_ref, nthreads=NTHREADS)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    Pm = Pm.double().cpu().numpy()
+    worst = float(np.max(np.abs(Pm - Pmo) / Fo[:, None]))
+    _note("worst |P - oracle| / F = %.3g" % worst)
+    assert worst <= tol
+    # the trace is the flux
+    tr = Pm[:, 0] + Pm[:, 1] + Pm[:, 2]
+    tol_tr = 1e-12 if prec == "f64" else 1e-6
+    assert np.all(np.abs(tr - F.double().cpu().numpy()) <= tol_tr * Fo)
+
+
+def test_second_moment_isotropic_and_launch_shapes():
+    _note("second moment: isotropic sources, launch shapes")
+    c = np.array([0.5, 0.5, 0.5])
+    h = 0.25
+    pos = np.vstack([c] + [c + s * h * e for e in np.eye(3) for s in (1.0, -1.0)])
+    dev = "cuda"
+    d64 = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)  # noqa: E731
+    t = P.build_tree(d64(pos), d64(np.ones(7)), d64(np.zeros(7)), d64([0.0] + [1.0] * 6),
+                     d64(np.ones(7)), bucket_size=1)
+    F, _, Pm = t.flux_moments(0.0, 0.1, sinks=torch.tensor([0], dtype=torch.int32, device=dev))
+    F, Pm = float(F[0]), Pm[0].cpu().numpy()
+    assert np.all(np.abs(Pm[:3] - F / 3.0) <= 1e-15 * F)
+    assert np.all(np.abs(Pm[3:]) <= 1e-16 * F)
+    arrs = W.lognormal_box(4000, 150, 6.0, 74)
+    tg = _tree(W._pack("mom2", *arrs, prec="f32"))
+    ref = tg.flux_moments(0.75, 0.1)[2].clone()
+    for launch in [(8, 4, 64), (4, 4, 64), (1, 1, 128)]:
+        tg.set_launch(*launch)
+        assert torch.equal(tg.flux_moments(0.75, 0.1)[2], ref), launch
