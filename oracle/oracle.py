@@ -70,6 +70,11 @@ def lib():
         L.oracle_flux_moments.restype = ctypes.c_int
         L.oracle_flux_moments.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
                                           ctypes.c_int, P, P, P]
+        L.oracle_set_bands.restype = ctypes.c_int
+        L.oracle_set_bands.argtypes = [P, ctypes.c_int, P]
+        L.oracle_flux_bands.restype = ctypes.c_int
+        L.oracle_flux_bands.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
+                                        ctypes.c_int, P, P]
         L.oracle_ray_log.restype = ctypes.c_int64
         L.oracle_ray_log.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                      ctypes.c_int64] + [P] * 6
@@ -174,6 +179,24 @@ class OracleTree:
         if rc != 0:
             raise ValueError("oracle_flux_moments rejected its arguments")
         return F, Fv, Pm
+
+    def flux_bands(self, theta, tau_ref, kappa_bands, sinks=None, nthreads=0):
+        """Flux per opacity band on one traversal (refined where any band's
+        criterion holds).  kappa_bands: (k, n).  Returns (Fb[ns, k], counters)."""
+        kb = np.ascontiguousarray(kappa_bands, dtype=np.float64)
+        if kb.ndim != 2 or kb.shape[1] != self.n:
+            raise ValueError("kappa_bands must be (k, n)")
+        if lib().oracle_set_bands(self._h, int(kb.shape[0]), _ptr(kb)) != 0:
+            raise ValueError("oracle_set_bands rejected its arguments")
+        s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+        ns = self.n if s is None else int(s.shape[0])
+        Fb = np.empty((ns, kb.shape[0]), np.float64)
+        C = np.empty((ns, 5), np.int64)
+        rc = lib().oracle_flux_bands(self._h, float(theta), float(tau_ref), _ptr(s), ns,
+                                     int(nthreads), _ptr(Fb), _ptr(C))
+        if rc != 0:
+            raise ValueError("oracle_flux_bands rejected its arguments")
+        return Fb, C
 
     def ray_log(self, theta, tau_ref, sink, cap=1 << 20):
         C = np.empty(cap, np.int64)

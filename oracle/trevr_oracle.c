@@ -61,6 +61,11 @@ typedef struct {
   uint64_t *pkey;
   int64_t *perm, *leaf_of;
   onode *nd;
+  /* bands (oracle_set_bands): transport alpha per band and the band-maximum
+   * transport spread, which takes the refinement decisions */
+  int nbands;
+  double *band_alpha; /* [nbands][m] */
+  double *band_dalpha; /* [m] */
 } otree;
 
 static double tr(const otree *t, double v) {
@@ -259,6 +264,88 @@ static void cell_properties(otree *t) {
   }
 }
 
+/* Cell alpha and spread for one opacity field kap (per particle), with the
+ * same sums, inheritance and directional bounds as cell_properties. */
+static void band_properties(const otree *t, const double *kap, double *alpha, double *dalpha) {
+  double *A = (double *)calloc((size_t)t->m, sizeof(double));
+  double *amin = (double *)malloc(3 * (size_t)t->m * sizeof(double));
+  double *amax = (double *)malloc(3 * (size_t)t->m * sizeof(double));
+  for (int64_t id = t->m - 1; id >= 0; --id) {
+    const onode *p = &t->nd[id];
+    if (p->leaf) {
+      for (int64_t k = p->first; k < p->first + p->count; ++k) {
+        int64_t q = t->perm[k];
+        if (t->mass[q] > 0) A[id] += t->mass[q] * kap[q];
+      }
+    } else {
+      A[id] = A[id + 1] + A[p->right];
+    }
+  }
+  for (int64_t id = 0; id < t->m; ++id) {
+    const onode *p = &t->nd[id];
+    if (p->B > 0)
+      alpha[id] = A[id] / p->B;
+    else
+      alpha[id] = (p->parent < 0) ? 0.0 : alpha[p->parent];
+  }
+  for (int64_t id = t->m - 1; id >= 0; --id) {
+    const onode *p = &t->nd[id];
+    double *mn = &amin[3 * id], *mx = &amax[3 * id];
+    if (p->leaf) {
+      for (int b = 0; b < 3; ++b) mn[b] = mx[b] = alpha[id];
+    } else {
+      const double *lmn = &amin[3 * (id + 1)], *lmx = &amax[3 * (id + 1)];
+      const double *rmn = &amin[3 * p->right], *rmx = &amax[3 * p->right];
+      int s = t->axis[p->depth];
+      for (int b = 0; b < 3; ++b) {
+        if (b == s) {
+          mn[b] = 0.5 * (lmn[b] + rmn[b]);
+          mx[b] = 0.5 * (lmx[b] + rmx[b]);
+        } else {
+          mn[b] = lmn[b] < rmn[b] ? lmn[b] : rmn[b];
+          mx[b] = lmx[b] > rmx[b] ? lmx[b] : rmx[b];
+        }
+      }
+    }
+    double lo = mn[0], hi = mx[0];
+    for (int b = 1; b < 3; ++b) {
+      if (mn[b] < lo) lo = mn[b];
+      if (mx[b] > hi) hi = mx[b];
+    }
+    dalpha[id] = hi - lo;
+  }
+  free(A);
+  free(amin);
+  free(amax);
+}
+
+/* Several opacity bands on one traversal (a reading: the paper's method
+ * carries one opacity): band b's cell alpha comes from kappa_b exactly as the
+ * tree's own alpha comes from kappa; a piece is refined where any band's
+ * criterion asks for it, (max_b spread_b) l > tau_ref, so every band meets
+ * eq. (refcrit).  kappa_bands: [k][n], k <= 8. */
+int oracle_set_bands(void *h, int k, const double *kappa_bands) {
+  otree *t = (otree *)h;
+  if (k < 1 || k > 8) return -1;
+  free(t->band_alpha);
+  free(t->band_dalpha);
+  t->nbands = k;
+  t->band_alpha = (double *)malloc((size_t)k * (size_t)t->m * sizeof(double));
+  t->band_dalpha = (double *)calloc((size_t)t->m, sizeof(double));
+  double *da = (double *)malloc((size_t)t->m * sizeof(double));
+  for (int b = 0; b < k; ++b) {
+    double *al = t->band_alpha + (size_t)b * (size_t)t->m;
+    band_properties(t, kappa_bands + (size_t)b * (size_t)t->n, al, da);
+    for (int64_t id = 0; id < t->m; ++id) {
+      al[id] = tr(t, al[id]);
+      const double d = tr(t, da[id]);
+      if (d > t->band_dalpha[id]) t->band_dalpha[id] = d;
+    }
+  }
+  free(da);
+  return 0;
+}
+
 void oracle_free(void *h) {
   otree *t = (otree *)h;
   if (!t) return;
@@ -271,6 +358,8 @@ void oracle_free(void *h) {
   free(t->perm);
   free(t->leaf_of);
   free(t->nd);
+  free(t->band_alpha);
+  free(t->band_dalpha);
   free(t);
 }
 
@@ -398,6 +487,7 @@ typedef struct {
 typedef struct {
   double d[3], inv[3], r2, r;
   double tau;
+  double tau_b[8]; /* per band (band mode) */
   int nseg, cap;
   oseg *seg;
 } oray;
@@ -410,6 +500,8 @@ typedef struct {
   double F, G;
   double Fv[3]; /* vector flux: sum of f times the unit vector from source to sink */
   double Pm[6]; /* second moment: sum of f n_a n_b (xx, yy, zz, xy, xz, yz) */
+  int bands;     /* band mode: per-band tau and flux, band-maximum spread */
+  double Fb[8];
   int64_t n_open, n_rays, n_psrc, n_seg, n_trace;
   /* adjoint accumulators (NULL in a forward pass) */
   double w;
@@ -424,12 +516,20 @@ typedef struct {
   double *log_y, *log_L, *log_tau, *log_f;
 } osink;
 
+/* the spread (alpha_max - alpha_min) that takes a cell's refinement decision */
+static double spread(const osink *c, int64_t X) {
+  return c->bands ? c->t->band_dalpha[X] : c->t->nd[X].t_dalpha;
+}
+
 /* one alpha * l term of eq. (tausum) */
 static void add_piece(osink *c, oray *ry, int64_t node, double ta, int taga,
                       double tb, int tagb, double l) {
   double alpha = c->t->nd[node].t_alpha;
   if (l > 0) c->n_seg++;
   ry->tau += alpha * l;
+  if (c->bands)
+    for (int b = 0; b < c->t->nbands; ++b)
+      ry->tau_b[b] += c->t->band_alpha[(size_t)b * (size_t)c->t->m + (size_t)node] * l;
   if (c->abar || (c->piece_node && c->log_n == c->piece_ray)) {
     if (ry->nseg == ry->cap) {
       ry->cap = ry->cap ? 2 * ry->cap : 32;
@@ -456,7 +556,7 @@ static void refine(osink *c, oray *ry, int64_t X, double ta, int taga,
   const onode *p = &t->nd[X];
   double l = ry->r * (tb - ta);
   c->n_trace++;
-  if (p->leaf || !(p->t_dalpha * l > c->tau_ref)) {
+  if (p->leaf || !(spread(c, X) * l > c->tau_ref)) {
     add_piece(c, ry, X, ta, taga, tb, tagb, l);
     return;
   }
@@ -494,7 +594,7 @@ static void chain_piece(osink *c, oray *ry, int64_t P, int64_t X, double ta,
                         int taga, double tb, int tagb) {
   double l = ry->r * (tb - ta);
   c->n_trace++;
-  if (c->t->nd[P].t_dalpha * l > c->tau_ref) {
+  if (spread(c, P) * l > c->tau_ref) {
     refine(c, ry, X, ta, taga, tb, tagb);
     return;
   }
@@ -602,6 +702,9 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
   double f = (L * exp(-ry.tau)) / ((4.0 * M_PI) * ry.r2);
   c->F += f;
   c->G += f * ry.tau;
+  if (c->bands)
+    for (int b = 0; b < t->nbands; ++b)
+      c->Fb[b] += (L * exp(-ry.tau_b[b])) / ((4.0 * M_PI) * ry.r2);
   /* the ray's direction of travel at the sink, (x_i - y) / r */
   double nv[3];
   for (int a = 0; a < 3; ++a) {
@@ -785,6 +888,34 @@ int oracle_flux_moments(void *h, double theta, double tau_ref, const int64_t *si
     F[q] = c.F;
     for (int a = 0; a < 3; ++a) Fv[3 * q + a] = c.Fv[a];
     for (int a = 0; a < 6; ++a) Pm[6 * q + a] = c.Pm[a];
+  }
+  return 0;
+}
+
+/* Flux per band (oracle_set_bands first): Fb receives nbands per sink; the
+ * counters are those of the band traversal. */
+int oracle_flux_bands(void *h, double theta, double tau_ref, const int64_t *sinks,
+                      int64_t ns, int nthreads, double *Fb, int64_t *counters) {
+  const otree *t = (const otree *)h;
+  if (!(theta >= 0) || t->nbands < 1) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t q = 0; q < ns; ++q) {
+    int64_t i = sinks ? sinks[q] : q;
+    osink c;
+    sink_init(&c, t, i, theta, tau_ref);
+    c.bands = 1;
+    walk(&c, 0);
+    for (int b = 0; b < t->nbands; ++b) Fb[(size_t)t->nbands * (size_t)q + b] = c.Fb[b];
+    if (counters) {
+      counters[5 * q + 0] = c.n_open;
+      counters[5 * q + 1] = c.n_rays;
+      counters[5 * q + 2] = c.n_psrc;
+      counters[5 * q + 3] = c.n_seg;
+      counters[5 * q + 4] = c.n_trace;
+    }
   }
   return 0;
 }
