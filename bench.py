@@ -109,6 +109,34 @@ def vector_flux(torch, tree, w, reps=3):
             "moments_ms": tm, "moments_sink_fluxes_per_s": n / (tm * 1e-3)}
 
 
+def bands(torch, tree, w, reps=3):
+    """Three opacity bands (kappa scaled by 0.3, 1 and 3) on the headline tree:
+    time to set them, and HIP-event time of one band flux call."""
+    st = torch.cuda.current_stream()
+    kap = torch.as_tensor(w["kappa"], device="cuda")
+    kb = torch.stack([0.3 * kap, kap, 3.0 * kap]).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree.set_bands(kb)
+    torch.cuda.synchronize()
+    set_ms = (time.perf_counter() - t0) * 1e3
+    tree.flux_bands(w["theta"], w["tau_ref"])
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        tree.flux_bands(w["theta"], w["tau_ref"])
+        b.record(st)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    t = float(np.median(ms))
+    n = int(w["pos"].shape[0])
+    return {"workload": w["name"], "n_bands": 3, "set_bands_ms": set_ms, "ms": t,
+            "sink_fluxes_per_s": n / (t * 1e-3)}
+
+
 def adjoint_ratio(torch, P, reps=3):
     from paper_1902_08083_amd import workloads as W
     w = W.c5()
@@ -311,6 +339,9 @@ def main():
     if not args.no_vector:
         log("vector flux on the same workload")
         out["vector_flux"] = vector_flux(torch, tree, w)
+    if not args.no_vector:
+        log("three opacity bands on the same workload")
+        out["bands"] = bands(torch, tree, w)
     if not args.no_adjoint:
         log("adjoint ratio on the 2^20 workload")
         out["adjoint"] = adjoint_ratio(torch, P)

@@ -210,6 +210,30 @@ int trevr_compute_flux_moments(const trevr_tree *tree, double theta_open, double
                                void *flux_vec, void *flux_mom, int32_t *counters,
                                hipStream_t stream);
 
+/* Several opacity bands on one traversal (a reading: the paper carries one
+ * opacity; this is the frequency-band extension of the same walk).  Band b's
+ * cell alpha and directional spread come from its opacity field exactly as
+ * the tree's own come from kappa (Sec. 2.2.3, eqs. for alpha and the spread;
+ * the density weights are the tree's).  A piece is refined where the largest
+ * band spread asks for it, (max_b (alpha_max - alpha_min)_b) l > tau_ref
+ * (eq. refcrit), so every band meets the criterion; each band sums its own
+ * tau_b and flux L exp(-tau_b) / (4 pi r^2).  One band equal to the tree's
+ * kappa gives trevr_compute_flux's result up to summation order.
+ * trevr_set_bands: kappa_bands device [n_bands][n], per particle in input
+ * order, precision of the tree, finite and >= 0; 1 <= n_bands <= 4.  Waits on
+ * `stream`.  Errors: TREVR_E_ARG, _STATE, _NONFINITE, _VALUE, _HIP.  A build
+ * or a refit drops the bands.
+ * trevr_compute_flux_bands: flux_bands device [n_bands][n_sinks], precision
+ * of the tree (NaN for an invalid sink index); counters as trevr_compute_flux
+ * (of the band traversal).  Runs a 3-wave kernel whatever the launch shape.
+ * Asynchronous, allocates nothing.  Errors: as trevr_compute_flux, and
+ * TREVR_E_STATE if no bands are set. */
+int trevr_set_bands(trevr_tree *tree, int32_t n_bands, const void *kappa_bands,
+                    hipStream_t stream);
+int trevr_compute_flux_bands(const trevr_tree *tree, double theta_open, double tau_ref,
+                             const int32_t *sinks, int64_t n_sinks, void *flux_bands,
+                             int32_t *counters, hipStream_t stream);
+
 /* The flux and its adjoint with the traversal recorded once.  The recording
  * flux computes exactly what trevr_compute_flux computes (same arguments and
  * errors) and in addition stores every ray's optical depth tau (binary64, in

@@ -69,7 +69,9 @@ trevr_tree::~trevr_tree() {
                           &n_amax, &n_alpha_min, &n_alpha_max, &n_dalpha, &n_xl, &n_lc,
                           &n_lfar, &keys_in, &keys_out, &vals_in, &vals_out, &sort_tmp, &bfs,
                           &flags, &scan, &err, &box_key, &skeys, &small, &queue, &adj_node,
-                          &adj_part, &adj_heap, &adj_flux, &tape, &tape_next, &tape_head, &tape_ctr};
+                          &adj_part, &adj_heap, &adj_flux, &tape, &tape_next, &tape_head, &tape_ctr,
+                          &band_alpha, &band_dmax, &band_trace, &bs_A, &bs_alpha, &bs_amin,
+                          &bs_amax, &bs_amin_d, &bs_amax_d, &bs_dalpha};
   for (auto *b : all) b->release();
   if (tape_used_h) (void)hipHostFree(tape_used_h);
 }
@@ -124,6 +126,26 @@ int trevr_build_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t str
   int rc = trevr::check_particles(p);
   if (rc != TREVR_OK) return rc;
   return trevr::build_tree_impl(tree, p, stream);
+}
+
+int trevr_set_bands(trevr_tree *tree, int32_t n_bands, const void *kappa_bands,
+                    hipStream_t stream) {
+  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
+  if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");
+  if (n_bands < 1 || n_bands > 4) return trevr::fail(TREVR_E_ARG, "n_bands must be 1..4");
+  if (tree->n > 0 && !kappa_bands) return trevr::fail(TREVR_E_ARG, "kappa_bands is NULL");
+  return trevr::bands_impl(tree, n_bands, kappa_bands, stream);
+}
+
+int trevr_compute_flux_bands(const trevr_tree *tree, double theta_open, double tau_ref,
+                             const int32_t *sinks, int64_t n_sinks, void *flux_bands,
+                             int32_t *counters, hipStream_t stream) {
+  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (tree->n_bands < 1) return trevr::fail(TREVR_E_STATE, "no bands set on this tree");
+  if (n_sinks > 0 && !flux_bands) return trevr::fail(TREVR_E_ARG, "flux_bands is NULL");
+  return trevr::flux_bands_impl(tree, theta_open, tau_ref, sinks, n_sinks, flux_bands, counters,
+                                stream);
 }
 
 int trevr_refit_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream) {

@@ -57,6 +57,11 @@ struct FluxArgs {
   T *flux;
   T *flux_vec;  // [3][n_sinks]: the vector flux (kernels with MOM >= 1)
   T *flux_mom;  // [6][n_sinks]: the second moment xx, yy, zz, xy, xz, yz (MOM == 2)
+  // opacity bands (kernels with NBND > 0): a.TR then carries the largest band
+  // spread; each band's cell alpha is band_alpha[b][cell]
+  const T *__restrict__ band_alpha;
+  int32_t n_bands;
+  T *flux_bands;  // [n_bands][n_sinks]
   int32_t *counters;
   int32_t *queue;  // kXcd counters
   // Tape of per-ray optical depths: one block of 64 per round, the blocks of
@@ -227,6 +232,23 @@ struct TauSum {
 // The same sum in the adjoint's first pass.
 struct TauSumA : TauSum {
   static constexpr bool kLight = true;
+};
+
+// Band policy: one tau per opacity band; a piece's alpha is that band's cell
+// value (the record's own alpha is not used).
+constexpr int kMaxBands = 4;
+template <typename T>
+struct BandSum {
+  static constexpr bool kLight = false;
+  const T *ba;
+  int64_t m;
+  int nb;
+  double tau[kMaxBands] = {0.0, 0.0, 0.0, 0.0};
+  __device__ __forceinline__ void operator()(int node, int, double, double l, double, int,
+                                             double, int) {
+    for (int b = 0; b < kMaxBands; ++b)
+      if (b < nb) tau[b] += (double)ba[(int64_t)b * m + node] * l;
+  }
 };
 
 // Adjoint policy: d loss / d alpha_cell += -g l, and d tau / d y gets
@@ -748,7 +770,7 @@ constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source,
 // owning sink's context by lane shuffles; each owner adds its results in
 // queue order, so a sink's sum is in its own walk order whatever the other
 // sinks of the wave are.
-template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0>
+template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0, int NBND = 0>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
@@ -878,6 +900,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     double F = 0.0;
     double FV[3] = {0.0, 0.0, 0.0};            // vector flux (MOM >= 1)
     double FP[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // second moment (MOM == 2)
+    double FB[kMaxBands] = {0.0, 0.0, 0.0, 0.0};      // flux per band (NBND > 0)
     int n_open = 0, n_rays = 0, n_psrc = 0;
     int qh = 0, qn = 0;  // the queue: first entry, entries (wave-uniform)
     int live = -1;       // the walk's path is s_path[0 .. live]
@@ -919,6 +942,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       double f = 0.0;
       double fv[3] = {0.0, 0.0, 0.0};  // f along the ray's direction of travel n
       double fp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // f n_a n_b
+      double fb[kMaxBands] = {0.0, 0.0, 0.0, 0.0};      // f per band
       int tblk = -1;     // this round's tape block
       bool rp = false;   // tau from the tape
       if (!ADJ && a.tape_mode == 1) {
@@ -975,10 +999,20 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         c.n_trace = 0;
         ray_setup(c, (double)yx, (double)yy, (double)yz);
         std::conditional_t<ADJ, TauSumA, TauSum> ts;
-        if (rp)
+        if constexpr (NBND > 0) {  // one traversal, one tau per band
+          BandSum<T> bsum;
+          bsum.ba = a.band_alpha;
+          bsum.m = a.m;
+          bsum.nb = a.n_bands;
+          trace_pieces<T>(a, C, keyC, depthC, tk, c, bsum);
+          for (int b = 0; b < kMaxBands; ++b)
+            if (b < a.n_bands)
+              fb[b] = ((double)L * exp(-bsum.tau[b])) / ((4.0 * M_PI) * c.r2);
+        } else if (rp) {
           ts.tau = tau_rec;
-        else
+        } else {
           trace_pieces<T>(a, C, keyC, depthC, tk, c, ts);
+        }
         if (!ADJ && tblk >= 0) a.tape[(int64_t)tblk * 64 + lane] = ts.tau;
         f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
         if (MOM >= 1) {
@@ -1095,6 +1129,12 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                 fvj[q3] = __hiloint2double(
                     __builtin_amdgcn_ds_permute(to, in ? __double2hiint(fv[q3]) : 0),
                     __builtin_amdgcn_ds_permute(to, in ? __double2loint(fv[q3]) : 0));
+            double fbj[kMaxBands] = {0.0, 0.0, 0.0, 0.0};
+            if (NBND > 0)
+              for (int b = 0; b < kMaxBands; ++b)
+                fbj[b] = __hiloint2double(
+                    __builtin_amdgcn_ds_permute(to, in ? __double2hiint(fb[b]) : 0),
+                    __builtin_amdgcn_ds_permute(to, in ? __double2loint(fb[b]) : 0));
             double fpj[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if (MOM == 2)
               for (int q6 = 0; q6 < 6; ++q6)
@@ -1120,6 +1160,13 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                                        __builtin_amdgcn_readlane(__double2loint(fv[q3]), j63));
                   if (lane == 63) fvj[q3] = v63;
                 }
+              if (NBND > 0)
+                for (int b = 0; b < kMaxBands; ++b) {
+                  const double v63 =
+                      __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fb[b]), j63),
+                                       __builtin_amdgcn_readlane(__double2loint(fb[b]), j63));
+                  if (lane == 63) fbj[b] = v63;
+                }
               if (MOM == 2)
                 for (int q6 = 0; q6 < 6; ++q6) {
                   const double v63 =
@@ -1134,6 +1181,8 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                 for (int q3 = 0; q3 < 3; ++q3) FV[q3] += fvj[q3];
               if (MOM == 2)
                 for (int q6 = 0; q6 < 6; ++q6) FP[q6] += fpj[q6];
+              if (NBND > 0)
+                for (int b = 0; b < kMaxBands; ++b) FB[b] += fbj[b];
             }
           }
         } else {
@@ -1149,6 +1198,13 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                     __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fv[q3]), j),
                                      __builtin_amdgcn_readlane(__double2loint(fv[q3]), j));
                 if (lane == oj) FV[q3] += vj;
+              }
+            if (NBND > 0)
+              for (int b = 0; b < kMaxBands; ++b) {
+                const double vj =
+                    __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(fb[b]), j),
+                                     __builtin_amdgcn_readlane(__double2loint(fb[b]), j));
+                if (lane == oj) FB[b] += vj;
               }
             if (MOM == 2)
               for (int q6 = 0; q6 < 6; ++q6) {
@@ -1272,13 +1328,16 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       wave_sync();
       if (in_list) {
         const int64_t out = a.sinks ? q : (int64_t)a.perm[k];
-        a.flux[out] = bad ? (T)NAN : (T)F;
+        if (NBND == 0) a.flux[out] = bad ? (T)NAN : (T)F;  // the band kernel has no flux
         if (MOM >= 1)
           for (int q3 = 0; q3 < 3; ++q3)
             a.flux_vec[q3 * a.n_sinks + out] = bad ? (T)NAN : (T)FV[q3];
         if (MOM == 2)
           for (int q6 = 0; q6 < 6; ++q6)
             a.flux_mom[q6 * a.n_sinks + out] = bad ? (T)NAN : (T)FP[q6];
+        if (NBND > 0)
+          for (int b = 0; b < kMaxBands; ++b)
+            if (b < a.n_bands) a.flux_bands[b * a.n_sinks + out] = bad ? (T)NAN : (T)FB[b];
         if (a.counters) {
           int32_t *o = a.counters + 5 * out;
           o[0] = bad ? -1 : n_open;
@@ -1311,6 +1370,12 @@ template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4v(
     FluxArgs<T> a) {
   walk_body<T, false, occ_ks(4, false), occ_kr(4, false), occ_hn(4, false), 1>(a);
+}
+// The flux per opacity band, at the 3-wave budget.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3b(
+    FluxArgs<T> a) {
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, kMaxBands>(a);
 }
 // The flux with the vector flux and the second moment, at the 3-wave budget.
 template <typename T>
@@ -1429,6 +1494,14 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   const int64_t need = (a.n_chunks + waves - 1) / waves;
   if (blocks > need) blocks = need;
   if constexpr (!ADJ) {
+    if (a.flux_bands) {  // the bands: the 3-wave kernel, at most 3 waves per SIMD
+      const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
+      int64_t vb = (int64_t)bpc * t->num_cu;
+      if (vb > need) vb = need;
+      k_walk3b<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      TREVR_HIP(hipGetLastError());
+      return TREVR_OK;
+    }
     if (a.flux_mom) {  // the moments: the 3-wave kernel, at most 3 waves per SIMD
       const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
@@ -1495,6 +1568,27 @@ int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *
   if (t->prec == TREVR_F64)
     return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s);
   return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s);
+}
+
+template <typename T>
+static int flux_bands_typed(const trevr_tree *t, double theta, double tau_ref,
+                            const int32_t *sinks, int64_t n_sinks, void *flux_bands,
+                            int32_t *counters, hipStream_t s) {
+  if (n_sinks == 0) return TREVR_OK;
+  FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
+  a.TR = static_cast<const TraceRecT<T> *>(t->band_trace.p);  // largest band spread
+  a.band_alpha = t->band_alpha.as<T>();
+  a.n_bands = t->n_bands;
+  a.flux_bands = static_cast<T *>(flux_bands);
+  a.counters = counters;
+  return launch_walk<T, false>(t, a, s);
+}
+
+int flux_bands_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                    int64_t n_sinks, void *flux_bands, int32_t *counters, hipStream_t s) {
+  if (t->prec == TREVR_F64)
+    return flux_bands_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux_bands, counters, s);
+  return flux_bands_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux_bands, counters, s);
 }
 
 int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,

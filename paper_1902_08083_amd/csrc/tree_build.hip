@@ -697,6 +697,130 @@ static int build_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   return TREVR_OK;
 }
 
+// ---- opacity bands ----------------------------------------------------------
+// Band b's cell alpha and spread come from its opacity field exactly as the
+// tree's own do from kappa (the same sums in the same order, B = sum m/rho
+// shared); a trace record copy carries the largest band spread, which takes
+// the refinement decisions.
+template <typename T>
+__global__ void k_band_bucket(const BfsNode *lvl, int cnt, const T *pmass, const T *kap,
+                              const int32_t *perm, double *A) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt) return;
+  const BfsNode nd = lvl[j];
+  if (nd.child >= 0) return;
+  double a = 0;
+  for (int k = nd.first; k < nd.first + nd.count; ++k) {
+    double m = (double)pmass[k];
+    if (m > 0) a += m * (double)kap[perm[k]];
+  }
+  A[nd.pre] = a;
+}
+
+__global__ void k_band_internal(const BfsNode *lvl, int cnt, const int32_t *right, double *A) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt) return;
+  const BfsNode nd = lvl[j];
+  if (nd.child < 0) return;
+  int p = nd.pre;
+  A[p] = A[p + 1] + A[right[p]];
+}
+
+template <typename T>
+__global__ void k_band_pack(const double *alpha, const double *dalpha, int64_t m, int first,
+                            T *band_alpha, double *dmax) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  band_alpha[p] = (T)alpha[p];
+  const double d = (double)(T)dalpha[p];
+  dmax[p] = first || d > dmax[p] ? d : dmax[p];
+}
+
+template <typename T>
+__global__ void k_band_records(const TraceRecT<T> *TR, const double *dmax, int64_t m,
+                               TraceRecT<T> *out) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  TraceRecT<T> r = TR[p];
+  r.dalpha = (T)dmax[p];
+  out[p] = r;
+}
+
+template <typename T>
+__global__ void k_band_check(const T *kap, int64_t count, int *err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double k = (double)kap[i];
+  if (!isfinite(k))
+    atomicOr(err, ERR_NONFINITE);
+  else if (k < 0)
+    atomicOr(err, ERR_VALUE);
+}
+
+template <typename T>
+static int bands_typed(trevr_tree *t, int nb, const T *kb, hipStream_t s) {
+  const int64_t n = t->n, m = t->m;
+  const size_t mm = (size_t)(m > 0 ? m : 1);
+  TREVR_HIP(hipMemsetAsync(t->err.p, 0, 4, s));
+  if (n > 0) k_band_check<T><<<nblk(n * nb), 256, 0, s>>>(kb, n * nb, t->err.as<int>());
+  TREVR_HIP(hipGetLastError());
+  int herr = 0;
+  TREVR_HIP(hipMemcpyAsync(&herr, t->err.p, 4, hipMemcpyDeviceToHost, s));
+  TREVR_HIP(hipStreamSynchronize(s));
+  if (herr & ERR_NONFINITE) return fail(TREVR_E_NONFINITE, "non-finite band opacity");
+  if (herr & ERR_VALUE) return fail(TREVR_E_VALUE, "negative band opacity");
+  TREVR_HIP(t->band_alpha.ensure(sizeof(T) * mm * nb));
+  TREVR_HIP(t->band_dmax.ensure(8 * mm));
+  TREVR_HIP(t->band_trace.ensure(sizeof(TraceRecT<T>) * mm));
+  DevBuf *scr[] = {&t->bs_A, &t->bs_alpha, &t->bs_amin_d, &t->bs_amax_d, &t->bs_dalpha};
+  for (DevBuf *b : scr) TREVR_HIP(b->ensure(8 * mm));
+  TREVR_HIP(t->bs_amin.ensure(24 * mm));
+  TREVR_HIP(t->bs_amax.ensure(24 * mm));
+  // the build's topology and B; band scratch for everything kappa touches
+  Props P{t->bs_A.as<double>(),     t->n_B.as<double>(),      nullptr,
+          nullptr,                  t->bs_alpha.as<double>(), t->bs_amin.as<double>(),
+          t->bs_amax.as<double>(),  t->bs_amin_d.as<double>(), t->bs_amax_d.as<double>(),
+          t->bs_dalpha.as<double>(), nullptr,                  nullptr,
+          nullptr,                  t->n_first.as<int32_t>(), t->n_count.as<int32_t>(),
+          t->n_right.as<int32_t>(), t->n_parent.as<int32_t>(), t->n_depth.as<int32_t>(),
+          t->n_axis.as<int8_t>(),   t->n_lo.as<double>(),     t->n_hi.as<double>(),
+          m};
+  const int nlev = (int)t->level_cnt.size();
+  const BfsNode *bfs = t->bfs.as<BfsNode>();
+  for (int b = 0; b < nb; ++b) {
+    const T *kap = kb + (size_t)b * (size_t)n;
+    for (int d = nlev - 1; d >= 0; --d) {
+      const BfsNode *lvl = bfs + t->level_off[d];
+      int c = (int)t->level_cnt[d];
+      k_band_bucket<T><<<nblk(c), 256, 0, s>>>(lvl, c, t->pmass.as<T>(), kap,
+                                               t->perm.as<int32_t>(), P.A);
+      k_band_internal<<<nblk(c), 256, 0, s>>>(lvl, c, P.right, P.A);
+    }
+    for (int d = 0; d < nlev; ++d)
+      k_alpha<<<nblk(t->level_cnt[d]), 256, 0, s>>>(bfs + t->level_off[d],
+                                                     (int)t->level_cnt[d], P);
+    for (int d = nlev - 1; d >= 0; --d)
+      k_bounds<<<nblk(t->level_cnt[d]), 256, 0, s>>>(bfs + t->level_off[d],
+                                                      (int)t->level_cnt[d], P);
+    k_band_pack<T><<<nblk(m), 256, 0, s>>>(P.alpha, P.dalpha, m, b == 0,
+                                           t->band_alpha.as<T>() + (size_t)b * (size_t)m,
+                                           t->band_dmax.as<double>());
+  }
+  k_band_records<T><<<nblk(m), 256, 0, s>>>(t->trace.as<TraceRecT<T>>(),
+                                            t->band_dmax.as<double>(), m,
+                                            t->band_trace.as<TraceRecT<T>>());
+  TREVR_HIP(hipGetLastError());
+  TREVR_HIP(hipStreamSynchronize(s));
+  t->n_bands = nb;
+  return TREVR_OK;
+}
+
+int bands_impl(trevr_tree *t, int nb, const void *kb, hipStream_t s) {
+  t->n_bands = 0;
+  if (t->prec == TREVR_F64) return bands_typed<double>(t, nb, (const double *)kb, s);
+  return bands_typed<float>(t, nb, (const float *)kb, s);
+}
+
 // Refit: new mass, rho, kappa and lum on the positions of the build.  Each
 // particle's position must equal, value for value, the one the tree was built
 // from (then every key, and the whole topology, is unchanged); the values are
@@ -745,6 +869,7 @@ static int refit_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
 
 int refit_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   t->tape_ok = false;
+  t->n_bands = 0;
   if (t->prec == TREVR_F64) return refit_typed<double>(t, p, s);
   return refit_typed<float>(t, p, s);
 }
@@ -752,6 +877,7 @@ int refit_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
 int build_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   t->built = false;
   t->tape_ok = false;
+  t->n_bands = 0;
   if (p->prec == TREVR_F64) return build_typed<double>(t, p, s);
   return build_typed<float>(t, p, s);
 }

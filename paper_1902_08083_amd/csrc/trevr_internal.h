@@ -151,6 +151,11 @@ struct trevr_tree {
   // work queue (one counter per XCD) and adjoint scratch
   trevr::DevBuf queue;
   trevr::DevBuf adj_node, adj_part, adj_heap, adj_flux;
+  // opacity bands (trevr_set_bands): per band cell alpha [n_bands][m] in the
+  // transport precision, the largest band spread, trace records carrying it
+  int32_t n_bands = 0;
+  trevr::DevBuf band_alpha, band_dmax, band_trace;
+  trevr::DevBuf bs_A, bs_alpha, bs_amin, bs_amax, bs_amin_d, bs_amax_d, bs_dalpha;
   // tape of per-ray optical depths from the last recording flux call
   trevr::DevBuf tape, tape_next, tape_head, tape_ctr;
   int64_t tape_cap = 0;             // blocks of 64
@@ -171,6 +176,9 @@ int hip_fail(hipError_t e, const char *what);
 
 int build_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s);
 int refit_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s);
+int bands_impl(trevr_tree *t, int nb, const void *kappa_bands, hipStream_t s);
+int flux_bands_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                    int64_t n_sinks, void *flux_bands, int32_t *counters, hipStream_t s);
 int export_tree_impl(const trevr_tree *t, int64_t *perm, int64_t *leaf_of, int64_t *node_i,
                      uint64_t *node_key, double *node_f, hipStream_t s);
 int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,

@@ -66,7 +66,8 @@ EXPORTED = (
     "trevr_set_launch", "trevr_get_launch", "trevr_set_adjoint_launch",
     "trevr_get_adjoint_launch", "trevr_export_tree", "trevr_compute_flux_taped",
     "trevr_compute_flux_adjoint_taped", "trevr_reserve_tape", "trevr_compute_flux_vector",
-    "trevr_refit_tree", "trevr_compute_flux_moments",
+    "trevr_refit_tree", "trevr_compute_flux_moments", "trevr_set_bands",
+    "trevr_compute_flux_bands",
 )
 
 
@@ -102,6 +103,10 @@ def lib():
     L.trevr_compute_flux_adjoint_taped.argtypes = [P, P, P, P, P, P]
     L.trevr_refit_tree.restype = I
     L.trevr_refit_tree.argtypes = [P, ctypes.POINTER(_Particles), P]
+    L.trevr_set_bands.restype = I
+    L.trevr_set_bands.argtypes = [P, ctypes.c_int32, P, P]
+    L.trevr_compute_flux_bands.restype = I
+    L.trevr_compute_flux_bands.argtypes = [P, D, D, P, I64, P, P, P]
     L.trevr_compute_flux_moments.restype = I
     L.trevr_compute_flux_moments.argtypes = [P, D, D, P, I64, P, P, P, P, P]
     L.trevr_compute_flux_vector.restype = I
@@ -171,6 +176,7 @@ class Tree:
                                   box_offsets, device)
         _check(lib().trevr_build_tree(self._h, ctypes.byref(p), _stream()))
         self._layout = (box_lo, box_hi, bucket_size, box_offsets)
+        self._n_bands = 0  # a build drops the bands
         self.n = p.n
         self.dtype = keep[0].dtype
         self.prec = p.prec
@@ -185,6 +191,7 @@ class Tree:
         p, keep = self._particles(pos, rho, kappa, lum, mass, box_lo, box_hi, bucket_size,
                                   box_offsets, self.device)
         _check(lib().trevr_refit_tree(self._h, ctypes.byref(p), _stream()))
+        self._n_bands = 0  # so does a refit
         return self
 
     @staticmethod
@@ -287,6 +294,24 @@ class Tree:
                                                 _ptr(C), _stream()))
         out = (F, Fv.t(), Pm.t())
         return out + (C,) if counters else out
+
+    def set_bands(self, kappa_bands):
+        """Opacity bands: kappa_bands (k, n), 1 <= k <= 4, in input order."""
+        kb = torch.as_tensor(kappa_bands, dtype=self.dtype, device=self.device).contiguous()
+        if kb.dim() != 2 or kb.shape[1] != self.n:
+            raise ValueError("kappa_bands must be (k, n)")
+        _check(lib().trevr_set_bands(self._h, int(kb.shape[0]), _ptr(kb), _stream()))
+        self._n_bands = int(kb.shape[0])
+
+    def flux_bands(self, theta_open, tau_ref, sinks=None, counters=False):
+        """Flux per band (n_sinks x k) on one traversal (see set_bands)."""
+        s, ns = self._sinks(sinks)
+        k = getattr(self, "_n_bands", 0)
+        Fb = torch.empty((max(k, 1), ns), dtype=self.dtype, device=self.device)
+        C = torch.empty((ns, 5), dtype=torch.int32, device=self.device) if counters else None
+        _check(lib().trevr_compute_flux_bands(self._h, float(theta_open), float(tau_ref),
+                                              _ptr(s), ns, _ptr(Fb), _ptr(C), _stream()))
+        return (Fb.t(), C) if counters else Fb.t()
 
     def adjoint_taped(self, grad_flux):
         """The adjoint for the arguments of the last flux(..., tape=True)."""
