@@ -267,6 +267,9 @@ def main():
     ap.add_argument("--profile-once", action="store_true",
                     help="one tree build and one flux launch of the headline workload, then a "
                          "copy of 1 GiB (counter calibration); prints nothing else")
+    ap.add_argument("--profile-adjoint", action="store_true",
+                    help="the 2^20 adjoint workload: one tree build, then three recording "
+                         "flux launches each followed by the taped adjoint; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the per-sink walk shards over sinks with a "
@@ -278,6 +281,18 @@ def main():
     import paper_1902_08083_amd as P
     from paper_1902_08083_amd import workloads as W
 
+    if args.profile_adjoint:
+        w = W.c5()
+        pos, rho, kappa, lum, mass = to_dev(w, torch)
+        tree = P.build_tree(pos, rho, kappa, lum, mass, w["box_lo"], w["box_hi"],
+                            w["bucket_size"])
+        gF = torch.ones(pos.shape[0], dtype=pos.dtype, device="cuda")
+        for _ in range(3):
+            tree.flux(w["theta"], w["tau_ref"], tape=True)
+            tree.adjoint_taped(gF)
+        torch.cuda.synchronize()
+        log("profile-adjoint done: launch %s" % (tree.get_launch(adjoint=True),))
+        return
     log("generating workload")
     w = W.c3(n=args.n)
     if args.profile_once:
