@@ -75,6 +75,20 @@ def lib():
         L.oracle_flux_bands.restype = ctypes.c_int
         L.oracle_flux_bands.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
                                         ctypes.c_int, P, P]
+        L.oracle_sph_line.restype = ctypes.c_double
+        L.oracle_sph_line.argtypes = [ctypes.c_double] * 4
+        L.oracle_set_sph.restype = ctypes.c_int
+        L.oracle_set_sph.argtypes = [P, P]
+        L.oracle_sph_neighbours.restype = ctypes.c_int64
+        L.oracle_sph_neighbours.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P]
+        L.oracle_sph_spread.restype = ctypes.c_int
+        L.oracle_sph_spread.argtypes = [P, P]
+        L.oracle_flux_sph.restype = ctypes.c_int
+        L.oracle_flux_sph.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
+                                      ctypes.c_int, P, P]
+        L.oracle_ray_log_sph.restype = ctypes.c_int64
+        L.oracle_ray_log_sph.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                         ctypes.c_int64] + [P] * 6
         L.oracle_ray_log.restype = ctypes.c_int64
         L.oracle_ray_log.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                      ctypes.c_int64] + [P] * 6
@@ -198,15 +212,53 @@ class OracleTree:
             raise ValueError("oracle_flux_bands rejected its arguments")
         return Fb, C
 
-    def ray_log(self, theta, tau_ref, sink, cap=1 << 20):
+    # ---- sub-bucket particle trace ----
+    def set_sph(self, h):
+        """Smoothing lengths (input order) for the sub-bucket particle trace."""
+        h = _d(h)
+        if h.shape != (self.n,):
+            raise ValueError("h must have one entry per particle")
+        self._h_sph = h
+        if lib().oracle_set_sph(self._h, _ptr(h)) != 0:
+            raise ValueError("oracle_set_sph rejected the smoothing lengths")
+
+    def flux_sph(self, theta, tau_ref, sinks=None, nthreads=0):
+        """Flux with the sub-bucket particle trace: (F, counters[ns, 5])."""
+        s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+        ns = self.n if s is None else int(s.shape[0])
+        F = np.empty(ns, np.float64)
+        C = np.empty((ns, 5), np.int64)
+        rc = lib().oracle_flux_sph(self._h, float(theta), float(tau_ref), _ptr(s), ns,
+                                   int(nthreads), _ptr(F), _ptr(C))
+        if rc != 0:
+            raise ValueError("oracle_flux_sph rejected its arguments (set_sph first)")
+        return F, C
+
+    def sph_neighbours(self, node):
+        n = int(lib().oracle_sph_neighbours(self._h, int(node), 0, None))
+        out = np.empty(max(n, 1), np.int64)
+        lib().oracle_sph_neighbours(self._h, int(node), n, _ptr(out))
+        return out[:n]
+
+    def sph_spread(self):
+        dp = np.empty(self.m, np.float64)
+        if lib().oracle_sph_spread(self._h, _ptr(dp)) != 0:
+            raise ValueError("set_sph first")
+        return dp
+
+    def ray_log_sph(self, theta, tau_ref, sink, cap=1 << 20):
+        return self.ray_log(theta, tau_ref, sink, cap, sph=True)
+
+    def ray_log(self, theta, tau_ref, sink, cap=1 << 20, sph=False):
         C = np.empty(cap, np.int64)
         src = np.empty(cap, np.int64)
         y = np.empty((cap, 3), np.float64)
         L = np.empty(cap, np.float64)
         tau = np.empty(cap, np.float64)
         f = np.empty(cap, np.float64)
-        nr = lib().oracle_ray_log(self._h, float(theta), float(tau_ref), int(sink), cap,
-                                  _ptr(C), _ptr(src), _ptr(y), _ptr(L), _ptr(tau), _ptr(f))
+        fn = lib().oracle_ray_log_sph if sph else lib().oracle_ray_log
+        nr = fn(self._h, float(theta), float(tau_ref), int(sink), cap,
+                _ptr(C), _ptr(src), _ptr(y), _ptr(L), _ptr(tau), _ptr(f))
         k = min(nr, cap)
         return {"C": C[:k], "src": src[:k], "y": y[:k], "L": L[:k], "tau": tau[:k], "f": f[:k]}
 
@@ -232,3 +284,8 @@ class OracleTree:
         lib().oracle_adjoint(self._h, float(theta), float(tau_ref), _ptr(s), ns, _ptr(g),
                              int(nthreads), _ptr(gr), _ptr(gk), _ptr(gl))
         return gr, gk, gl
+
+
+def sph_line(b, h, u0, u1):
+    """Integral of the M4 kernel W(sqrt(b^2 + u^2), h) over u in [u0, u1]."""
+    return float(lib().oracle_sph_line(float(b), float(h), float(u0), float(u1)))

@@ -25,6 +25,9 @@
  *   Sec. 2.2.3, eq. (refcrit): refine where tau_ref < (alpha_max-alpha_min) l;
  *                   directional alpha_min / alpha_max built bottom-up
  *   Sec. 2.3:       volume-weighted cell density sum(m)/sum(m/rho)
+ *   Sec. 2.2.3 and 2.3 (sub-bucket refinement): below a bucket, an SPH-style
+ *                   particle trace, tau = sum_j m_j kappa_j (integral of the
+ *                   smoothing kernel along the ray), the receiver excluded
  * The adjoint (gradients of a flux loss) is not in the paper; it is the exact
  * derivative of the forward above with every discrete decision held fixed.
  */
@@ -66,6 +69,12 @@ typedef struct {
   int nbands;
   double *band_alpha; /* [nbands][m] */
   double *band_dalpha; /* [m] */
+  /* sub-bucket particle trace (oracle_set_sph): smoothing lengths, m kappa,
+   * each bucket's transport particle spread (-1 for other cells) and the
+   * absorbers whose kernel support reaches the bucket's box (CSR by cell) */
+  int sph;
+  double *sph_h, *sph_mk, *sph_dp, *sph_hmax;
+  int64_t *nb_off, *nb_idx;
 } otree;
 
 static double tr(const otree *t, double v) {
@@ -360,6 +369,12 @@ void oracle_free(void *h) {
   free(t->nd);
   free(t->band_alpha);
   free(t->band_dalpha);
+  free(t->sph_h);
+  free(t->sph_mk);
+  free(t->sph_dp);
+  free(t->sph_hmax);
+  free(t->nb_off);
+  free(t->nb_idx);
   free(t);
 }
 
@@ -501,6 +516,7 @@ typedef struct {
   double Fv[3]; /* vector flux: sum of f times the unit vector from source to sink */
   double Pm[6]; /* second moment: sum of f n_a n_b (xx, yy, zz, xy, xz, yz) */
   int bands;     /* band mode: per-band tau and flux, band-maximum spread */
+  int sph;       /* sub-bucket particle trace below the buckets */
   double Fb[8];
   int64_t n_open, n_rays, n_psrc, n_seg, n_trace;
   /* adjoint accumulators (NULL in a forward pass) */
@@ -521,12 +537,214 @@ static double spread(const osink *c, int64_t X) {
   return c->bands ? c->t->band_dalpha[X] : c->t->nd[X].t_dalpha;
 }
 
+/* ---------------------------------------------- sub-bucket particle trace ---- */
+
+/* The M4 cubic spline kernel with support 2h, W(r, h) = w(r/h) / (pi h^3),
+ * normalised so that its volume integral is one. */
+static double w_m4(double q) {
+  if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+  if (q < 2.0) {
+    double u = 2.0 - q;
+    return 0.25 * u * u * u;
+  }
+  return 0.0;
+}
+
+/* The integrand of the line integral in units of h: w(sqrt(beta^2 + s^2)). */
+static double w_line(double beta, double s) { return w_m4(sqrt(beta * beta + s * s)); }
+
+/* Five-point Gauss-Legendre rule on [a, b] (nodes and weights from their
+ * closed forms: 0, +-sqrt(5 -+ 2 sqrt(10/7)) / 3). */
+static double gl5(double beta, double a, double b) {
+  const double x1 = sqrt(5.0 - 2.0 * sqrt(10.0 / 7.0)) / 3.0;
+  const double x2 = sqrt(5.0 + 2.0 * sqrt(10.0 / 7.0)) / 3.0;
+  const double w0 = 128.0 / 225.0;
+  const double w1 = (322.0 + 13.0 * sqrt(70.0)) / 900.0;
+  const double w2 = (322.0 - 13.0 * sqrt(70.0)) / 900.0;
+  const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
+  double sum = w0 * w_line(beta, c);
+  sum += w1 * (w_line(beta, c - hw * x1) + w_line(beta, c + hw * x1));
+  sum += w2 * (w_line(beta, c - hw * x2) + w_line(beta, c + hw * x2));
+  return hw * sum;
+}
+
+/* Adaptive quadrature: the rule on [a, b] against the rule on its halves,
+ * to 1e-15 per unit length (w <= 1, so rounding stays below that). */
+static double gl5_adapt(double beta, double a, double b, double whole, int depth) {
+  double m = 0.5 * (a + b);
+  double left = gl5(beta, a, m), right = gl5(beta, m, b);
+  double two = left + right;
+  if (depth >= 40 || fabs(two - whole) <= 1e-15 * (b - a)) return two;
+  return gl5_adapt(beta, a, m, left, depth + 1) + gl5_adapt(beta, m, b, right, depth + 1);
+}
+
+/* Integral of W(sqrt(b^2 + u^2), h) over u in [u0, u1] (u0 <= u1): the
+ * plain definition, by adaptive quadrature on the pieces between the points
+ * where the kernel's formula changes (q = 1, 2) and the closest approach. */
+double oracle_sph_line(double b, double h, double u0, double u1) {
+  if (!(h > 0) || !(u1 > u0)) return 0.0;
+  double beta = b / h, s0 = u0 / h, s1 = u1 / h;
+  if (beta >= 2.0) return 0.0;
+  double e2 = sqrt(4.0 - beta * beta);
+  double cuts[7];
+  int nc = 0;
+  cuts[nc++] = -e2;
+  if (beta < 1.0) cuts[nc++] = -sqrt(1.0 - beta * beta);
+  cuts[nc++] = 0.0;
+  if (beta < 1.0) cuts[nc++] = sqrt(1.0 - beta * beta);
+  cuts[nc++] = e2;
+  double total = 0.0;
+  for (int k = 0; k + 1 < nc; ++k) {
+    double a = cuts[k] > s0 ? cuts[k] : s0;
+    double e = cuts[k + 1] < s1 ? cuts[k + 1] : s1;
+    if (e > a) total += gl5_adapt(beta, a, e, gl5(beta, a, e), 0);
+  }
+  return total / (M_PI * h * h);
+}
+
+/* Optical depth of the ray piece [ta, tb] inside bucket X, Sec. 2.3: each
+ * absorber j whose kernel reaches the bucket adds m_j kappa_j times the
+ * kernel's integral over the piece; the receiving particle does not absorb
+ * its own radiation. */
+static double sph_piece(const osink *c, const oray *ry, int64_t X, double ta, double tb) {
+  const otree *t = c->t;
+  double tau = 0.0;
+  for (int64_t k = t->nb_off[X]; k < t->nb_off[X + 1]; ++k) {
+    int64_t j = t->nb_idx[k];
+    if (j == c->i) continue;
+    const double *xj = &t->x[3 * j];
+    double dl[3], p[3];
+    for (int a = 0; a < 3; ++a) dl[a] = xj[a] - c->xi[a];
+    /* closest approach to the ray's line at parameter ts */
+    double ts = ((dl[0] * ry->d[0] + dl[1] * ry->d[1]) + dl[2] * ry->d[2]) / ry->r2;
+    for (int a = 0; a < 3; ++a) p[a] = dl[a] - ts * ry->d[a];
+    double b = sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
+    tau += t->sph_mk[j] * oracle_sph_line(b, t->sph_h[j], (ta - ts) * ry->r, (tb - ts) * ry->r);
+  }
+  return tau;
+}
+
+/* the absorbers whose kernel support (radius 2 h) reaches box [lo, hi], by a
+ * query down the tree; each cell carries the largest h of its absorbers */
+static void sph_query(const otree *t, int64_t C, const double *lo, const double *hi,
+                      int64_t *out, int64_t *n, int count_only) {
+  const onode *p = &t->nd[C];
+  if (!(t->sph_hmax[C] > 0)) return;
+  double g2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double g = p->lo[a] - hi[a];
+    double g1 = lo[a] - p->hi[a];
+    if (g1 > g) g = g1;
+    if (g > 0) g2 += g * g;
+  }
+  if (!(g2 < 4.0 * t->sph_hmax[C] * t->sph_hmax[C])) return;
+  if (p->leaf) {
+    for (int64_t k = p->first; k < p->first + p->count; ++k) {
+      int64_t j = t->perm[k];
+      if (!(t->sph_mk[j] > 0)) continue;
+      double d2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        double v = t->x[3 * j + a];
+        double g = lo[a] - v > v - hi[a] ? lo[a] - v : v - hi[a];
+        if (g > 0) d2 += g * g;
+      }
+      if (d2 < 4.0 * t->sph_h[j] * t->sph_h[j]) {
+        if (!count_only) out[*n] = j;
+        ++*n;
+      }
+    }
+    return;
+  }
+  sph_query(t, C + 1, lo, hi, out, n, count_only);
+  sph_query(t, p->right, lo, hi, out, n, count_only);
+}
+
+/* Smoothing lengths h (input order, > 0) for the sub-bucket particle trace.
+ * A bucket's refinement decision uses the spread of its particles' absorption
+ * coefficients kappa rho (those with mass), in the transport precision. */
+int oracle_set_sph(void *hd, const double *h) {
+  otree *t = (otree *)hd;
+  for (int64_t i = 0; i < t->n; ++i)
+    if (!(h[i] > 0) || !isfinite(h[i])) return -1;
+  size_t nn = (size_t)(t->n > 0 ? t->n : 1), mm = (size_t)t->m;
+  free(t->sph_h);
+  free(t->sph_mk);
+  free(t->sph_dp);
+  free(t->sph_hmax);
+  free(t->nb_off);
+  free(t->nb_idx);
+  t->sph_h = (double *)malloc(nn * sizeof(double));
+  t->sph_mk = (double *)malloc(nn * sizeof(double));
+  t->sph_dp = (double *)malloc(mm * sizeof(double));
+  t->sph_hmax = (double *)calloc(mm, sizeof(double));
+  t->nb_off = (int64_t *)calloc(mm + 1, sizeof(int64_t));
+  for (int64_t i = 0; i < t->n; ++i) {
+    t->sph_h[i] = tr(t, h[i]);
+    t->sph_mk[i] = t->mass[i] > 0 ? t->mass[i] * t->kappa[i] : 0.0;
+  }
+  for (int64_t id = t->m - 1; id >= 0; --id) {
+    const onode *p = &t->nd[id];
+    t->sph_dp[id] = -1.0;
+    if (p->leaf) {
+      double lo = INFINITY, hi = -INFINITY, hm = 0.0;
+      for (int64_t k = p->first; k < p->first + p->count; ++k) {
+        int64_t j = t->perm[k];
+        if (t->mass[j] > 0) {
+          double a = t->kappa[j] * t->rho[j];
+          if (a < lo) lo = a;
+          if (a > hi) hi = a;
+        }
+        if (t->sph_mk[j] > 0 && t->sph_h[j] > hm) hm = t->sph_h[j];
+      }
+      t->sph_dp[id] = hi >= lo ? tr(t, hi - lo) : 0.0;
+      t->sph_hmax[id] = hm;
+    } else {
+      double a = t->sph_hmax[id + 1], b = t->sph_hmax[p->right];
+      t->sph_hmax[id] = a > b ? a : b;
+    }
+  }
+  for (int64_t id = 0; id < t->m; ++id) {
+    int64_t cnt = 0;
+    if (t->nd[id].leaf) sph_query(t, 0, t->nd[id].lo, t->nd[id].hi, NULL, &cnt, 1);
+    t->nb_off[id + 1] = t->nb_off[id] + cnt;
+  }
+  t->nb_idx = (int64_t *)malloc((size_t)(t->nb_off[t->m] > 0 ? t->nb_off[t->m] : 1) *
+                                sizeof(int64_t));
+  for (int64_t id = 0; id < t->m; ++id) {
+    int64_t cnt = 0;
+    if (t->nd[id].leaf)
+      sph_query(t, 0, t->nd[id].lo, t->nd[id].hi, t->nb_idx + t->nb_off[id], &cnt, 0);
+  }
+  t->sph = 1;
+  return 0;
+}
+
+/* A bucket's absorbers (input indices, tree order); returns their number. */
+int64_t oracle_sph_neighbours(void *hd, int64_t node, int64_t cap, int64_t *out) {
+  const otree *t = (const otree *)hd;
+  if (!t->sph || node < 0 || node >= t->m) return -1;
+  int64_t n = t->nb_off[node + 1] - t->nb_off[node];
+  for (int64_t k = 0; k < n && k < cap; ++k) out[k] = t->nb_idx[t->nb_off[node] + k];
+  return n;
+}
+
+/* Each cell's sub-bucket decision spread (-1 for cells that are not buckets). */
+int oracle_sph_spread(void *hd, double *dp) {
+  const otree *t = (const otree *)hd;
+  if (!t->sph) return -1;
+  for (int64_t id = 0; id < t->m; ++id) dp[id] = t->sph_dp[id];
+  return 0;
+}
+
 /* one alpha * l term of eq. (tausum) */
 static void add_piece(osink *c, oray *ry, int64_t node, double ta, int taga,
                       double tb, int tagb, double l) {
   double alpha = c->t->nd[node].t_alpha;
   if (l > 0) c->n_seg++;
-  ry->tau += alpha * l;
+  if (c->sph && c->t->nd[node].leaf && c->t->sph_dp[node] * l > c->tau_ref)
+    ry->tau += sph_piece(c, ry, node, ta, tb); /* refinement below the bucket */
+  else
+    ry->tau += alpha * l;
   if (c->bands)
     for (int b = 0; b < c->t->nbands; ++b)
       ry->tau_b[b] += c->t->band_alpha[(size_t)b * (size_t)c->t->m + (size_t)node] * l;
@@ -918,6 +1136,55 @@ int oracle_flux_bands(void *h, double theta, double tau_ref, const int64_t *sink
     }
   }
   return 0;
+}
+
+/* Flux with the sub-bucket particle trace (oracle_set_sph first): as
+ * oracle_flux, but a ray piece in a bucket whose particle spread fails the
+ * refinement test, spread * l > tau_ref, takes the particle trace. */
+int oracle_flux_sph(void *h, double theta, double tau_ref, const int64_t *sinks, int64_t ns,
+                    int nthreads, double *F, int64_t *counters) {
+  const otree *t = (const otree *)h;
+  if (!(theta >= 0) || !t->sph) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t q = 0; q < ns; ++q) {
+    int64_t i = sinks ? sinks[q] : q;
+    osink c;
+    sink_init(&c, t, i, theta, tau_ref);
+    c.sph = 1;
+    walk(&c, 0);
+    F[q] = c.F;
+    if (counters) {
+      counters[5 * q + 0] = c.n_open;
+      counters[5 * q + 1] = c.n_rays;
+      counters[5 * q + 2] = c.n_psrc;
+      counters[5 * q + 3] = c.n_seg;
+      counters[5 * q + 4] = c.n_trace;
+    }
+  }
+  return 0;
+}
+
+/* oracle_ray_log with the sub-bucket particle trace. */
+int64_t oracle_ray_log_sph(void *h, double theta, double tau_ref, int64_t sink, int64_t cap,
+                           int64_t *C, int64_t *src, double *y, double *L, double *tau,
+                           double *f) {
+  const otree *t = (const otree *)h;
+  if (!t->sph) return -1;
+  osink c;
+  sink_init(&c, t, sink, theta, tau_ref);
+  c.sph = 1;
+  c.log_cap = cap;
+  c.log_C = C;
+  c.log_src = src;
+  c.log_y = y;
+  c.log_L = L;
+  c.log_tau = tau;
+  c.log_f = f;
+  walk(&c, 0);
+  return c.log_n;
 }
 
 /* Every ray of one sink, in walk order.  Returns the number of rays (the
