@@ -234,6 +234,40 @@ int trevr_compute_flux_bands(const trevr_tree *tree, double theta_open, double t
                              const int32_t *sinks, int64_t n_sinks, void *flux_bands,
                              int32_t *counters, hipStream_t stream);
 
+/* Refinement below the buckets: a particle trace in the manner of SPHRay
+ * (Sec. 2.2.3 and the ray-tracing passage of Sec. 2.3).  Where refinement
+ * reaches a bucket and the bucket's own spread still fails the criterion,
+ * spread * l > tau_ref (eq. refcrit; the spread is max - min of kappa rho over
+ * the bucket's particles with mass), the piece's optical depth is, instead of
+ * alpha_bucket l, the sum over the absorbers whose kernel support reaches the
+ * bucket's box of m_j kappa_j times the integral of their smoothing kernel
+ * along the piece (the paper's tau = (m int W) kappa ds); the receiving
+ * particle never absorbs its own radiation.  The kernel is the M4 cubic
+ * spline with support 2h, W(r, h) = w(r / h) / (pi h^3), integrated in closed
+ * form (binary64).  tau_ref = infinity gives trevr_compute_flux's result.
+ * trevr_set_sph: h device [n], smoothing lengths per particle in input order,
+ * precision of the tree, finite and > 0.  Builds, on the device, each
+ * bucket's absorber list (4 B per entry, typically 100-200 entries per bucket)
+ * and per-particle and per-cell data (24-40 B per particle, 12-16 B per cell),
+ * owned by the tree.  Waits on `stream`.  Errors: TREVR_E_ARG, _STATE,
+ * _NONFINITE, _VALUE, _HIP.  A build or a refit drops the smoothing lengths.
+ * trevr_compute_flux_sph: as trevr_compute_flux (arguments, counters, NaN for
+ * an invalid sink index), with the particle trace below the buckets.  Runs a
+ * 3-wave kernel whatever the launch shape.  Asynchronous, allocates nothing.
+ * Errors: as trevr_compute_flux, and TREVR_E_STATE without smoothing lengths.
+ * trevr_export_sph: the absorber lists to host memory: *n_entries receives the
+ * total entries; if offsets is not NULL, offsets [m + 1] (per cell, in the
+ * depth-first order of trevr_export_tree; empty but at buckets), neighbours
+ * [n_entries] (input indices, ascending tree order within a list) and, if not
+ * NULL, spread [m] (the decision spread, -1 for cells that are not buckets).
+ * Waits on `stream`.  Errors: TREVR_E_ARG, _STATE, _HIP. */
+int trevr_set_sph(trevr_tree *tree, const void *h, hipStream_t stream);
+int trevr_compute_flux_sph(const trevr_tree *tree, double theta_open, double tau_ref,
+                           const int32_t *sinks, int64_t n_sinks, void *flux, int32_t *counters,
+                           hipStream_t stream);
+int trevr_export_sph(const trevr_tree *tree, int64_t *n_entries, int64_t *offsets,
+                     int64_t *neighbours, double *spread, hipStream_t stream);
+
 /* The flux and its adjoint with the traversal recorded once.  The recording
  * flux computes exactly what trevr_compute_flux computes (same arguments and
  * errors) and in addition stores every ray's optical depth tau (binary64, in

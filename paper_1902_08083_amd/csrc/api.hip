@@ -71,7 +71,8 @@ trevr_tree::~trevr_tree() {
                           &flags, &scan, &err, &box_key, &skeys, &small, &queue, &adj_node,
                           &adj_part, &adj_heap, &adj_flux, &tape, &tape_next, &tape_head, &tape_ctr,
                           &band_alpha, &band_dmax, &band_trace, &bs_A, &bs_alpha, &bs_amin,
-                          &bs_amax, &bs_amin_d, &bs_amax_d, &bs_dalpha};
+                          &bs_amax, &bs_amin_d, &bs_amax_d, &bs_dalpha, &pkappa, &sph_pos,
+                          &sph_mk, &sph_dp, &sph_hmax, &sph_cnt, &sph_off, &sph_nb};
   for (auto *b : all) b->release();
   if (tape_used_h) (void)hipHostFree(tape_used_h);
 }
@@ -146,6 +147,33 @@ int trevr_compute_flux_bands(const trevr_tree *tree, double theta_open, double t
   if (n_sinks > 0 && !flux_bands) return trevr::fail(TREVR_E_ARG, "flux_bands is NULL");
   return trevr::flux_bands_impl(tree, theta_open, tau_ref, sinks, n_sinks, flux_bands, counters,
                                 stream);
+}
+
+int trevr_set_sph(trevr_tree *tree, const void *h, hipStream_t stream) {
+  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
+  if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");
+  if (tree->n > 0 && !h) return trevr::fail(TREVR_E_ARG, "h is NULL");
+  return trevr::sph_impl(tree, h, stream);
+}
+
+int trevr_compute_flux_sph(const trevr_tree *tree, double theta_open, double tau_ref,
+                           const int32_t *sinks, int64_t n_sinks, void *flux, int32_t *counters,
+                           hipStream_t stream) {
+  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (!tree->sph_ok) return trevr::fail(TREVR_E_STATE, "no smoothing lengths set on this tree");
+  if (n_sinks > 0 && !flux) return trevr::fail(TREVR_E_ARG, "flux is NULL");
+  return trevr::flux_sph_impl(tree, theta_open, tau_ref, sinks, n_sinks, flux, counters, stream);
+}
+
+int trevr_export_sph(const trevr_tree *tree, int64_t *n_entries, int64_t *offsets,
+                     int64_t *neighbours, double *spread, hipStream_t stream) {
+  if (!tree || !n_entries) return trevr::fail(TREVR_E_ARG, "tree or n_entries is NULL");
+  if (!tree->built || !tree->sph_ok)
+    return trevr::fail(TREVR_E_STATE, "no smoothing lengths set on this tree");
+  if (offsets && tree->sph_entries > 0 && !neighbours)
+    return trevr::fail(TREVR_E_ARG, "neighbours is NULL");
+  return trevr::export_sph_impl(tree, n_entries, offsets, neighbours, spread, stream);
 }
 
 int trevr_refit_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream) {

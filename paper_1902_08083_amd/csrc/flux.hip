@@ -62,6 +62,14 @@ struct FluxArgs {
   const T *__restrict__ band_alpha;
   int32_t n_bands;
   T *flux_bands;  // [n_bands][n_sinks]
+  // sub-bucket particle trace (kernels with SPH): per cell the decision
+  // spread (-1 but at buckets), per bucket its absorbers (sorted indices,
+  // int64 offsets by cell), per particle x, y, z, h and m kappa
+  const T *__restrict__ sph_dp;
+  const int64_t *__restrict__ sph_off;
+  const int32_t *__restrict__ sph_nb;
+  const P4<T> *__restrict__ sph_pos;
+  const double *__restrict__ sph_mk;
   int32_t *counters;
   int32_t *queue;  // kXcd counters
   // Tape of per-ray optical depths: one block of 64 per round, the blocks of
@@ -248,6 +256,90 @@ struct BandSum {
                                              double, int) {
     for (int b = 0; b < kMaxBands; ++b)
       if (b < nb) tau[b] += (double)ba[(int64_t)b * m + node] * l;
+  }
+};
+
+// The M4 cubic spline (support 2h, W = w(r/h) / (pi h^3)) integrated along a
+// line at impact parameter b, in units of h: G(beta, s) is the integral of
+// w(sqrt(beta^2 + u^2)) over u in [0, s], s >= 0.  w is a polynomial in q on
+// q < 1 and on 1 <= q < 2, and along the line the integrals of q^0 and q^2 are
+// polynomials in u, those of q and q^3 closed forms with asinh(u / beta).
+// in_out: the inner and the outer polynomial's primitive at s (q = |(beta, s)|).
+__device__ __forceinline__ void m4_prims(double beta, double b2, double s, double &p_in,
+                                         double &p_out) {
+  const double q = sqrt(b2 + s * s);
+  const double as = beta > 0.0 ? asinh(s / beta) : 0.0;
+  const double i1 = 0.5 * (s * q + b2 * as);
+  const double i2 = b2 * s + (s * s * s) / 3.0;
+  const double i3 = 0.125 * (s * q * (2.0 * s * s + 5.0 * b2)) + 0.375 * (b2 * b2) * as;
+  p_in = s - 1.5 * i2 + 0.75 * i3;
+  p_out = 2.0 * s - 3.0 * i1 + 1.5 * i2 - 0.25 * i3;
+}
+// G at |v|, with the sign of v (G is odd in s); s1, s2: where q = 1, 2 along
+// the line (s1 = 0 when beta >= 1), k_io = inner - outer primitive at s1.
+__device__ __forceinline__ double m4_g(double beta, double b2, double v, double s1, double s2,
+                                       double k_io) {
+  double s = fabs(v);
+  s = s < s2 ? s : s2;
+  double p_in, p_out;
+  m4_prims(beta, b2, s, p_in, p_out);
+  const double g = s <= s1 ? p_in : k_io + p_out;
+  return v < 0.0 ? -g : g;
+}
+// Integral of W(sqrt(b^2 + u^2), h) over u in [u0, u1].
+__device__ __forceinline__ double m4_line(double b, double h, double u0, double u1) {
+  const double beta = b / h;
+  if (!(beta < 2.0)) return 0.0;
+  const double b2 = beta * beta;
+  const double s2 = sqrt(4.0 - b2);
+  const double v0 = u0 / h, v1 = u1 / h;
+  if (v0 >= s2 || v1 <= -s2) return 0.0;  // the piece misses the support
+  double s1 = 0.0, k_io = 0.0;
+  if (b2 < 1.0) {
+    s1 = sqrt(1.0 - b2);
+    double p_in, p_out;
+    m4_prims(beta, b2, s1, p_in, p_out);
+    k_io = p_in - p_out;
+  }
+  const double g = m4_g(beta, b2, v1, s1, s2, k_io) - m4_g(beta, b2, v0, s1, s2, k_io);
+  return g / (M_PI * h * h);
+}
+
+// Sub-bucket policy (Sec. 2.2.3, 2.3): a piece in a bucket whose particle
+// spread fails the refinement test, spread * l > tau_ref, takes the particle
+// trace -- each of the bucket's absorbers but the receiving particle adds
+// m kappa times its kernel's integral over the piece; every other piece adds
+// alpha l as in eq. (tausum).
+template <typename T>
+struct SphSum {
+  static constexpr bool kLight = false;
+  const T *dp;
+  const int64_t *off;
+  const int32_t *nb;
+  const P4<T> *pos;
+  const double *mk;
+  double xi[3], d[3], r, r2, tau_ref;
+  int self;  // the receiver (sorted index)
+  double tau = 0.0;
+  __device__ __forceinline__ void operator()(int node, int, double alpha, double l, double ta,
+                                             int, double tb, int) {
+    const double spread = (double)dp[node];
+    if (!(spread >= 0.0 && spread * l > tau_ref)) {
+      tau += alpha * l;
+      return;
+    }
+    const int64_t e = off[node + 1];
+    for (int64_t k = off[node]; k < e; ++k) {
+      const int j = nb[k];
+      if (j == self) continue;
+      const P4<T> pj = pos[j];
+      const double dl0 = (double)pj.x - xi[0], dl1 = (double)pj.y - xi[1],
+                   dl2 = (double)pj.z - xi[2];
+      const double ts = ((dl0 * d[0] + dl1 * d[1]) + dl2 * d[2]) / r2;  // closest approach
+      const double p0 = dl0 - ts * d[0], p1 = dl1 - ts * d[1], p2 = dl2 - ts * d[2];
+      const double b = sqrt((p0 * p0 + p1 * p1) + p2 * p2);
+      tau += mk[j] * m4_line(b, (double)pj.L, (ta - ts) * r, (tb - ts) * r);
+    }
   }
 };
 
@@ -770,7 +862,7 @@ constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source,
 // owning sink's context by lane shuffles; each owner adds its results in
 // queue order, so a sink's sum is in its own walk order whatever the other
 // sinks of the wave are.
-template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0, int NBND = 0>
+template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0, int NBND = 0, int SPH = 0>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
@@ -939,6 +1031,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       tk.pre = s_pre;
       tk.win = s_anc + owner;
       const double wg = ADJ ? __shfl(wgt, owner) : 0.0;
+      const int self_k = SPH > 0 ? __shfl(k, owner) : 0;  // the receiving particle
       double f = 0.0;
       double fv[3] = {0.0, 0.0, 0.0};  // f along the ray's direction of travel n
       double fp[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // f n_a n_b
@@ -999,7 +1092,24 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         c.n_trace = 0;
         ray_setup(c, (double)yx, (double)yy, (double)yz);
         std::conditional_t<ADJ, TauSumA, TauSum> ts;
-        if constexpr (NBND > 0) {  // one traversal, one tau per band
+        if constexpr (SPH > 0) {  // particle trace below the buckets
+          SphSum<T> ss;
+          ss.dp = a.sph_dp;
+          ss.off = a.sph_off;
+          ss.nb = a.sph_nb;
+          ss.pos = a.sph_pos;
+          ss.mk = a.sph_mk;
+          for (int q3 = 0; q3 < 3; ++q3) {
+            ss.xi[q3] = c.xi[q3];
+            ss.d[q3] = c.d[q3];
+          }
+          ss.r = c.r;
+          ss.r2 = c.r2;
+          ss.tau_ref = c.tau_ref;
+          ss.self = self_k;
+          trace_pieces<T>(a, C, keyC, depthC, tk, c, ss);
+          ts.tau = ss.tau;
+        } else if constexpr (NBND > 0) {  // one traversal, one tau per band
           BandSum<T> bsum;
           bsum.ba = a.band_alpha;
           bsum.m = a.m;
@@ -1377,6 +1487,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     FluxArgs<T> a) {
   walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, kMaxBands>(a);
 }
+// The flux with the sub-bucket particle trace, at the 3-wave budget.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3s(
+    FluxArgs<T> a) {
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, 0, 1>(a);
+}
 // The flux with the vector flux and the second moment, at the 3-wave budget.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3m(
@@ -1502,6 +1618,14 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
+    if (a.sph_nb) {  // the particle trace: the 3-wave kernel, at most 3 waves per SIMD
+      const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
+      int64_t vb = (int64_t)bpc * t->num_cu;
+      if (vb > need) vb = need;
+      k_walk3s<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      TREVR_HIP(hipGetLastError());
+      return TREVR_OK;
+    }
     if (a.flux_mom) {  // the moments: the 3-wave kernel, at most 3 waves per SIMD
       const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
@@ -1589,6 +1713,29 @@ int flux_bands_impl(const trevr_tree *t, double theta, double tau_ref, const int
   if (t->prec == TREVR_F64)
     return flux_bands_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux_bands, counters, s);
   return flux_bands_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux_bands, counters, s);
+}
+
+template <typename T>
+static int flux_sph_typed(const trevr_tree *t, double theta, double tau_ref,
+                          const int32_t *sinks, int64_t n_sinks, void *flux, int32_t *counters,
+                          hipStream_t s) {
+  if (n_sinks == 0) return TREVR_OK;
+  FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
+  a.sph_dp = t->sph_dp.as<T>();
+  a.sph_off = t->sph_off.as<int64_t>();
+  a.sph_nb = t->sph_nb.as<int32_t>();
+  a.sph_pos = t->sph_pos.as<P4<T>>();
+  a.sph_mk = t->sph_mk.as<double>();
+  a.flux = static_cast<T *>(flux);
+  a.counters = counters;
+  return launch_walk<T, false>(t, a, s);
+}
+
+int flux_sph_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                  int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s) {
+  if (t->prec == TREVR_F64)
+    return flux_sph_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
+  return flux_sph_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
 }
 
 int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,

@@ -379,7 +379,7 @@ __global__ void k_finish2(const int32_t *skip, const double *split, int64_t m, W
 
 template <typename T>
 __global__ void k_particles(PartIn<T> in, const int32_t *perm, int64_t n, P4<T> *ps,
-                            int32_t *inv, T *pmass, T *prho) {
+                            int32_t *inv, T *pmass, T *prho, T *pkappa) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int q = perm[k];
@@ -392,6 +392,7 @@ __global__ void k_particles(PartIn<T> in, const int32_t *perm, int64_t n, P4<T> 
   inv[q] = (int32_t)k;
   pmass[k] = in.mass ? in.mass[q] : (T)1;
   prho[k] = in.rho[q];
+  pkappa[k] = in.kappa[q];
 }
 
 __global__ void k_sorted_box(const int32_t *perm, const int64_t *box_off, int nbox, int64_t n,
@@ -450,9 +451,11 @@ static int cell_props(trevr_tree *t, const PartIn<T> &in, int64_t n, int64_t m, 
   TREVR_HIP(t->pbox.ensure(4 * nn));
   TREVR_HIP(t->pmass.ensure(sizeof(T) * nn));
   TREVR_HIP(t->prho.ensure(sizeof(T) * nn));
+  TREVR_HIP(t->pkappa.ensure(sizeof(T) * nn));
   if (n > 0) {
     k_particles<T><<<nblk(n), 256, 0, s>>>(in, perm, n, t->psrc.as<P4<T>>(), t->inv.as<int32_t>(),
-                                           t->pmass.as<T>(), t->prho.as<T>());
+                                           t->pmass.as<T>(), t->prho.as<T>(),
+                                           t->pkappa.as<T>());
     k_sorted_box<<<nblk(n), 256, 0, s>>>(perm, t->box_off.as<int64_t>(), nbox, n,
                                          t->pbox.as<int32_t>());
   }
@@ -821,6 +824,233 @@ int bands_impl(trevr_tree *t, int nb, const void *kb, hipStream_t s) {
   return bands_typed<float>(t, nb, (const float *)kb, s);
 }
 
+// ---- sub-bucket particle trace (Sec. 2.2.3, 2.3) --------------------------
+//
+// Below a bucket the ray meets particles: each absorber j adds m_j kappa_j
+// times its smoothing kernel's integral along the piece.  The set-up keeps,
+// in sorted order, every particle's position and h and its m kappa; per
+// bucket the spread of kappa rho over its particles (the refinement decision
+// at that level); and per bucket the absorbers whose kernel support (radius
+// 2h) reaches its box, found by a query down the tree with the largest h of
+// each cell's absorbers.
+template <typename T>
+__global__ void k_sph_particles(const T *h, const int32_t *perm, const P4<T> *ps,
+                                const T *pmass, const T *pkappa, int64_t n, P4<T> *pos,
+                                double *mk, int *err) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const T hv = h[perm[k]];
+  const double hd = (double)hv;
+  if (!isfinite(hd))
+    atomicOr(err, ERR_NONFINITE);
+  else if (!(hd > 0))
+    atomicOr(err, ERR_VALUE);
+  P4<T> v = ps[k];
+  v.L = hv;
+  pos[k] = v;
+  const double m = (double)pmass[k];
+  mk[k] = m > 0 ? m * (double)pkappa[k] : 0.0;
+}
+
+template <typename T>
+__global__ void k_sph_bucket(const BfsNode *lvl, int cnt, const T *pmass, const T *pkappa,
+                             const T *prho, const P4<T> *pos, const double *mk, T *dp,
+                             double *hmax) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt) return;
+  const BfsNode nd = lvl[j];
+  if (nd.child >= 0) {
+    dp[nd.pre] = (T)-1;
+    return;
+  }
+  double lo = INFINITY, hi = -INFINITY, hm = 0.0;
+  for (int k = nd.first; k < nd.first + nd.count; ++k) {
+    if ((double)pmass[k] > 0) {
+      const double a = (double)pkappa[k] * (double)prho[k];
+      lo = a < lo ? a : lo;
+      hi = a > hi ? a : hi;
+    }
+    const double h = (double)pos[k].L;
+    if (mk[k] > 0 && h > hm) hm = h;
+  }
+  dp[nd.pre] = hi >= lo ? (T)(hi - lo) : (T)0;
+  hmax[nd.pre] = hm;
+}
+
+__global__ void k_sph_internal(const BfsNode *lvl, int cnt, const int32_t *right,
+                               double *hmax) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt) return;
+  const BfsNode nd = lvl[j];
+  if (nd.child < 0) return;
+  const int p = nd.pre;
+  const double a = hmax[p + 1], b = hmax[right[p]];
+  hmax[p] = a > b ? a : b;
+}
+
+// One thread per cell; a bucket walks its box's tree in depth-first order,
+// skipping subtrees whose absorbers cannot reach it.  Without `off` it counts
+// its absorbers, with it writes them (sorted indices, ascending).
+template <typename T>
+__global__ void k_sph_lists(int64_t m, const int32_t *right, const int32_t *skip,
+                            const int32_t *first, const int32_t *count, const int32_t *nbox,
+                            const int32_t *box_root, const double *lo, const double *hi,
+                            const double *hmax, const P4<T> *pos, const double *mk,
+                            const int64_t *off, int32_t *cnt, int32_t *out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  if (right[p] >= 0) {
+    if (!off) cnt[p] = 0;
+    return;
+  }
+  double blo[3], bhi[3];
+  for (int a = 0; a < 3; ++a) {
+    blo[a] = lo[a * m + p];
+    bhi[a] = hi[a * m + p];
+  }
+  const int root = box_root[nbox[p]];
+  const int end = skip[root];
+  const int64_t w = off ? off[p] : 0;
+  int found = 0;
+  for (int c = root; c < end;) {
+    const double hm = hmax[c];
+    double g2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      double g = lo[a * m + c] - bhi[a];
+      const double g1 = blo[a] - hi[a * m + c];
+      if (g1 > g) g = g1;
+      if (g > 0) g2 += g * g;
+    }
+    if (!(hm > 0) || !(g2 < 4.0 * hm * hm)) {
+      c = skip[c];
+      continue;
+    }
+    if (right[c] >= 0) {
+      ++c;
+      continue;
+    }
+    for (int k = first[c]; k < first[c] + count[c]; ++k) {
+      if (!(mk[k] > 0)) continue;
+      const P4<T> v = pos[k];
+      const double x[3] = {(double)v.x, (double)v.y, (double)v.z};
+      double d2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        const double g = blo[a] - x[a] > x[a] - bhi[a] ? blo[a] - x[a] : x[a] - bhi[a];
+        if (g > 0) d2 += g * g;
+      }
+      const double h = (double)v.L;
+      if (d2 < 4.0 * h * h) {
+        if (off) out[w + found] = k;
+        ++found;
+      }
+    }
+    c = skip[c];
+  }
+  if (!off) cnt[p] = found;
+}
+
+__global__ void k_sph_total(const int32_t *cnt, const int64_t *off, int64_t m, int64_t *tot) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    tot[0] = m > 0 ? off[m - 1] + (int64_t)cnt[m - 1] : 0;
+}
+
+template <typename T>
+static int sph_typed(trevr_tree *t, const T *h, hipStream_t s) {
+  const int64_t n = t->n, m = t->m;
+  const size_t mm = (size_t)(m > 0 ? m : 1), nn = (size_t)(n > 0 ? n : 1);
+  TREVR_HIP(t->sph_pos.ensure(sizeof(P4<T>) * nn));
+  TREVR_HIP(t->sph_mk.ensure(8 * nn));
+  TREVR_HIP(t->sph_dp.ensure(sizeof(T) * mm));
+  TREVR_HIP(t->sph_hmax.ensure(8 * mm));
+  TREVR_HIP(t->sph_cnt.ensure(4 * mm));
+  TREVR_HIP(t->sph_off.ensure(8 * (mm + 1)));
+  TREVR_HIP(hipMemsetAsync(t->err.p, 0, 4, s));
+  if (n > 0)
+    k_sph_particles<T><<<nblk(n), 256, 0, s>>>(
+        h, t->perm.as<int32_t>(), t->psrc.as<P4<T>>(), t->pmass.as<T>(), t->pkappa.as<T>(), n,
+        t->sph_pos.as<P4<T>>(), t->sph_mk.as<double>(), t->err.as<int>());
+  TREVR_HIP(hipGetLastError());
+  int herr = 0;
+  TREVR_HIP(hipMemcpyAsync(&herr, t->err.p, 4, hipMemcpyDeviceToHost, s));
+  TREVR_HIP(hipStreamSynchronize(s));
+  if (herr & ERR_NONFINITE) return fail(TREVR_E_NONFINITE, "non-finite smoothing length");
+  if (herr & ERR_VALUE) return fail(TREVR_E_VALUE, "smoothing length not positive");
+  const BfsNode *bfs = t->bfs.as<BfsNode>();
+  for (int d = (int)t->level_cnt.size() - 1; d >= 0; --d) {
+    const BfsNode *lvl = bfs + t->level_off[d];
+    const int c = (int)t->level_cnt[d];
+    k_sph_bucket<T><<<nblk(c), 256, 0, s>>>(lvl, c, t->pmass.as<T>(), t->pkappa.as<T>(),
+                                            t->prho.as<T>(), t->sph_pos.as<P4<T>>(),
+                                            t->sph_mk.as<double>(), t->sph_dp.as<T>(),
+                                            t->sph_hmax.as<double>());
+    k_sph_internal<<<nblk(c), 256, 0, s>>>(lvl, c, t->n_right.as<int32_t>(),
+                                           t->sph_hmax.as<double>());
+  }
+  auto lists = [&](const int64_t *off, int32_t *out) {
+    k_sph_lists<T><<<nblk(m, 128), 128, 0, s>>>(
+        m, t->n_right.as<int32_t>(), t->n_skip.as<int32_t>(), t->n_first.as<int32_t>(),
+        t->n_count.as<int32_t>(), t->n_box.as<int32_t>(), t->box_root.as<int32_t>(),
+        t->n_lo.as<double>(), t->n_hi.as<double>(), t->sph_hmax.as<double>(),
+        t->sph_pos.as<P4<T>>(), t->sph_mk.as<double>(), off, t->sph_cnt.as<int32_t>(), out);
+  };
+  if (m > 0) lists(nullptr, nullptr);
+  int32_t *cnt = t->sph_cnt.as<int32_t>();
+  int64_t *off = t->sph_off.as<int64_t>();
+  size_t tmp = 0;
+  TREVR_HIP(rocprim::exclusive_scan(nullptr, tmp, cnt, off, (int64_t)0, (size_t)m,
+                                    rocprim::plus<int64_t>(), s));
+  if (tmp > t->sort_tmp.bytes) TREVR_HIP(t->sort_tmp.ensure(tmp));
+  tmp = t->sort_tmp.bytes;
+  TREVR_HIP(rocprim::exclusive_scan(t->sort_tmp.p, tmp, cnt, off, (int64_t)0, (size_t)m,
+                                    rocprim::plus<int64_t>(), s));
+  k_sph_total<<<1, 64, 0, s>>>(cnt, off, m, off + m);
+  TREVR_HIP(hipGetLastError());
+  int64_t total = 0;
+  TREVR_HIP(hipMemcpyAsync(&total, off + m, 8, hipMemcpyDeviceToHost, s));
+  TREVR_HIP(hipStreamSynchronize(s));
+  TREVR_HIP(t->sph_nb.ensure(4 * (size_t)(total > 0 ? total : 1)));
+  if (m > 0) lists(off, t->sph_nb.as<int32_t>());
+  TREVR_HIP(hipGetLastError());
+  TREVR_HIP(hipStreamSynchronize(s));
+  t->sph_entries = total;
+  t->sph_ok = true;
+  return TREVR_OK;
+}
+
+int sph_impl(trevr_tree *t, const void *h, hipStream_t s) {
+  t->sph_ok = false;
+  if (t->prec == TREVR_F64) return sph_typed<double>(t, (const double *)h, s);
+  return sph_typed<float>(t, (const float *)h, s);
+}
+
+// The absorber lists (input indices) and each cell's decision spread, to host
+// memory; with offsets == NULL only the number of list entries.
+int export_sph_impl(const trevr_tree *t, int64_t *n_entries, int64_t *offsets,
+                    int64_t *neighbours, double *spread, hipStream_t s) {
+  *n_entries = t->sph_entries;
+  if (!offsets) return TREVR_OK;
+  const int64_t m = t->m, e = t->sph_entries;
+  std::vector<int32_t> nb((size_t)(e > 0 ? e : 1)), perm((size_t)(t->n > 0 ? t->n : 1));
+  TREVR_HIP(hipMemcpyAsync(offsets, t->sph_off.p, 8 * (size_t)(m + 1), hipMemcpyDeviceToHost, s));
+  if (e > 0) TREVR_HIP(hipMemcpyAsync(nb.data(), t->sph_nb.p, 4 * (size_t)e, hipMemcpyDeviceToHost, s));
+  if (t->n > 0)
+    TREVR_HIP(hipMemcpyAsync(perm.data(), t->perm.p, 4 * (size_t)t->n, hipMemcpyDeviceToHost, s));
+  std::vector<double> dp((size_t)(m > 0 ? m : 1));
+  if (t->prec == TREVR_F64) {
+    if (m > 0) TREVR_HIP(hipMemcpyAsync(dp.data(), t->sph_dp.p, 8 * (size_t)m, hipMemcpyDeviceToHost, s));
+    TREVR_HIP(hipStreamSynchronize(s));
+  } else {
+    std::vector<float> f((size_t)(m > 0 ? m : 1));
+    if (m > 0) TREVR_HIP(hipMemcpyAsync(f.data(), t->sph_dp.p, 4 * (size_t)m, hipMemcpyDeviceToHost, s));
+    TREVR_HIP(hipStreamSynchronize(s));
+    for (int64_t p = 0; p < m; ++p) dp[(size_t)p] = (double)f[(size_t)p];
+  }
+  for (int64_t k = 0; k < e; ++k) neighbours[k] = perm[(size_t)nb[(size_t)k]];
+  if (spread)
+    for (int64_t p = 0; p < m; ++p) spread[p] = dp[(size_t)p];
+  return TREVR_OK;
+}
+
 // Refit: new mass, rho, kappa and lum on the positions of the build.  Each
 // particle's position must equal, value for value, the one the tree was built
 // from (then every key, and the whole topology, is unchanged); the values are
@@ -870,6 +1100,7 @@ static int refit_typed(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
 int refit_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   t->tape_ok = false;
   t->n_bands = 0;
+  t->sph_ok = false;
   if (t->prec == TREVR_F64) return refit_typed<double>(t, p, s);
   return refit_typed<float>(t, p, s);
 }
@@ -878,6 +1109,7 @@ int build_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   t->built = false;
   t->tape_ok = false;
   t->n_bands = 0;
+  t->sph_ok = false;
   if (p->prec == TREVR_F64) return build_typed<double>(t, p, s);
   return build_typed<float>(t, p, s);
 }

@@ -133,7 +133,7 @@ struct trevr_tree {
   // transport
   trevr::DevBuf walk, trace, key, psrc;
   // particles in sorted order
-  trevr::DevBuf perm, inv, leaf, pbox, pmass, prho;
+  trevr::DevBuf perm, inv, leaf, pbox, pmass, prho, pkappa;
   // per box
   trevr::DevBuf box_root, box_off, box_lo, box_hi, axis_tab;
   trevr::DevBuf axmask;  // per box: 3 u64, bit (62 - depth) set where that depth splits axis a
@@ -156,6 +156,13 @@ struct trevr_tree {
   int32_t n_bands = 0;
   trevr::DevBuf band_alpha, band_dmax, band_trace;
   trevr::DevBuf bs_A, bs_alpha, bs_amin, bs_amax, bs_amin_d, bs_amax_d, bs_dalpha;
+  // sub-bucket particle trace (trevr_set_sph), sorted order: per particle
+  // x, y, z, h (P4 with h in place of L) and m kappa; per cell the decision
+  // spread (-1 but at buckets) and the largest h of its absorbers; per bucket
+  // the absorbers whose kernel reaches its box (int64 offsets by cell)
+  bool sph_ok = false;
+  int64_t sph_entries = 0;
+  trevr::DevBuf sph_pos, sph_mk, sph_dp, sph_hmax, sph_cnt, sph_off, sph_nb;
   // tape of per-ray optical depths from the last recording flux call
   trevr::DevBuf tape, tape_next, tape_head, tape_ctr;
   int64_t tape_cap = 0;             // blocks of 64
@@ -179,6 +186,11 @@ int refit_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s);
 int bands_impl(trevr_tree *t, int nb, const void *kappa_bands, hipStream_t s);
 int flux_bands_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                     int64_t n_sinks, void *flux_bands, int32_t *counters, hipStream_t s);
+int sph_impl(trevr_tree *t, const void *h, hipStream_t s);
+int export_sph_impl(const trevr_tree *t, int64_t *n_entries, int64_t *offsets,
+                    int64_t *neighbours, double *spread, hipStream_t s);
+int flux_sph_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                  int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s);
 int export_tree_impl(const trevr_tree *t, int64_t *perm, int64_t *leaf_of, int64_t *node_i,
                      uint64_t *node_key, double *node_f, hipStream_t s);
 int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,

@@ -67,7 +67,7 @@ EXPORTED = (
     "trevr_get_adjoint_launch", "trevr_export_tree", "trevr_compute_flux_taped",
     "trevr_compute_flux_adjoint_taped", "trevr_reserve_tape", "trevr_compute_flux_vector",
     "trevr_refit_tree", "trevr_compute_flux_moments", "trevr_set_bands",
-    "trevr_compute_flux_bands",
+    "trevr_compute_flux_bands", "trevr_set_sph", "trevr_compute_flux_sph", "trevr_export_sph",
 )
 
 
@@ -107,6 +107,12 @@ def lib():
     L.trevr_set_bands.argtypes = [P, ctypes.c_int32, P, P]
     L.trevr_compute_flux_bands.restype = I
     L.trevr_compute_flux_bands.argtypes = [P, D, D, P, I64, P, P, P]
+    L.trevr_set_sph.restype = I
+    L.trevr_set_sph.argtypes = [P, P, P]
+    L.trevr_compute_flux_sph.restype = I
+    L.trevr_compute_flux_sph.argtypes = [P, D, D, P, I64, P, P, P]
+    L.trevr_export_sph.restype = I
+    L.trevr_export_sph.argtypes = [P, P, P, P, P, P]
     L.trevr_compute_flux_moments.restype = I
     L.trevr_compute_flux_moments.argtypes = [P, D, D, P, I64, P, P, P, P, P]
     L.trevr_compute_flux_vector.restype = I
@@ -312,6 +318,37 @@ class Tree:
         _check(lib().trevr_compute_flux_bands(self._h, float(theta_open), float(tau_ref),
                                               _ptr(s), ns, _ptr(Fb), _ptr(C), _stream()))
         return (Fb.t(), C) if counters else Fb.t()
+
+    def set_sph(self, h):
+        """Smoothing lengths h (n,), input order, for the particle trace below
+        the buckets (see flux_sph)."""
+        hv = torch.as_tensor(h, dtype=self.dtype, device=self.device).contiguous()
+        if hv.shape != (self.n,):
+            raise ValueError("h must have one entry per particle")
+        _check(lib().trevr_set_sph(self._h, _ptr(hv), _stream()))
+
+    def flux_sph(self, theta_open, tau_ref, sinks=None, counters=False, out=None):
+        """Flux with the SPH-style particle trace below the buckets."""
+        s, ns = self._sinks(sinks)
+        F = out if out is not None else torch.empty(ns, dtype=self.dtype, device=self.device)
+        C = torch.empty((ns, 5), dtype=torch.int32, device=self.device) if counters else None
+        _check(lib().trevr_compute_flux_sph(self._h, float(theta_open), float(tau_ref), _ptr(s),
+                                            ns, _ptr(F), _ptr(C), _stream()))
+        return (F, C) if counters else F
+
+    def export_sph(self):
+        """The absorber lists: (offsets[m + 1], neighbours (input indices), spread[m])."""
+        import numpy as np
+        m = self.info()["m"]
+        ne = ctypes.c_int64(0)
+        _check(lib().trevr_export_sph(self._h, ctypes.byref(ne), None, None, None, _stream()))
+        off = np.empty(m + 1, np.int64)
+        nb = np.empty(max(ne.value, 1), np.int64)
+        sp = np.empty(max(m, 1), np.float64)
+        _check(lib().trevr_export_sph(self._h, ctypes.byref(ne), off.ctypes.data_as(ctypes.c_void_p),
+                                      nb.ctypes.data_as(ctypes.c_void_p),
+                                      sp.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return off, nb[:ne.value], sp[:m]
 
     def adjoint_taped(self, grad_flux):
         """The adjoint for the arguments of the last flux(..., tape=True)."""
