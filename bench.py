@@ -137,6 +137,43 @@ def bands(torch, tree, w, reps=3):
             "sink_fluxes_per_s": n / (t * 1e-3)}
 
 
+def sph(torch, tree, w, reps=2):
+    """The particle trace below the buckets on the headline tree, smoothing
+    lengths h = 1.2 (m / rho)^(1/3): time to set them (absorber lists), and
+    HIP-event time of one flux call at the workload's theta_open and tau_ref."""
+    st = torch.cuda.current_stream()
+    m = torch.as_tensor(w["mass"], device="cuda").double()
+    rho = torch.as_tensor(w["rho"], device="cuda").double()
+    h = (1.2 * (m / rho) ** (1.0 / 3.0)).to(tree.dtype).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree.set_sph(h)
+    torch.cuda.synchronize()
+    set_ms = (time.perf_counter() - t0) * 1e3
+    off = tree.export_sph()[0]
+    n = int(w["pos"].shape[0])
+    out = {"workload": w["name"], "h": "1.2 (m/rho)^(1/3)", "set_sph_ms": set_ms,
+           "absorber_entries": int(off[-1])}
+
+    def t_of(tau_ref):
+        tree.flux_sph(w["theta"], tau_ref)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            tree.flux_sph(w["theta"], tau_ref)
+            b.record(st)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms))
+
+    t = t_of(w["tau_ref"])
+    out.update({"tau_ref": w["tau_ref"], "ms": t, "sink_fluxes_per_s": n / (t * 1e-3)})
+    return out
+
+
 def adjoint_ratio(torch, P, reps=3):
     from paper_1902_08083_amd import workloads as W
     w = W.c5()
@@ -357,6 +394,9 @@ def main():
     if not args.no_vector:
         log("three opacity bands on the same workload")
         out["bands"] = bands(torch, tree, w)
+    if not args.no_vector:
+        log("particle trace below the buckets on the same workload")
+        out["sph"] = sph(torch, tree, w)
     if not args.no_adjoint:
         log("adjoint ratio on the 2^20 workload")
         out["adjoint"] = adjoint_ratio(torch, P)

@@ -72,7 +72,8 @@ trevr_tree::~trevr_tree() {
                           &adj_part, &adj_heap, &adj_flux, &tape, &tape_next, &tape_head, &tape_ctr,
                           &band_alpha, &band_dmax, &band_trace, &bs_A, &bs_alpha, &bs_amin,
                           &bs_amax, &bs_amin_d, &bs_amax_d, &bs_dalpha, &pkappa, &sph_pos,
-                          &sph_mk, &sph_dp, &sph_hmax, &sph_cnt, &sph_off, &sph_nb};
+                          &sph_mk, &sph_dp, &sph_hmax, &sph_cnt, &sph_off, &sph_nb,
+                          &sph_trace};
   for (auto *b : all) b->release();
   if (tape_used_h) (void)hipHostFree(tape_used_h);
 }

@@ -62,10 +62,9 @@ struct FluxArgs {
   const T *__restrict__ band_alpha;
   int32_t n_bands;
   T *flux_bands;  // [n_bands][n_sinks]
-  // sub-bucket particle trace (kernels with SPH): per cell the decision
-  // spread (-1 but at buckets), per bucket its absorbers (sorted indices,
+  // sub-bucket particle trace (kernels with SPH; a.TR then carries each
+  // bucket's particle spread): per bucket its absorbers (sorted indices,
   // int64 offsets by cell), per particle x, y, z, h and m kappa
-  const T *__restrict__ sph_dp;
   const int64_t *__restrict__ sph_off;
   const int32_t *__restrict__ sph_nb;
   const P4<T> *__restrict__ sph_pos;
@@ -165,6 +164,13 @@ __device__ __forceinline__ void gbl_add(double *p, double v) {
   (void)__builtin_amdgcn_global_atomic_fadd_f64((gbl_f64 *)p, v);
 }
 
+// Orders a wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
@@ -226,13 +232,17 @@ __device__ __forceinline__ void stack_pop(const RayCtx &c, const StackSpill &ovf
 // depth, [64, 128) the walk path at that depth, -1 the cell itself.
 constexpr int kSlotSrc = 64;
 
+// A policy receives each piece as (cell, slot, alpha, length, entry t and
+// plane, exit t and plane, spread) -- spread: for a bucket, its record's
+// spread field (the particle spread in the particle-trace kernel's records),
+// -1 for other cells.
 // Forward policy: tau = sum alpha l (eq. tausum).  kLight picks the form of
 // the refinement step (see refine_branchy).
 struct TauSum {
   static constexpr bool kLight = false;
   double tau = 0.0;
   __device__ __forceinline__ void operator()(int, int, double alpha, double l, double, int,
-                                             double, int) {
+                                             double, int, double) {
     tau += alpha * l;
   }
 };
@@ -253,7 +263,7 @@ struct BandSum {
   int nb;
   double tau[kMaxBands] = {0.0, 0.0, 0.0, 0.0};
   __device__ __forceinline__ void operator()(int node, int, double, double l, double, int,
-                                             double, int) {
+                                             double, int, double) {
     for (int b = 0; b < kMaxBands; ++b)
       if (b < nb) tau[b] += (double)ba[(int64_t)b * m + node] * l;
   }
@@ -309,39 +319,178 @@ __device__ __forceinline__ double m4_line(double b, double h, double u0, double 
 // spread fails the refinement test, spread * l > tau_ref, takes the particle
 // trace -- each of the bucket's absorbers but the receiving particle adds
 // m kappa times its kernel's integral over the piece; every other piece adds
-// alpha l as in eq. (tausum).
+// alpha l as in eq. (tausum).  Few pieces take the particle trace, each with a
+// list of a few hundred absorbers, so a lane leaves its first kSphJobs such
+// pieces as jobs that the whole wave runs after the round's trace (sph_jobs);
+// further ones it traces itself.
+constexpr int kSphJobs = 4;
+
+// The ray for absorber terms: binary64, and binary32 for the rejection test.
+struct SphRay {
+  double xi[3], d[3], r, r2;
+  float xf[3], df[3], inv_r2f, inv_rf;
+  float slack;  // 4e-6 of the magnitude of the ray's coordinates (and of its length)
+  int self;     // the receiving particle (sorted index)
+  __device__ __forceinline__ void finish() {
+    double mag = r;
+    for (int a = 0; a < 3; ++a) {
+      xf[a] = (float)xi[a];
+      df[a] = (float)d[a];
+      const double a0 = fabs(xi[a]), a1 = fabs(xi[a] + d[a]);
+      mag = fmax(mag, fmax(a0, a1) + r);
+    }
+    inv_r2f = (float)(1.0 / r2);
+    inv_rf = (float)(1.0 / r);
+    slack = (float)(4e-6 * mag);
+  }
+  // whether absorber j's support may reach the piece (never false for one
+  // whose term is not zero; false for the receiver)
+  template <typename T>
+  __device__ __forceinline__ bool reaches(const P4<T> *pos, int j, float taf, float tbf) const {
+    if (j == self) return false;
+    const P4<T> pj = pos[j];
+    // Rejection in binary32: the absorber's distance to the line, or its
+    // closest approach beyond the piece's ends, exceeds 2h (1 + 1e-3) + slack.
+    // The binary32 error of both, in length, is below 1e-6 of the
+    // coordinates' magnitude, which slack covers four times over, so a
+    // rejected absorber's term is exactly zero in binary64 as well.
+    const float ex = (float)pj.x - xf[0], ey = (float)pj.y - xf[1], ez = (float)pj.z - xf[2];
+    const float tsf = ((ex * df[0] + ey * df[1]) + ez * df[2]) * inv_r2f;
+    const float px = ex - tsf * df[0], py = ey - tsf * df[1], pz = ez - tsf * df[2];
+    const float reach = 2.002f * (float)pj.L + slack;
+    if ((px * px + py * py) + pz * pz >= reach * reach) return false;
+    const float win = reach * inv_rf;
+    return !(tsf <= taf - win || tsf >= tbf + win);
+  }
+  // absorber j's term m kappa (integral of W along the piece), binary64
+  template <typename T>
+  __device__ __forceinline__ double exact(const P4<T> *pos, const double *mk, int j, double ta,
+                                          double tb) const {
+    const P4<T> pj = pos[j];
+    const double dl0 = (double)pj.x - xi[0], dl1 = (double)pj.y - xi[1],
+                 dl2 = (double)pj.z - xi[2];
+    const double ts = ((dl0 * d[0] + dl1 * d[1]) + dl2 * d[2]) / r2;  // closest approach
+    const double p0 = dl0 - ts * d[0], p1 = dl1 - ts * d[1], p2 = dl2 - ts * d[2];
+    const double b = sqrt((p0 * p0 + p1 * p1) + p2 * p2);
+    return mk[j] * m4_line(b, (double)pj.L, (ta - ts) * r, (tb - ts) * r);
+  }
+};
+
 template <typename T>
 struct SphSum {
   static constexpr bool kLight = false;
-  const T *dp;
   const int64_t *off;
   const int32_t *nb;
   const P4<T> *pos;
   const double *mk;
-  double xi[3], d[3], r, r2, tau_ref;
-  int self;  // the receiver (sorted index)
+  const RayCtx *c;  // the lane's ray (xi, d, r, r2)
+  double tau_ref;
+  int self;  // the receiving particle (sorted index)
   double tau = 0.0;
+  int nj = 0;  // jobs left for the wave: bucket, piece ends
+  int jn[kSphJobs];
+  double jta[kSphJobs], jtb[kSphJobs];
+
   __device__ __forceinline__ void operator()(int node, int, double alpha, double l, double ta,
-                                             int, double tb, int) {
-    const double spread = (double)dp[node];
+                                             int, double tb, int, double spread) {
     if (!(spread >= 0.0 && spread * l > tau_ref)) {
       tau += alpha * l;
       return;
     }
+    if (nj < kSphJobs) {  // selects keep the job slots in registers
+      for (int q = 0; q < kSphJobs; ++q)
+        if (q == nj) {
+          jn[q] = node;
+          jta[q] = ta;
+          jtb[q] = tb;
+        }
+      ++nj;
+      return;
+    }
+    SphRay g;
+    for (int a = 0; a < 3; ++a) {
+      g.xi[a] = c->xi[a];
+      g.d[a] = c->d[a];
+    }
+    g.r = c->r;
+    g.r2 = c->r2;
+    g.self = self;
+    g.finish();
     const int64_t e = off[node + 1];
+    const float taf = (float)ta, tbf = (float)tb;
     for (int64_t k = off[node]; k < e; ++k) {
       const int j = nb[k];
-      if (j == self) continue;
-      const P4<T> pj = pos[j];
-      const double dl0 = (double)pj.x - xi[0], dl1 = (double)pj.y - xi[1],
-                   dl2 = (double)pj.z - xi[2];
-      const double ts = ((dl0 * d[0] + dl1 * d[1]) + dl2 * d[2]) / r2;  // closest approach
-      const double p0 = dl0 - ts * d[0], p1 = dl1 - ts * d[1], p2 = dl2 - ts * d[2];
-      const double b = sqrt((p0 * p0 + p1 * p1) + p2 * p2);
-      tau += mk[j] * m4_line(b, (double)pj.L, (ta - ts) * r, (tb - ts) * r);
+      if (g.reaches(pos, j, taf, tbf)) tau += g.exact(pos, mk, j, ta, tb);
     }
   }
 };
+
+// The jobs of every lane's SphSum, one at a time, by the whole wave.  The
+// lanes test the bucket's absorbers 64 at a time and pack those that reach
+// the piece into an LDS buffer of the wave (kSphBuf entries; the refinement
+// stack's, which is free between rays); the packed ones are then evaluated
+// in binary64, lane i taking entries i, i + 64, ...  The terms are summed in a
+// fixed order (per lane, then a butterfly over the wave) and the sum is added
+// to the job's lane.  Called by all lanes of the wave together; c is the
+// lane's ray.
+constexpr int kSphBuf = 1024;
+template <typename T>
+__device__ __forceinline__ void sph_jobs(SphSum<T> &ss, const RayCtx &c, int lane,
+                                         int32_t *buf) {
+  const uint64_t below = (1ull << lane) - 1;
+  lds_i32 *lb = (lds_i32 *)buf;
+  for (int q = 0; q < kSphJobs; ++q) {
+    uint64_t pend = __ballot(ss.nj > q);
+    while (pend) {
+      const int L = __ffsll((unsigned long long)pend) - 1;
+      pend &= pend - 1;
+      int node = 0;
+      double ta = 0.0, tb = 0.0;
+      for (int u = 0; u < kSphJobs; ++u)
+        if (u == q) {
+          node = ss.jn[u];
+          ta = ss.jta[u];
+          tb = ss.jtb[u];
+        }
+      node = __shfl(node, L);
+      ta = __shfl(ta, L);
+      tb = __shfl(tb, L);
+      SphRay g;  // the job lane's ray
+      for (int a = 0; a < 3; ++a) {
+        g.xi[a] = __shfl(c.xi[a], L);
+        g.d[a] = __shfl(c.d[a], L);
+      }
+      g.r = __shfl(c.r, L);
+      g.r2 = __shfl(c.r2, L);
+      g.self = __shfl(ss.self, L);
+      g.finish();
+      const float taf = (float)ta, tbf = (float)tb;
+      const int64_t b0 = ss.off[node], e = ss.off[node + 1];
+      double part = 0.0;
+      int nbuf = 0;
+      for (int64_t k0 = b0; k0 < e; k0 += 64) {
+        const int64_t k = k0 + lane;
+        int j = 0;
+        bool hit = false;
+        if (k < e) {
+          j = ss.nb[k];
+          hit = g.reaches(ss.pos, j, taf, tbf);
+        }
+        const uint64_t bm = __ballot(hit);
+        if (hit) lb[nbuf + __popcll(bm & below)] = j;
+        nbuf += __popcll(bm);
+        if (nbuf > kSphBuf - 64 || k0 + 64 >= e) {
+          wave_sync();
+          for (int i = lane; i < nbuf; i += 64) part += g.exact(ss.pos, ss.mk, lb[i], ta, tb);
+          wave_sync();
+          nbuf = 0;
+        }
+      }
+      part = wave_sum(part);
+      if (lane == L) ss.tau += part;
+    }
+  }
+}
 
 // Adjoint policy: d loss / d alpha_cell += -g l, and d tau / d y gets
 // r alpha (d tb/dy - d ta/dy) with d t/d y_a = -t / d_a for a plane crossing:
@@ -384,7 +533,7 @@ struct Scatter {
       gbl_add(&abar[node], v);
   }
   __device__ __forceinline__ void operator()(int node, int slot, double alpha, double l,
-                                             double ta, int ga, double tb, int gb) {
+                                             double ta, int ga, double tb, int gb, double) {
     const double v = -(g * l);
     if (slot >= kSlotSrc) {  // a source-side cell: pooled while it is on the walk's path
       const int dd = slot - kSlotSrc;
@@ -438,7 +587,8 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
     int ncur = cur;
     if (!split_it) {
       if (l > 0) c.n_seg++;
-      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb);
+      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb,
+           right == 0 ? (double)rec.dalpha : -1.0);
       go = sp > base;
       if (go) {
         int nd, tg;
@@ -580,7 +730,8 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
     raw = tr_fetch(TR, done ? cur : ncur);
     if (!split_it) {
       if (l > 0) c.n_seg++;
-      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb);
+      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb,
+           right == 0 ? (double)rec.dalpha : -1.0);
     }
     if (done) return;  // no entry left; an empty interval only at the top call
     cur = ncur;
@@ -620,7 +771,7 @@ __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
     return;
   }
   if (l > 0) c.n_seg++;
-  emit(P, slot, (double)rP.alpha, l, ta, ga, tb, gb);
+  emit(P, slot, (double)rP.alpha, l, ta, ga, tb, gb, -1.0);
 }
 
 // The sink's bucket and where its ancestors are kept: depths <= dpre are
@@ -632,6 +783,7 @@ struct SinkCtx {
   uint64_t keyS;
   int depthS;
   double alphaS;
+  double spreadS;  // the bucket's particle spread (particle-trace kernel), else 0
   uint64_t axm[3];  // the box's split axis masks over path-bit positions
   int root;
   int dpre;
@@ -673,7 +825,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     c.n_trace++;
     const double l = c.r * (1.0 - 0.0);
     if (l > 0) c.n_seg++;
-    emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, 1.0, -1);
+    emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, 1.0, -1, sk.spreadS);
     return;
   }
   StackSpill ovf;
@@ -747,7 +899,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     c.n_trace++;
     const double l = c.r * (tP - 0.0);
     if (l > 0) c.n_seg++;
-    emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, tP, gP);
+    emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, tP, gP, sk.spreadS);
   }
   // source side, [tQ, 1]: C's ancestors below A are found walking down from
   // A along C's path bits.  A lower child is the next cell in depth-first
@@ -843,13 +995,6 @@ static_assert(occ_lds<false>(5) * 20 <= kLdsPerCu && occ_lds<true>(5) * 20 <= kL
 static_assert(occ_lds<false>(6) * 24 <= kLdsPerCu && occ_lds<true>(6) * 24 <= kLdsPerCu, "");
 static_assert(occ_lds<false>(8) * 32 <= kLdsPerCu && occ_lds<true>(8) * 32 <= kLdsPerCu, "");
 
-// Orders a wave's LDS writes before its later LDS reads by other lanes.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source, not a cell
 
 // The source walk of 64 sinks, one per lane, shared by the wave (Sec. 2.2.1).
@@ -939,6 +1084,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     sk.keyS = a.key[sk.S];
     sk.depthS = a.ndepth[sk.S];
     sk.alphaS = (double)a.TR[sk.S].alpha;
+    sk.spreadS = SPH > 0 ? (double)a.TR[sk.S].dalpha : 0.0;
     const int my_box = a.pbox[k];
     const int my_root = a.box_root[my_box];
     sk.axm[0] = a.axmask[3 * my_box + 0];
@@ -1022,6 +1168,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       tk.keyS = __shfl(sk.keyS, owner);
       tk.depthS = __shfl(sk.depthS, owner);
       tk.alphaS = __shfl(sk.alphaS, owner);
+      tk.spreadS = SPH > 0 ? __shfl(sk.spreadS, owner) : 0.0;
       tk.axm[0] = __shfl(sk.axm[0], owner);
       tk.axm[1] = __shfl(sk.axm[1], owner);
       tk.axm[2] = __shfl(sk.axm[2], owner);
@@ -1064,6 +1211,12 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         if (busy) tau_rec = a.tape[(int64_t)tblk * 64 + lane];
         tcur = a.tape_next[tblk];
       }
+      SphSum<T> ss;       // (SPH) the particle trace, with its jobs for the wave
+      double sph_L = 0.0;
+      ss.off = a.sph_off;
+      ss.nb = a.sph_nb;
+      ss.pos = a.sph_pos;
+      ss.mk = a.sph_mk;
       if (busy) {
         const bool psrc = (e & kQParticle) != 0;
         const int id = (int)(e & ~kQParticle);
@@ -1093,22 +1246,12 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         ray_setup(c, (double)yx, (double)yy, (double)yz);
         std::conditional_t<ADJ, TauSumA, TauSum> ts;
         if constexpr (SPH > 0) {  // particle trace below the buckets
-          SphSum<T> ss;
-          ss.dp = a.sph_dp;
-          ss.off = a.sph_off;
-          ss.nb = a.sph_nb;
-          ss.pos = a.sph_pos;
-          ss.mk = a.sph_mk;
-          for (int q3 = 0; q3 < 3; ++q3) {
-            ss.xi[q3] = c.xi[q3];
-            ss.d[q3] = c.d[q3];
-          }
-          ss.r = c.r;
-          ss.r2 = c.r2;
+          ss.c = &c;
           ss.tau_ref = c.tau_ref;
           ss.self = self_k;
           trace_pieces<T>(a, C, keyC, depthC, tk, c, ss);
           ts.tau = ss.tau;
+          sph_L = (double)L;
         } else if constexpr (NBND > 0) {  // one traversal, one tau per band
           BandSum<T> bsum;
           bsum.ba = a.band_alpha;
@@ -1171,6 +1314,12 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
             for (int q3 = 0; q3 < 3; ++q3)
               sv[1 + q3] = sc.g * (-2.0 * c.d[q3] / c.r2 - sc.dtdy[q3]);
         }
+      }
+      if constexpr (SPH > 0) {  // the round's particle-trace jobs, by the whole wave
+        const bool had = ss.nj > 0;
+        static_assert(SPH == 0 || KR * 64 * 8 >= kSphBuf * 4, "job buffer in the stack's LDS");
+        sph_jobs<T>(ss, c, lane, reinterpret_cast<int32_t *>(s_stb));
+        if (had) f = (sph_L * exp(-ss.tau)) / ((4.0 * M_PI) * c.r2);
       }
       if (ADJ) {
         // Rays of one source are adjacent in the queue (a visited cell's
@@ -1721,7 +1870,7 @@ static int flux_sph_typed(const trevr_tree *t, double theta, double tau_ref,
                           hipStream_t s) {
   if (n_sinks == 0) return TREVR_OK;
   FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
-  a.sph_dp = t->sph_dp.as<T>();
+  a.TR = static_cast<const TraceRecT<T> *>(t->sph_trace.p);  // buckets: particle spread
   a.sph_off = t->sph_off.as<int64_t>();
   a.sph_nb = t->sph_nb.as<int32_t>();
   a.sph_pos = t->sph_pos.as<P4<T>>();

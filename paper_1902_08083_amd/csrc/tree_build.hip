@@ -949,6 +949,17 @@ __global__ void k_sph_lists(int64_t m, const int32_t *right, const int32_t *skip
   if (!off) cnt[p] = found;
 }
 
+// The walk's trace records with each bucket's particle spread in its spread
+// field (a bucket's own spread is never used to split it).
+template <typename T>
+__global__ void k_sph_records(const TraceRecT<T> *TR, const T *dp, int64_t m, TraceRecT<T> *out) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  TraceRecT<T> r = TR[p];
+  if (rax_right(r.right_ax) == 0) r.dalpha = dp[p];
+  out[p] = r;
+}
+
 __global__ void k_sph_total(const int32_t *cnt, const int64_t *off, int64_t m, int64_t *tot) {
   if (threadIdx.x == 0 && blockIdx.x == 0)
     tot[0] = m > 0 ? off[m - 1] + (int64_t)cnt[m - 1] : 0;
@@ -964,6 +975,7 @@ static int sph_typed(trevr_tree *t, const T *h, hipStream_t s) {
   TREVR_HIP(t->sph_hmax.ensure(8 * mm));
   TREVR_HIP(t->sph_cnt.ensure(4 * mm));
   TREVR_HIP(t->sph_off.ensure(8 * (mm + 1)));
+  TREVR_HIP(t->sph_trace.ensure(sizeof(TraceRecT<T>) * mm));
   TREVR_HIP(hipMemsetAsync(t->err.p, 0, 4, s));
   if (n > 0)
     k_sph_particles<T><<<nblk(n), 256, 0, s>>>(
@@ -993,7 +1005,11 @@ static int sph_typed(trevr_tree *t, const T *h, hipStream_t s) {
         t->n_lo.as<double>(), t->n_hi.as<double>(), t->sph_hmax.as<double>(),
         t->sph_pos.as<P4<T>>(), t->sph_mk.as<double>(), off, t->sph_cnt.as<int32_t>(), out);
   };
-  if (m > 0) lists(nullptr, nullptr);
+  if (m > 0) {
+    k_sph_records<T><<<nblk(m), 256, 0, s>>>(t->trace.as<TraceRecT<T>>(), t->sph_dp.as<T>(), m,
+                                             t->sph_trace.as<TraceRecT<T>>());
+    lists(nullptr, nullptr);
+  }
   int32_t *cnt = t->sph_cnt.as<int32_t>();
   int64_t *off = t->sph_off.as<int64_t>();
   size_t tmp = 0;

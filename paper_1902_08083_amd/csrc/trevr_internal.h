@@ -159,10 +159,11 @@ struct trevr_tree {
   // sub-bucket particle trace (trevr_set_sph), sorted order: per particle
   // x, y, z, h (P4 with h in place of L) and m kappa; per cell the decision
   // spread (-1 but at buckets) and the largest h of its absorbers; per bucket
-  // the absorbers whose kernel reaches its box (int64 offsets by cell)
+  // the absorbers whose kernel reaches its box (int64 offsets by cell); trace
+  // records whose buckets carry their particle spread
   bool sph_ok = false;
   int64_t sph_entries = 0;
-  trevr::DevBuf sph_pos, sph_mk, sph_dp, sph_hmax, sph_cnt, sph_off, sph_nb;
+  trevr::DevBuf sph_pos, sph_mk, sph_dp, sph_hmax, sph_cnt, sph_off, sph_nb, sph_trace;
   // tape of per-ray optical depths from the last recording flux call
   trevr::DevBuf tape, tape_next, tape_head, tape_ctr;
   int64_t tape_cap = 0;             // blocks of 64

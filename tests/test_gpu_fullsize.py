@@ -5,6 +5,8 @@ times (default launch shapes).
     moment and three opacity bands at every sink in one launch; the oracle
     evaluates a seeded sample of sinks (within 1e-5 of the flux in binary32
     transport, counters identical for the bands);
+  * the same workload with the particle trace below the buckets (smoothing
+    lengths 1.2 (m / rho)^(1/3)), sampled sinks against the oracle;
   * 2^20 particles (the adjoint workload): the recording flux and the taped
     adjoint at every particle, checked through identities that hold at any
     size: sum L dLoss/dL = sum w F (the flux is linear in L) and
@@ -89,3 +91,21 @@ def test_c5_full_size_taped_adjoint_identities():
     _note("sum kappa dkappa %.9g, sum rho drho %.9g" % (sk, sr))
     assert abs(sk - sr) <= 2e-5 * max(abs(sk), abs(sr))
     assert sk < 0  # more opacity, less flux
+
+
+def test_c3_full_size_sph_sampled():
+    _note("c3 full size (2^21): particle trace below the buckets; sampled")
+    w = W.c3()
+    th, tr = w["theta"], w["tau_ref"]
+    tg, to = _trees(w)
+    h = (1.2 * (np.asarray(w["mass"], np.float64) / np.asarray(w["rho"], np.float64))
+         ** (1.0 / 3.0)).astype(np.float32)
+    tg.set_sph(torch.as_tensor(h, device="cuda"))
+    F, C = tg.flux_sph(th, tr, counters=True)
+    F, C = F.double().cpu().numpy(), C.cpu().numpy()
+    to.set_sph(h.astype(np.float64))
+    sample = np.sort(np.random.default_rng(12).choice(w["pos"].shape[0], size=256,
+                                                      replace=False))
+    Fo, Co = to.flux_sph(th, tr, sinks=sample, nthreads=NTHREADS)
+    assert np.array_equal(C[sample].astype(np.int64), Co)
+    assert np.max(np.abs(F[sample] - Fo) / Fo) <= 1e-5
