@@ -89,6 +89,13 @@ def lib():
         L.oracle_ray_log_sph.restype = ctypes.c_int64
         L.oracle_ray_log_sph.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                          ctypes.c_int64] + [P] * 6
+        L.oracle_flux_variant.restype = ctypes.c_int
+        L.oracle_flux_variant.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_double, P, ctypes.c_int64,
+                                          ctypes.c_int, P, P]
+        L.oracle_ray_log_variant.restype = ctypes.c_int64
+        L.oracle_ray_log_variant.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int64, ctypes.c_int64] + [P] * 6
         L.oracle_ray_log.restype = ctypes.c_int64
         L.oracle_ray_log.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                      ctypes.c_int64] + [P] * 6
@@ -211,6 +218,37 @@ class OracleTree:
         if rc != 0:
             raise ValueError("oracle_flux_bands rejected its arguments")
         return Fb, C
+
+    # ---- walk variants ----
+    def flux_variant(self, theta, tau_ref, open_mode=0, ray_mode=0, tau_max=np.inf, sinks=None,
+                     nthreads=0):
+        """Flux with a walk variant: open_mode 0 (sink point, eq. openangle), 1 (the
+        sink's bucket box), 2 (Gasoline's r_open about x_L); ray_mode 0 (up the
+        tree), 1 (top down from the meeting cell); rays with tau > tau_max
+        contribute nothing.  Returns (F, counters[ns, 5])."""
+        s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+        ns = self.n if s is None else int(s.shape[0])
+        F = np.empty(ns, np.float64)
+        C = np.empty((ns, 5), np.int64)
+        rc = lib().oracle_flux_variant(self._h, float(theta), float(tau_ref), int(open_mode),
+                                       int(ray_mode), float(tau_max), _ptr(s), ns,
+                                       int(nthreads), _ptr(F), _ptr(C))
+        if rc != 0:
+            raise ValueError("oracle_flux_variant rejected its arguments")
+        return F, C
+
+    def ray_log_variant(self, theta, tau_ref, sink, open_mode=0, ray_mode=0, cap=1 << 20):
+        C = np.empty(cap, np.int64)
+        src = np.empty(cap, np.int64)
+        y = np.empty((cap, 3), np.float64)
+        L = np.empty(cap, np.float64)
+        tau = np.empty(cap, np.float64)
+        f = np.empty(cap, np.float64)
+        nr = lib().oracle_ray_log_variant(self._h, float(theta), float(tau_ref), int(open_mode),
+                                          int(ray_mode), int(sink), cap, _ptr(C), _ptr(src),
+                                          _ptr(y), _ptr(L), _ptr(tau), _ptr(f))
+        k = min(nr, cap)
+        return {"C": C[:k], "src": src[:k], "y": y[:k], "L": L[:k], "tau": tau[:k], "f": f[:k]}
 
     # ---- sub-bucket particle trace ----
     def set_sph(self, h):

@@ -25,6 +25,8 @@
  *   Sec. 2.2.3, eq. (refcrit): refine where tau_ref < (alpha_max-alpha_min) l;
  *                   directional alpha_min / alpha_max built bottom-up
  *   Sec. 2.3:       volume-weighted cell density sum(m)/sum(m/rho)
+ *   Sec. 2.3, 3 (walk variants): a per-bucket opening test, Gasoline's opening
+ *                   radius, a top-down ray walk, early termination past tau_max
  *   Sec. 2.2.3 and 2.3 (sub-bucket refinement): below a bucket, an SPH-style
  *                   particle trace, tau = sum_j m_j kappa_j (integral of the
  *                   smoothing kernel along the ray), the receiver excluded
@@ -517,6 +519,12 @@ typedef struct {
   double Pm[6]; /* second moment: sum of f n_a n_b (xx, yy, zz, xy, xz, yz) */
   int bands;     /* band mode: per-band tau and flux, band-maximum spread */
   int sph;       /* sub-bucket particle trace below the buckets */
+  /* walk variants: opening test 0 eq. (openangle) at the sink point, 1 at the
+   * sink's bucket box, 2 Gasoline's opening radius about x_L; ray walk 0 up
+   * the tree (Sec. 2.2.2), 1 top down from the meeting cell; rays with
+   * tau > tau_max contribute nothing (early termination) */
+  int open_mode, ray_mode;
+  double tau_max;
   double Fb[8];
   int64_t n_open, n_rays, n_psrc, n_seg, n_trace;
   /* adjoint accumulators (NULL in a forward pass) */
@@ -843,6 +851,12 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
     int a = __builtin_clzll(kS ^ kC) - 1; /* depth of the meeting cell */
     int64_t A = S;
     while (t->nd[A].depth > a) A = t->nd[A].parent;
+    if (c->ray_mode == 1) {
+      /* top down (Sec. 3 discussion of other walks): the meeting cell holds
+       * the whole ray; refine it from there by eq. (refcrit) alone */
+      refine(c, &ry, A, 0.0, -1, 1.0, -1);
+      goto done;
+    }
     int axA = t->axis[a];
     double sA = t->nd[A].t_split;
     int sr = key_bit(kS, a), cr = key_bit(kC, a);
@@ -917,7 +931,9 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
     }
     refine(c, &ry, C, tQ, gQ, 1.0, -1);
   }
-  double f = (L * exp(-ry.tau)) / ((4.0 * M_PI) * ry.r2);
+done:;
+  /* early termination: a ray past tau_max contributes nothing */
+  double f = ry.tau > c->tau_max ? 0.0 : (L * exp(-ry.tau)) / ((4.0 * M_PI) * ry.r2);
   c->F += f;
   c->G += f * ry.tau;
   if (c->bands)
@@ -999,7 +1015,30 @@ static void walk(osink *c, int64_t id) {
     dd[a] = g > 0.0 ? g : 0.0;
   }
   double r2 = (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2];
-  if (p->t_lfar * p->t_lfar < c->theta2 * r2) {
+  int accept = p->t_lfar * p->t_lfar < c->theta2 * r2;
+  if (c->open_mode == 1) {
+    /* per bucket: r from the sink's bucket box to the cell's box, so that
+     * every sink of a bucket takes the same decision */
+    const onode *b = &t->nd[c->S];
+    double g2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      double u = p->t_lo[a] - b->t_hi[a];
+      double v = b->t_lo[a] - p->t_hi[a];
+      double g = u > v ? u : v;
+      if (g > 0.0) g2 += g * g;
+    }
+    accept = p->t_lfar * p->t_lfar < c->theta2 * g2;
+  } else if (c->open_mode == 2) {
+    /* Gasoline (Sec. 2.3): opened inside r_open = 2 B_max / (sqrt(3) theta)
+     * about the centre (here x_L; B_max the distance to the furthest vertex,
+     * l_far), i.e. accepted where 3 theta^2 d^2 > 4 l_far^2; a cell holding
+     * the sink is always opened */
+    double e[3];
+    for (int a = 0; a < 3; ++a) e[a] = c->xi[a] - p->t_xl[a];
+    double d2 = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+    accept = r2 > 0.0 && 3.0 * c->theta2 * d2 > 4.0 * (p->t_lfar * p->t_lfar);
+  }
+  if (accept) {
     c->n_rays++;
     trace_ray(c, id, p->t_xl, p->t_lc, -1);
     return;
@@ -1029,6 +1068,7 @@ static void sink_init(osink *c, const otree *t, int64_t i, double theta,
   for (int a = 0; a < 3; ++a) c->xi[a] = t->x[3 * i + a];
   c->theta2 = theta * theta;
   c->tau_ref = tau_ref;
+  c->tau_max = INFINITY;
 }
 
 /* Flux (angle-summed intensity, eq. simpint summed over sources) at each
@@ -1176,6 +1216,59 @@ int64_t oracle_ray_log_sph(void *h, double theta, double tau_ref, int64_t sink, 
   osink c;
   sink_init(&c, t, sink, theta, tau_ref);
   c.sph = 1;
+  c.log_cap = cap;
+  c.log_C = C;
+  c.log_src = src;
+  c.log_y = y;
+  c.log_L = L;
+  c.log_tau = tau;
+  c.log_f = f;
+  walk(&c, 0);
+  return c.log_n;
+}
+
+/* Flux with the walk variants (open_mode 0, 1, 2; ray_mode 0, 1; tau_max,
+ * +infinity for none), otherwise as oracle_flux. */
+int oracle_flux_variant(void *h, double theta, double tau_ref, int open_mode, int ray_mode,
+                        double tau_max, const int64_t *sinks, int64_t ns, int nthreads,
+                        double *F, int64_t *counters) {
+  const otree *t = (const otree *)h;
+  if (!(theta >= 0) || open_mode < 0 || open_mode > 2 || ray_mode < 0 || ray_mode > 1 ||
+      !(tau_max > 0))
+    return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t q = 0; q < ns; ++q) {
+    int64_t i = sinks ? sinks[q] : q;
+    osink c;
+    sink_init(&c, t, i, theta, tau_ref);
+    c.open_mode = open_mode;
+    c.ray_mode = ray_mode;
+    c.tau_max = tau_max;
+    walk(&c, 0);
+    F[q] = c.F;
+    if (counters) {
+      counters[5 * q + 0] = c.n_open;
+      counters[5 * q + 1] = c.n_rays;
+      counters[5 * q + 2] = c.n_psrc;
+      counters[5 * q + 3] = c.n_seg;
+      counters[5 * q + 4] = c.n_trace;
+    }
+  }
+  return 0;
+}
+
+/* oracle_ray_log with the walk variants. */
+int64_t oracle_ray_log_variant(void *h, double theta, double tau_ref, int open_mode,
+                               int ray_mode, int64_t sink, int64_t cap, int64_t *C,
+                               int64_t *src, double *y, double *L, double *tau, double *f) {
+  const otree *t = (const otree *)h;
+  osink c;
+  sink_init(&c, t, sink, theta, tau_ref);
+  c.open_mode = open_mode;
+  c.ray_mode = ray_mode;
   c.log_cap = cap;
   c.log_C = C;
   c.log_src = src;
