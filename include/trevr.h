@@ -234,6 +234,35 @@ int trevr_compute_flux_bands(const trevr_tree *tree, double theta_open, double t
                              const int32_t *sinks, int64_t n_sinks, void *flux_bands,
                              int32_t *counters, hipStream_t stream);
 
+/* Walk variants the paper proposes (each a separate mode; 0 / 0 / +infinity
+ * is exactly trevr_compute_flux's traversal):
+ *   open_mode 0: eq. openangle at the sink point (the default);
+ *             1: per bucket -- r is the distance from the sink's bucket box
+ *                to the cell's box, so every sink of a bucket opens and merges
+ *                the same cells (the interaction list of Gasoline's bucket
+ *                walk);
+ *             2: Gasoline's opening radius (Sec. 2.3): a cell is merged when
+ *                the sink lies farther than r_open = 2 B_max / (sqrt(3) theta)
+ *                from its centre of luminosity (B_max: the distance from it
+ *                to the cell's furthest vertex) and outside the cell;
+ *   ray_mode  0: up the tree from the sink's bucket and the source cell
+ *                (Sec. 2.2.2, the default);
+ *             1: top down -- the meeting cell holds the whole ray, which is
+ *                refined from there by eq. refcrit alone (the more aggressive
+ *                walk Sec. 3 discusses);
+ *   tau_max:  early termination (Sec. 4) -- a ray whose optical depth exceeds
+ *             tau_max contributes nothing and is traced no further once its
+ *             partial sum passes it; +infinity for none.
+ * Arguments and results as trevr_compute_flux; with tau_max finite the
+ * counters count the pieces actually traced.  Runs a 3-wave kernel whatever
+ * the launch shape.  Asynchronous, allocates nothing.  Errors: as
+ * trevr_compute_flux, and TREVR_E_ARG for a mode out of range or
+ * tau_max <= 0 (NaN). */
+int trevr_compute_flux_variant(const trevr_tree *tree, double theta_open, double tau_ref,
+                               int32_t open_mode, int32_t ray_mode, double tau_max,
+                               const int32_t *sinks, int64_t n_sinks, void *flux,
+                               int32_t *counters, hipStream_t stream);
+
 /* Refinement below the buckets: a particle trace in the manner of SPHRay
  * (Sec. 2.2.3 and the ray-tracing passage of Sec. 2.3).  Where refinement
  * reaches a bucket and the bucket's own spread still fails the criterion,

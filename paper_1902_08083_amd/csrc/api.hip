@@ -150,6 +150,20 @@ int trevr_compute_flux_bands(const trevr_tree *tree, double theta_open, double t
                                 stream);
 }
 
+int trevr_compute_flux_variant(const trevr_tree *tree, double theta_open, double tau_ref,
+                               int32_t open_mode, int32_t ray_mode, double tau_max,
+                               const int32_t *sinks, int64_t n_sinks, void *flux,
+                               int32_t *counters, hipStream_t stream) {
+  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (open_mode < 0 || open_mode > 2) return trevr::fail(TREVR_E_ARG, "open_mode must be 0, 1 or 2");
+  if (ray_mode < 0 || ray_mode > 1) return trevr::fail(TREVR_E_ARG, "ray_mode must be 0 or 1");
+  if (!(tau_max > 0)) return trevr::fail(TREVR_E_ARG, "tau_max must be > 0 (or +infinity)");
+  if (n_sinks > 0 && !flux) return trevr::fail(TREVR_E_ARG, "flux is NULL");
+  return trevr::flux_variant_impl(tree, theta_open, tau_ref, open_mode, ray_mode, tau_max, sinks,
+                                  n_sinks, flux, counters, stream);
+}
+
 int trevr_set_sph(trevr_tree *tree, const void *h, hipStream_t stream) {
   if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
   if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");

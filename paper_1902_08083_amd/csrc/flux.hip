@@ -69,6 +69,12 @@ struct FluxArgs {
   const int32_t *__restrict__ sph_nb;
   const P4<T> *__restrict__ sph_pos;
   const double *__restrict__ sph_mk;
+  // walk variants (kernels with VAR): opening test 0 at the sink point,
+  // 1 at the sink's bucket box, 2 Gasoline's opening radius about x_L; ray
+  // walk 0 up the tree, 1 top down from the meeting cell; rays past tau_max
+  // contribute nothing (and stop being traced)
+  int32_t variant, open_mode, ray_mode;
+  double tau_max;
   int32_t *counters;
   int32_t *queue;  // kXcd counters
   // Tape of per-ray optical depths: one block of 64 per round, the blocks of
@@ -240,6 +246,7 @@ constexpr int kSlotSrc = 64;
 // the refinement step (see refine_branchy).
 struct TauSum {
   static constexpr bool kLight = false;
+  static constexpr bool kVar = false;  // walk variants: top-down walk, early stop
   double tau = 0.0;
   __device__ __forceinline__ void operator()(int, int, double alpha, double l, double, int,
                                              double, int, double) {
@@ -252,12 +259,21 @@ struct TauSumA : TauSum {
   static constexpr bool kLight = true;
 };
 
+// The sum of the walk variants: the tracer stops once tau passes tau_max
+// (pieces add non-negative terms, so the ray's full tau would too).
+struct TauVar : TauSum {
+  static constexpr bool kVar = true;
+  double tau_max;
+  __device__ __forceinline__ bool stop() const { return tau > tau_max; }
+};
+
 // Band policy: one tau per opacity band; a piece's alpha is that band's cell
 // value (the record's own alpha is not used).
 constexpr int kMaxBands = 4;
 template <typename T>
 struct BandSum {
   static constexpr bool kLight = false;
+  static constexpr bool kVar = false;
   const T *ba;
   int64_t m;
   int nb;
@@ -379,6 +395,7 @@ struct SphRay {
 template <typename T>
 struct SphSum {
   static constexpr bool kLight = false;
+  static constexpr bool kVar = false;
   const int64_t *off;
   const int32_t *nb;
   const P4<T> *pos;
@@ -498,6 +515,7 @@ __device__ __forceinline__ void sph_jobs(SphSum<T> &ss, const RayCtx &c, int lan
 // minus exits) are kept in u, and d tau / d y_a += r u_a / d_a once per ray.
 struct Scatter {
   static constexpr bool kLight = true;
+  static constexpr bool kVar = false;
   double g;        // weight * flux contribution of the ray
   double dtdy[3];  // d tau / d y
   double u[3];     // per axis: sum of alpha t over entry crossings minus exit crossings
@@ -590,6 +608,7 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
       emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb,
            right == 0 ? (double)rec.dalpha : -1.0);
       go = sp > base;
+      if constexpr (Emit::kVar) go = go && !emit.stop();
       if (go) {
         int nd, tg;
         double tt;
@@ -832,6 +851,12 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   int sp = 0;  // deferred refinement jobs on the lane's stack
   const int ad = __clzll((long long)(sk.keyS ^ keyC)) - 1;  // depth of the meeting cell
   const int A = sink_anc<T>(a.TR, sk, ad);
+  if constexpr (Emit::kVar) {
+    if (a.ray_mode == 1) {  // top down: the meeting cell holds the whole ray
+      refine<T>(a.TR, A, -1, 0.0, -1, 1.0, -1, c, ovf, 0, 0, emit);
+      return;
+    }
+  }
   const TraceRecT<T> rA = load_tr(a.TR, A);
   const int axA = rax_axis(rA.right_ax);
   const int sr = (int)((sk.keyS >> (62 - ad)) & 1);
@@ -875,6 +900,8 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   double tP = tA;
   int gP = gA;
   while (mS) {
+    if constexpr (Emit::kVar)
+      if (emit.stop()) return;
     const int pos = 63 - __clzll((long long)mS);
     mS &= ~(1ull << pos);
     const int dd = 62 - pos;
@@ -911,6 +938,8 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   int Q = ((keyC >> (62 - ad)) & 1) ? rax_right(rA.right_ax) : A + 1;  // at depth ad + 1
   int dq = ad + 1;
   while (stops) {
+    if constexpr (Emit::kVar)
+      if (emit.stop()) return;
     const int pos = 63 - __clzll((long long)stops);
     stops &= ~(1ull << pos);
     const int dd = 62 - pos;
@@ -935,6 +964,8 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     Q = b ? rax_right(rQ.right_ax) : Q + 1;
     dq = dd + 1;
   }
+  if constexpr (Emit::kVar)
+    if (emit.stop()) return;
   refine<T>(a.TR, C, kSlotSrc + depthC, tQ, gQ, 1.0, -1, c, ovf, sp, 0, emit);
 }
 
@@ -1007,7 +1038,8 @@ constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source,
 // owning sink's context by lane shuffles; each owner adds its results in
 // queue order, so a sink's sum is in its own walk order whatever the other
 // sinks of the wave are.
-template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0, int NBND = 0, int SPH = 0>
+template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0, int NBND = 0, int SPH = 0,
+          int VAR = 0>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
@@ -1084,6 +1116,14 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     sk.keyS = a.key[sk.S];
     sk.depthS = a.ndepth[sk.S];
     sk.alphaS = (double)a.TR[sk.S].alpha;
+    double bb_lo[3] = {0.0, 0.0, 0.0}, bb_hi[3] = {0.0, 0.0, 0.0};  // (VAR) the bucket's box
+    if (VAR > 0) {
+      const WalkRecT<T> &wb = a.W[sk.S];
+      for (int q3 = 0; q3 < 3; ++q3) {
+        bb_lo[q3] = (double)wb.lo[q3];
+        bb_hi[q3] = (double)wb.hi[q3];
+      }
+    }
     sk.spreadS = SPH > 0 ? (double)a.TR[sk.S].dalpha : 0.0;
     const int my_box = a.pbox[k];
     const int my_root = a.box_root[my_box];
@@ -1261,6 +1301,11 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           for (int b = 0; b < kMaxBands; ++b)
             if (b < a.n_bands)
               fb[b] = ((double)L * exp(-bsum.tau[b])) / ((4.0 * M_PI) * c.r2);
+        } else if constexpr (VAR > 0) {  // walk variants, with the early stop
+          TauVar tv;
+          tv.tau_max = a.tau_max;
+          trace_pieces<T>(a, C, keyC, depthC, tk, c, tv);
+          ts.tau = tv.tau;
         } else if (rp) {
           ts.tau = tau_rec;
         } else {
@@ -1268,6 +1313,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         }
         if (!ADJ && tblk >= 0) a.tape[(int64_t)tblk * 64 + lane] = ts.tau;
         f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
+        if (VAR > 0 && ts.tau > a.tau_max) f = 0.0;  // early termination
         if (MOM >= 1) {
           double nv[3];
           for (int q3 = 0; q3 < 3; ++q3) {
@@ -1521,6 +1567,23 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
             const double r2 = (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
             const double lf = (double)w.lfar;
             acc = lf * lf < a.theta2 * r2;
+            if constexpr (VAR > 0) {
+              if (a.open_mode == 1) {  // r from the sink's bucket box
+                for (int q3 = 0; q3 < 3; ++q3) {
+                  const double u = (double)w.lo[q3] - bb_hi[q3];
+                  const double v = bb_lo[q3] - (double)w.hi[q3];
+                  const double gg = u > v ? u : v;
+                  g[q3] = gg > 0.0 ? gg : 0.0;
+                }
+                const double rb2 = (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+                acc = lf * lf < a.theta2 * rb2;
+              } else if (a.open_mode == 2) {  // outside r_open about x_L, sink outside
+                const double e0 = xo[0] - (double)w.xl[0], e1 = xo[1] - (double)w.xl[1],
+                             e2 = xo[2] - (double)w.xl[2];
+                const double d2 = (e0 * e0 + e1 * e1) + e2 * e2;
+                acc = r2 > 0.0 && (3.0 * a.theta2) * d2 > 4.0 * (lf * lf);
+              }
+            }
           }
           const uint64_t accm = __ballot(acc);
           openm = active & ~accm;
@@ -1635,6 +1698,12 @@ template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3b(
     FluxArgs<T> a) {
   walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, kMaxBands>(a);
+}
+// The flux with the walk variants, at the 3-wave budget.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3x(
+    FluxArgs<T> a) {
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, 0, 0, 1>(a);
 }
 // The flux with the sub-bucket particle trace, at the 3-wave budget.
 template <typename T>
@@ -1767,6 +1836,14 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
+    if (a.variant) {  // the walk variants: the 3-wave kernel, at most 3 waves per SIMD
+      const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
+      int64_t vb = (int64_t)bpc * t->num_cu;
+      if (vb > need) vb = need;
+      k_walk3x<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      TREVR_HIP(hipGetLastError());
+      return TREVR_OK;
+    }
     if (a.sph_nb) {  // the particle trace: the 3-wave kernel, at most 3 waves per SIMD
       const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
@@ -1885,6 +1962,31 @@ int flux_sph_impl(const trevr_tree *t, double theta, double tau_ref, const int32
   if (t->prec == TREVR_F64)
     return flux_sph_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
   return flux_sph_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
+}
+
+template <typename T>
+static int flux_variant_typed(const trevr_tree *t, double theta, double tau_ref, int open_mode,
+                              int ray_mode, double tau_max, const int32_t *sinks,
+                              int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s) {
+  if (n_sinks == 0) return TREVR_OK;
+  FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
+  a.variant = 1;
+  a.open_mode = open_mode;
+  a.ray_mode = ray_mode;
+  a.tau_max = tau_max;
+  a.flux = static_cast<T *>(flux);
+  a.counters = counters;
+  return launch_walk<T, false>(t, a, s);
+}
+
+int flux_variant_impl(const trevr_tree *t, double theta, double tau_ref, int open_mode,
+                      int ray_mode, double tau_max, const int32_t *sinks, int64_t n_sinks,
+                      void *flux, int32_t *counters, hipStream_t s) {
+  if (t->prec == TREVR_F64)
+    return flux_variant_typed<double>(t, theta, tau_ref, open_mode, ray_mode, tau_max, sinks,
+                                      n_sinks, flux, counters, s);
+  return flux_variant_typed<float>(t, theta, tau_ref, open_mode, ray_mode, tau_max, sinks,
+                                   n_sinks, flux, counters, s);
 }
 
 int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,

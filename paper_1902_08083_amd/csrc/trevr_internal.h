@@ -187,6 +187,9 @@ int refit_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s);
 int bands_impl(trevr_tree *t, int nb, const void *kappa_bands, hipStream_t s);
 int flux_bands_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                     int64_t n_sinks, void *flux_bands, int32_t *counters, hipStream_t s);
+int flux_variant_impl(const trevr_tree *t, double theta, double tau_ref, int open_mode,
+                      int ray_mode, double tau_max, const int32_t *sinks, int64_t n_sinks,
+                      void *flux, int32_t *counters, hipStream_t s);
 int sph_impl(trevr_tree *t, const void *h, hipStream_t s);
 int export_sph_impl(const trevr_tree *t, int64_t *n_entries, int64_t *offsets,
                     int64_t *neighbours, double *spread, hipStream_t s);

@@ -68,6 +68,7 @@ EXPORTED = (
     "trevr_compute_flux_adjoint_taped", "trevr_reserve_tape", "trevr_compute_flux_vector",
     "trevr_refit_tree", "trevr_compute_flux_moments", "trevr_set_bands",
     "trevr_compute_flux_bands", "trevr_set_sph", "trevr_compute_flux_sph", "trevr_export_sph",
+    "trevr_compute_flux_variant",
 )
 
 
@@ -107,6 +108,9 @@ def lib():
     L.trevr_set_bands.argtypes = [P, ctypes.c_int32, P, P]
     L.trevr_compute_flux_bands.restype = I
     L.trevr_compute_flux_bands.argtypes = [P, D, D, P, I64, P, P, P]
+    L.trevr_compute_flux_variant.restype = I
+    L.trevr_compute_flux_variant.argtypes = [P, D, D, ctypes.c_int32, ctypes.c_int32, D, P, I64,
+                                             P, P, P]
     L.trevr_set_sph.restype = I
     L.trevr_set_sph.argtypes = [P, P, P]
     L.trevr_compute_flux_sph.restype = I
@@ -318,6 +322,19 @@ class Tree:
         _check(lib().trevr_compute_flux_bands(self._h, float(theta_open), float(tau_ref),
                                               _ptr(s), ns, _ptr(Fb), _ptr(C), _stream()))
         return (Fb.t(), C) if counters else Fb.t()
+
+    def flux_variant(self, theta_open, tau_ref, open_mode=0, ray_mode=0,
+                     tau_max=float("inf"), sinks=None, counters=False, out=None):
+        """Flux with a walk variant: open_mode 0 (sink point), 1 (the sink's
+        bucket box), 2 (Gasoline's opening radius); ray_mode 0 (up the tree),
+        1 (top down from the meeting cell); rays past tau_max contribute nothing."""
+        s, ns = self._sinks(sinks)
+        F = out if out is not None else torch.empty(ns, dtype=self.dtype, device=self.device)
+        C = torch.empty((ns, 5), dtype=torch.int32, device=self.device) if counters else None
+        _check(lib().trevr_compute_flux_variant(self._h, float(theta_open), float(tau_ref),
+                                                int(open_mode), int(ray_mode), float(tau_max),
+                                                _ptr(s), ns, _ptr(F), _ptr(C), _stream()))
+        return (F, C) if counters else F
 
     def set_sph(self, h):
         """Smoothing lengths h (n,), input order, for the particle trace below
