@@ -174,6 +174,35 @@ def sph(torch, tree, w, reps=2):
     return out
 
 
+def variants(torch, tree, w, reps=2):
+    """The walk variants on the headline tree: HIP-event time of one flux call
+    per variant, its ray segments per sink, and its median |F / F_plain - 1|."""
+    st = torch.cuda.current_stream()
+    th, tr = w["theta"], w["tau_ref"]
+    F0 = tree.flux(th, tr).double()
+    out = {"workload": w["name"]}
+    for name, om, rm, tmax in (("bucket_opening", 1, 0, float("inf")),
+                               ("gasoline_opening", 2, 0, float("inf")),
+                               ("top_down", 0, 1, float("inf")),
+                               ("early_termination_tau_max_10", 0, 0, 10.0)):
+        F, C = tree.flux_variant(th, tr, om, rm, tmax, counters=True)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            tree.flux_variant(th, tr, om, rm, tmax)
+            b.record(st)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        dev = (F.double() / F0 - 1.0).abs()
+        out[name] = {"ms": float(np.median(ms)),
+                     "n_seg_per_sink": float(C[:, 3].double().mean()),
+                     "median_rel_diff_vs_plain": float(dev.median())}
+    return out
+
+
 def adjoint_ratio(torch, P, reps=3):
     from paper_1902_08083_amd import workloads as W
     w = W.c5()
@@ -394,6 +423,9 @@ def main():
     if not args.no_vector:
         log("three opacity bands on the same workload")
         out["bands"] = bands(torch, tree, w)
+    if not args.no_vector:
+        log("walk variants on the same workload")
+        out["variants"] = variants(torch, tree, w)
     if not args.no_vector:
         log("particle trace below the buckets on the same workload")
         out["sph"] = sph(torch, tree, w)
