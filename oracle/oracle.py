@@ -96,6 +96,13 @@ def lib():
         L.oracle_ray_log_variant.restype = ctypes.c_int64
         L.oracle_ray_log_variant.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int64, ctypes.c_int64] + [P] * 6
+        L.oracle_set_background.restype = ctypes.c_int
+        L.oracle_set_background.argtypes = [P, P, ctypes.c_double, P]
+        L.oracle_flux_background.restype = ctypes.c_int
+        L.oracle_flux_background.argtypes = [P, ctypes.c_double, ctypes.c_double, P,
+                                             ctypes.c_int64, ctypes.c_int, P, P]
+        L.oracle_background_cells.restype = ctypes.c_int
+        L.oracle_background_cells.argtypes = [P, P, P]
         L.oracle_ray_log.restype = ctypes.c_int64
         L.oracle_ray_log.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                      ctypes.c_int64] + [P] * 6
@@ -218,6 +225,36 @@ class OracleTree:
         if rc != 0:
             raise ValueError("oracle_flux_bands rejected its arguments")
         return Fb, C
+
+    # ---- background shell ----
+    def set_background(self, centre, radius, flags):
+        """Background sources (flags[n], input order) on the sphere (centre,
+        radius): merged cells of them radiate from the sphere."""
+        self._bg_c = _d(centre)
+        self._bg_f = np.ascontiguousarray(flags, dtype=np.uint8)
+        if self._bg_f.shape != (self.n,):
+            raise ValueError("flags must have one entry per particle")
+        if lib().oracle_set_background(self._h, _ptr(self._bg_c), float(radius),
+                                       _ptr(self._bg_f)) != 0:
+            raise ValueError("oracle_set_background rejected its arguments")
+
+    def flux_background(self, theta, tau_ref, sinks=None, nthreads=0):
+        s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+        ns = self.n if s is None else int(s.shape[0])
+        F = np.empty(ns, np.float64)
+        C = np.empty((ns, 5), np.int64)
+        rc = lib().oracle_flux_background(self._h, float(theta), float(tau_ref), _ptr(s), ns,
+                                          int(nthreads), _ptr(F), _ptr(C))
+        if rc != 0:
+            raise ValueError("oracle_flux_background rejected its arguments")
+        return F, C
+
+    def background_cells(self):
+        flag = np.empty(self.m, np.uint8)
+        pos = np.empty((self.m, 3), np.float64)
+        if lib().oracle_background_cells(self._h, _ptr(flag), _ptr(pos)) != 0:
+            raise ValueError("set_background first")
+        return flag.astype(bool), pos
 
     # ---- walk variants ----
     def flux_variant(self, theta, tau_ref, open_mode=0, ray_mode=0, tau_max=np.inf, sinks=None,

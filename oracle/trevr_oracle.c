@@ -25,6 +25,7 @@
  *   Sec. 2.2.3, eq. (refcrit): refine where tau_ref < (alpha_max-alpha_min) l;
  *                   directional alpha_min / alpha_max built bottom-up
  *   Sec. 2.3:       volume-weighted cell density sum(m)/sum(m/rho)
+ *   Sec. 2.2.4 (background shell): merged background sources on the sphere
  *   Sec. 2.3, 3 (walk variants): a per-bucket opening test, Gasoline's opening
  *                   radius, a top-down ray walk, early termination past tau_max
  *   Sec. 2.2.3 and 2.3 (sub-bucket refinement): below a bucket, an SPH-style
@@ -77,6 +78,12 @@ typedef struct {
   int sph;
   double *sph_h, *sph_mk, *sph_dp, *sph_hmax;
   int64_t *nb_off, *nb_idx;
+  /* background shell (oracle_set_background): per cell, whether all of its
+   * luminous particles are background sources, and then its merged source
+   * moved onto the sphere (transport precision) */
+  int bg;
+  unsigned char *bg_cell;
+  double *bg_pos; /* [m][3] */
 } otree;
 
 static double tr(const otree *t, double v) {
@@ -377,6 +384,8 @@ void oracle_free(void *h) {
   free(t->sph_hmax);
   free(t->nb_off);
   free(t->nb_idx);
+  free(t->bg_cell);
+  free(t->bg_pos);
   free(t);
 }
 
@@ -519,6 +528,7 @@ typedef struct {
   double Pm[6]; /* second moment: sum of f n_a n_b (xx, yy, zz, xy, xz, yz) */
   int bands;     /* band mode: per-band tau and flux, band-maximum spread */
   int sph;       /* sub-bucket particle trace below the buckets */
+  int bg;        /* merged background sources on the sphere */
   /* walk variants: opening test 0 eq. (openangle) at the sink point, 1 at the
    * sink's bucket box, 2 Gasoline's opening radius about x_L; ray walk 0 up
    * the tree (Sec. 2.2.2), 1 top down from the meeting cell; rays with
@@ -932,8 +942,16 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
     refine(c, &ry, C, tQ, gQ, 1.0, -1);
   }
 done:;
+  /* a merged cell of background sources radiates from its point on the
+   * sphere (Sec. 2.2.4); tau still runs to x_L, inside the cell */
+  double r2f = ry.r2;
+  if (c->bg && src < 0 && t->bg_cell[C]) {
+    double e[3];
+    for (int a = 0; a < 3; ++a) e[a] = t->bg_pos[3 * C + a] - c->xi[a];
+    r2f = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2];
+  }
   /* early termination: a ray past tau_max contributes nothing */
-  double f = ry.tau > c->tau_max ? 0.0 : (L * exp(-ry.tau)) / ((4.0 * M_PI) * ry.r2);
+  double f = ry.tau > c->tau_max ? 0.0 : (L * exp(-ry.tau)) / ((4.0 * M_PI) * r2f);
   c->F += f;
   c->G += f * ry.tau;
   if (c->bands)
@@ -1278,6 +1296,79 @@ int64_t oracle_ray_log_variant(void *h, double theta, double tau_ref, int open_m
   c.log_f = f;
   walk(&c, 0);
   return c.log_n;
+}
+
+/* Background shell (Sec. 2.2.4): flags[n] marks the background sources
+ * (input order), which lie on the sphere of the given centre and radius.  A
+ * cell whose luminous particles are all background sources has its merged
+ * source moved radially onto the sphere, y' = c + R (x_L - c) / |x_L - c|
+ * (the paper's remedy for merged centres of luminosity that fall inside the
+ * sphere); a ray from it keeps its optical depth to x_L and takes
+ * L e^-tau / (4 pi |y' - x_i|^2). */
+int oracle_set_background(void *h, const double *centre, double radius,
+                          const unsigned char *flags) {
+  otree *t = (otree *)h;
+  if (!(radius > 0) || !isfinite(radius)) return -1;
+  free(t->bg_cell);
+  free(t->bg_pos);
+  t->bg_cell = (unsigned char *)calloc((size_t)(t->m > 0 ? t->m : 1), 1);
+  t->bg_pos = (double *)calloc(3 * (size_t)(t->m > 0 ? t->m : 1), sizeof(double));
+  for (int64_t id = 0; id < t->m; ++id) {
+    const onode *p = &t->nd[id];
+    if (!(p->t_lc > 0)) continue;
+    int only = 1;
+    for (int64_t k = p->first; k < p->first + p->count; ++k) {
+      int64_t j = t->perm[k];
+      if (t->lum[j] > 0 && !flags[j]) only = 0;
+    }
+    if (!only) continue;
+    double v[3];
+    for (int a = 0; a < 3; ++a) v[a] = p->t_xl[a] - centre[a];
+    double len = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    t->bg_cell[id] = 1;
+    for (int a = 0; a < 3; ++a)
+      t->bg_pos[3 * id + a] = tr(t, len > 0 ? centre[a] + radius * (v[a] / len) : p->t_xl[a]);
+  }
+  t->bg = 1;
+  return 0;
+}
+
+/* Flux with the background shell's merged sources on the sphere. */
+int oracle_flux_background(void *h, double theta, double tau_ref, const int64_t *sinks,
+                           int64_t ns, int nthreads, double *F, int64_t *counters) {
+  const otree *t = (const otree *)h;
+  if (!(theta >= 0) || !t->bg) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t q = 0; q < ns; ++q) {
+    int64_t i = sinks ? sinks[q] : q;
+    osink c;
+    sink_init(&c, t, i, theta, tau_ref);
+    c.bg = 1;
+    walk(&c, 0);
+    F[q] = c.F;
+    if (counters) {
+      counters[5 * q + 0] = c.n_open;
+      counters[5 * q + 1] = c.n_rays;
+      counters[5 * q + 2] = c.n_psrc;
+      counters[5 * q + 3] = c.n_seg;
+      counters[5 * q + 4] = c.n_trace;
+    }
+  }
+  return 0;
+}
+
+/* The cells moved onto the sphere (flag) and their points, [m][3]. */
+int oracle_background_cells(void *h, unsigned char *flag, double *pos) {
+  const otree *t = (const otree *)h;
+  if (!t->bg) return -1;
+  for (int64_t id = 0; id < t->m; ++id) {
+    flag[id] = t->bg_cell[id];
+    for (int a = 0; a < 3; ++a) pos[3 * id + a] = t->bg_pos[3 * id + a];
+  }
+  return 0;
 }
 
 /* Every ray of one sink, in walk order.  Returns the number of rays (the
