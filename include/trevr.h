@@ -263,6 +263,31 @@ int trevr_compute_flux_variant(const trevr_tree *tree, double theta_open, double
                                const int32_t *sinks, int64_t n_sinks, void *flux,
                                int32_t *counters, hipStream_t stream);
 
+/* Background radiation from a shell of sources (Sec. 2.2.4): background
+ * sources are ordinary particles with luminosity (typically massless) placed
+ * on a sphere at the edge of the volume, e.g. on a golden-angle spiral.  A
+ * merged cell whose luminous particles are all background sources would
+ * radiate from its centre of luminosity, which lies inside the sphere and so
+ * over-estimates the flux near the shell; here it radiates from the point
+ * where the ray from the centre through x_L meets the sphere,
+ * y' = centre + radius (x_L - centre) / |x_L - centre|.  The ray's optical
+ * depth still runs to x_L (inside the cell); the flux term is
+ * L_C e^-tau / (4 pi |y' - x_i|^2).  At the shell's centre an optically thin
+ * flux is then exactly L / (4 pi R^2) at any theta_open.
+ * trevr_set_background: centre host double[3], radius > 0 (finite), flags
+ * device uint8 [n] (input order; non-zero marks a background source).  Waits
+ * on `stream`.  Errors: TREVR_E_ARG, _STATE, _HIP.  A build or a refit drops
+ * it.
+ * trevr_compute_flux_background: as trevr_compute_flux with that change.
+ * Runs the 3-wave kernel of the walk variants.  Asynchronous, allocates
+ * nothing.  Errors: as trevr_compute_flux, and TREVR_E_STATE without a
+ * background set. */
+int trevr_set_background(trevr_tree *tree, const double *centre, double radius,
+                         const uint8_t *flags, hipStream_t stream);
+int trevr_compute_flux_background(const trevr_tree *tree, double theta_open, double tau_ref,
+                                  const int32_t *sinks, int64_t n_sinks, void *flux,
+                                  int32_t *counters, hipStream_t stream);
+
 /* Refinement below the buckets: a particle trace in the manner of SPHRay
  * (Sec. 2.2.3 and the ray-tracing passage of Sec. 2.3).  Where refinement
  * reaches a bucket and the bucket's own spread still fails the criterion,

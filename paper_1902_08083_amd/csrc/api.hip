@@ -73,7 +73,7 @@ trevr_tree::~trevr_tree() {
                           &band_alpha, &band_dmax, &band_trace, &bs_A, &bs_alpha, &bs_amin,
                           &bs_amax, &bs_amin_d, &bs_amax_d, &bs_dalpha, &pkappa, &sph_pos,
                           &sph_mk, &sph_dp, &sph_hmax, &sph_cnt, &sph_off, &sph_nb,
-                          &sph_trace};
+                          &sph_trace, &bg_pos, &bg_nonbg};
   for (auto *b : all) b->release();
   if (tape_used_h) (void)hipHostFree(tape_used_h);
 }
@@ -162,6 +162,29 @@ int trevr_compute_flux_variant(const trevr_tree *tree, double theta_open, double
   if (n_sinks > 0 && !flux) return trevr::fail(TREVR_E_ARG, "flux is NULL");
   return trevr::flux_variant_impl(tree, theta_open, tau_ref, open_mode, ray_mode, tau_max, sinks,
                                   n_sinks, flux, counters, stream);
+}
+
+int trevr_set_background(trevr_tree *tree, const double *centre, double radius,
+                         const uint8_t *flags, hipStream_t stream) {
+  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
+  if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");
+  if (!centre || (tree->n > 0 && !flags)) return trevr::fail(TREVR_E_ARG, "centre or flags is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(centre[a])) return trevr::fail(TREVR_E_ARG, "centre is not finite");
+  if (!(radius > 0) || !std::isfinite(radius))
+    return trevr::fail(TREVR_E_ARG, "radius must be finite and > 0");
+  return trevr::background_impl(tree, centre, radius, flags, stream);
+}
+
+int trevr_compute_flux_background(const trevr_tree *tree, double theta_open, double tau_ref,
+                                  const int32_t *sinks, int64_t n_sinks, void *flux,
+                                  int32_t *counters, hipStream_t stream) {
+  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (!tree->bg_ok) return trevr::fail(TREVR_E_STATE, "no background shell set on this tree");
+  if (n_sinks > 0 && !flux) return trevr::fail(TREVR_E_ARG, "flux is NULL");
+  return trevr::flux_background_impl(tree, theta_open, tau_ref, sinks, n_sinks, flux, counters,
+                                     stream);
 }
 
 int trevr_set_sph(trevr_tree *tree, const void *h, hipStream_t stream) {

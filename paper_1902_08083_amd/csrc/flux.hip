@@ -75,6 +75,9 @@ struct FluxArgs {
   // contribute nothing (and stop being traced)
   int32_t variant, open_mode, ray_mode;
   double tau_max;
+  // background shell (kernels with VAR): per cell, x, y, z of its merged
+  // source on the sphere and L = 1 where that applies, else null
+  const P4<T> *__restrict__ bg_pos;
   int32_t *counters;
   int32_t *queue;  // kXcd counters
   // Tape of per-ray optical depths: one block of 64 per round, the blocks of
@@ -1313,7 +1316,18 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         }
         if (!ADJ && tblk >= 0) a.tape[(int64_t)tblk * 64 + lane] = ts.tau;
         f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
-        if (VAR > 0 && ts.tau > a.tau_max) f = 0.0;  // early termination
+        if constexpr (VAR > 0) {
+          if (a.bg_pos && !psrc) {  // a merged background cell radiates from the sphere
+            const P4<T> b = a.bg_pos[id];
+            if (b.L != (T)0) {
+              const double e0 = (double)b.x - c.xi[0], e1 = (double)b.y - c.xi[1],
+                           e2 = (double)b.z - c.xi[2];
+              const double r2f = (e0 * e0 + e1 * e1) + e2 * e2;
+              f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * r2f);
+            }
+          }
+          if (ts.tau > a.tau_max) f = 0.0;  // early termination
+        }
         if (MOM >= 1) {
           double nv[3];
           for (int q3 = 0; q3 < 3; ++q3) {
@@ -1987,6 +2001,28 @@ int flux_variant_impl(const trevr_tree *t, double theta, double tau_ref, int ope
                                       n_sinks, flux, counters, s);
   return flux_variant_typed<float>(t, theta, tau_ref, open_mode, ray_mode, tau_max, sinks,
                                    n_sinks, flux, counters, s);
+}
+
+template <typename T>
+static int flux_background_typed(const trevr_tree *t, double theta, double tau_ref,
+                                 const int32_t *sinks, int64_t n_sinks, void *flux,
+                                 int32_t *counters, hipStream_t s) {
+  if (n_sinks == 0) return TREVR_OK;
+  FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
+  a.variant = 1;  // the variants' kernel with its default modes
+  a.tau_max = INFINITY;
+  a.bg_pos = static_cast<const P4<T> *>(t->bg_pos.p);
+  a.flux = static_cast<T *>(flux);
+  a.counters = counters;
+  return launch_walk<T, false>(t, a, s);
+}
+
+int flux_background_impl(const trevr_tree *t, double theta, double tau_ref,
+                         const int32_t *sinks, int64_t n_sinks, void *flux, int32_t *counters,
+                         hipStream_t s) {
+  if (t->prec == TREVR_F64)
+    return flux_background_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
+  return flux_background_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, s);
 }
 
 int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,

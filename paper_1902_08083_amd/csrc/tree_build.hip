@@ -1067,6 +1067,87 @@ int export_sph_impl(const trevr_tree *t, int64_t *n_entries, int64_t *offsets,
   return TREVR_OK;
 }
 
+// ---- background shell (Sec. 2.2.4) -----------------------------------------
+//
+// Background sources sit on a sphere at the edge of the volume.  A merged
+// cell of them has its centre of luminosity inside the sphere, which
+// over-estimates the flux near the shell; such a cell (every luminous particle
+// in it a background source) is given the point where the ray from the centre
+// through its x_L meets the sphere, y' = c + R (x_L - c) / |x_L - c|.
+template <typename T>
+__global__ void k_bg_bucket(const BfsNode *lvl, int cnt, const P4<T> *ps, const int32_t *perm,
+                            const uint8_t *flags, const int32_t *right, int32_t *nonbg) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cnt) return;
+  const BfsNode nd = lvl[j];
+  const int p = nd.pre;
+  if (nd.child >= 0) {
+    nonbg[p] = nonbg[p + 1] | nonbg[right[p]];
+    return;
+  }
+  int any = 0;
+  for (int k = nd.first; k < nd.first + nd.count; ++k)
+    if (ps[k].L > (T)0 && !flags[perm[k]]) any = 1;
+  nonbg[p] = any;
+}
+
+template <typename T>
+__global__ void k_bg_cells(const WalkRecT<T> *W, const int32_t *nonbg, int64_t m, double c0,
+                           double c1, double c2, double radius, P4<T> *out) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  const WalkRecT<T> w = W[p];
+  P4<T> o;
+  o.x = w.xl[0];
+  o.y = w.xl[1];
+  o.z = w.xl[2];
+  o.L = (T)0;
+  if (w.L > (T)0 && !nonbg[p]) {
+    const double c[3] = {c0, c1, c2};
+    double v[3];
+    for (int a = 0; a < 3; ++a) v[a] = (double)w.xl[a] - c[a];
+    const double len = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    if (len > 0) {
+      o.x = (T)(c[0] + radius * (v[0] / len));
+      o.y = (T)(c[1] + radius * (v[1] / len));
+      o.z = (T)(c[2] + radius * (v[2] / len));
+    }
+    o.L = (T)1;
+  }
+  out[p] = o;
+}
+
+template <typename T>
+static int background_typed(trevr_tree *t, const double *centre, double radius,
+                            const uint8_t *flags, hipStream_t s) {
+  const int64_t m = t->m;
+  const size_t mm = (size_t)(m > 0 ? m : 1);
+  TREVR_HIP(t->bg_pos.ensure(sizeof(P4<T>) * mm));
+  TREVR_HIP(t->bg_nonbg.ensure(4 * mm));
+  const BfsNode *bfs = t->bfs.as<BfsNode>();
+  for (int d = (int)t->level_cnt.size() - 1; d >= 0; --d) {  // children first
+    const int c = (int)t->level_cnt[d];
+    k_bg_bucket<T><<<nblk(c), 256, 0, s>>>(bfs + t->level_off[d], c, t->psrc.as<P4<T>>(),
+                                           t->perm.as<int32_t>(), flags,
+                                           t->n_right.as<int32_t>(), t->bg_nonbg.as<int32_t>());
+  }
+  if (m > 0)
+    k_bg_cells<T><<<nblk(m), 256, 0, s>>>(t->walk.as<WalkRecT<T>>(), t->bg_nonbg.as<int32_t>(),
+                                          m, centre[0], centre[1], centre[2], radius,
+                                          t->bg_pos.as<P4<T>>());
+  TREVR_HIP(hipGetLastError());
+  TREVR_HIP(hipStreamSynchronize(s));
+  t->bg_ok = true;
+  return TREVR_OK;
+}
+
+int background_impl(trevr_tree *t, const double *centre, double radius, const uint8_t *flags,
+                    hipStream_t s) {
+  t->bg_ok = false;
+  if (t->prec == TREVR_F64) return background_typed<double>(t, centre, radius, flags, s);
+  return background_typed<float>(t, centre, radius, flags, s);
+}
+
 // Refit: new mass, rho, kappa and lum on the positions of the build.  Each
 // particle's position must equal, value for value, the one the tree was built
 // from (then every key, and the whole topology, is unchanged); the values are
@@ -1117,6 +1198,7 @@ int refit_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   t->tape_ok = false;
   t->n_bands = 0;
   t->sph_ok = false;
+  t->bg_ok = false;
   if (t->prec == TREVR_F64) return refit_typed<double>(t, p, s);
   return refit_typed<float>(t, p, s);
 }
@@ -1126,6 +1208,7 @@ int build_tree_impl(trevr_tree *t, const trevr_particles *p, hipStream_t s) {
   t->tape_ok = false;
   t->n_bands = 0;
   t->sph_ok = false;
+  t->bg_ok = false;
   if (p->prec == TREVR_F64) return build_typed<double>(t, p, s);
   return build_typed<float>(t, p, s);
 }

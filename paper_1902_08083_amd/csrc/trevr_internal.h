@@ -164,6 +164,11 @@ struct trevr_tree {
   bool sph_ok = false;
   int64_t sph_entries = 0;
   trevr::DevBuf sph_pos, sph_mk, sph_dp, sph_hmax, sph_cnt, sph_off, sph_nb, sph_trace;
+  // background shell (trevr_set_background): per cell whose luminous
+  // particles are all background sources, its merged source on the sphere
+  // (x, y, z; L = 1 for such a cell, 0 otherwise)
+  bool bg_ok = false;
+  trevr::DevBuf bg_pos, bg_nonbg;
   // tape of per-ray optical depths from the last recording flux call
   trevr::DevBuf tape, tape_next, tape_head, tape_ctr;
   int64_t tape_cap = 0;             // blocks of 64
@@ -191,6 +196,11 @@ int flux_variant_impl(const trevr_tree *t, double theta, double tau_ref, int ope
                       int ray_mode, double tau_max, const int32_t *sinks, int64_t n_sinks,
                       void *flux, int32_t *counters, hipStream_t s);
 int sph_impl(trevr_tree *t, const void *h, hipStream_t s);
+int background_impl(trevr_tree *t, const double *centre, double radius, const uint8_t *flags,
+                    hipStream_t s);
+int flux_background_impl(const trevr_tree *t, double theta, double tau_ref,
+                         const int32_t *sinks, int64_t n_sinks, void *flux, int32_t *counters,
+                         hipStream_t s);
 int export_sph_impl(const trevr_tree *t, int64_t *n_entries, int64_t *offsets,
                     int64_t *neighbours, double *spread, hipStream_t s);
 int flux_sph_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,

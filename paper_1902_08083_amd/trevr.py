@@ -68,7 +68,7 @@ EXPORTED = (
     "trevr_compute_flux_adjoint_taped", "trevr_reserve_tape", "trevr_compute_flux_vector",
     "trevr_refit_tree", "trevr_compute_flux_moments", "trevr_set_bands",
     "trevr_compute_flux_bands", "trevr_set_sph", "trevr_compute_flux_sph", "trevr_export_sph",
-    "trevr_compute_flux_variant",
+    "trevr_compute_flux_variant", "trevr_set_background", "trevr_compute_flux_background",
 )
 
 
@@ -111,6 +111,10 @@ def lib():
     L.trevr_compute_flux_variant.restype = I
     L.trevr_compute_flux_variant.argtypes = [P, D, D, ctypes.c_int32, ctypes.c_int32, D, P, I64,
                                              P, P, P]
+    L.trevr_set_background.restype = I
+    L.trevr_set_background.argtypes = [P, P, D, P, P]
+    L.trevr_compute_flux_background.restype = I
+    L.trevr_compute_flux_background.argtypes = [P, D, D, P, I64, P, P, P]
     L.trevr_set_sph.restype = I
     L.trevr_set_sph.argtypes = [P, P, P]
     L.trevr_compute_flux_sph.restype = I
@@ -334,6 +338,24 @@ class Tree:
         _check(lib().trevr_compute_flux_variant(self._h, float(theta_open), float(tau_ref),
                                                 int(open_mode), int(ray_mode), float(tau_max),
                                                 _ptr(s), ns, _ptr(F), _ptr(C), _stream()))
+        return (F, C) if counters else F
+
+    def set_background(self, centre, radius, flags):
+        """Background sources (flags (n,), non-zero = background) on the sphere
+        (centre, radius): merged cells of them radiate from the sphere."""
+        c = (ctypes.c_double * 3)(*[float(v) for v in centre])
+        f = torch.as_tensor(flags, device=self.device).to(torch.uint8).contiguous()
+        if f.shape != (self.n,):
+            raise ValueError("flags must have one entry per particle")
+        _check(lib().trevr_set_background(self._h, c, float(radius), _ptr(f), _stream()))
+
+    def flux_background(self, theta_open, tau_ref, sinks=None, counters=False, out=None):
+        """Flux with merged background sources on the shell's sphere."""
+        s, ns = self._sinks(sinks)
+        F = out if out is not None else torch.empty(ns, dtype=self.dtype, device=self.device)
+        C = torch.empty((ns, 5), dtype=torch.int32, device=self.device) if counters else None
+        _check(lib().trevr_compute_flux_background(self._h, float(theta_open), float(tau_ref),
+                                                   _ptr(s), ns, _ptr(F), _ptr(C), _stream()))
         return (F, C) if counters else F
 
     def set_sph(self, h):
