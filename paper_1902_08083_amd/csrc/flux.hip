@@ -969,7 +969,34 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   }
   if constexpr (Emit::kVar)
     if (emit.stop()) return;
-  refine<T>(a.TR, C, kSlotSrc + depthC, tQ, gQ, 1.0, -1, c, ovf, sp, 0, emit);
+  int X0 = C, slot0 = kSlotSrc + depthC, ga0 = gQ, gb0 = -1;
+  double ta0 = tQ, tb0 = 1.0;
+  if (!(1.0 > tQ) && sp > 0) {
+    // The source point lies on the meeting cell's plane, so C's interval is
+    // empty.  C's steps are taken here as refine takes them (each counted;
+    // a zero-length piece at the first cell that does not split), and the
+    // refinement starts from the top job instead, with the rest of the jobs
+    // under it (refine ends at an empty interval that it splits, which would
+    // leave them untraced).
+    for (int X = C;;) {  // a plane parallel to the ray passes the interval to one child
+      const TraceRecT<T> rX = load_tr(a.TR, X);
+      c.n_trace++;
+      const int right = rax_right(rX.right_ax);
+      if (!((right != 0) & ((double)rX.dalpha * 0.0 > c.tau_ref))) {
+        emit(X, X == C ? slot0 : -1, (double)rX.alpha, 0.0, tQ, gQ, 1.0, -1,
+             right == 0 ? (double)rX.dalpha : -1.0);
+        break;
+      }
+      const int ax = rax_axis(rX.right_ax);
+      if (!((c.pm >> ax) & 1)) break;  // a crossing plane: both parts are empty
+      X = sel3(c.xi, ax) >= (double)rX.split ? right : X + 1;
+    }
+    int mark;
+    stack_pop(c, ovf, --sp, mark, ga0, ta0);  // the job's marker: its entry
+    stack_pop(c, ovf, --sp, X0, gb0, tb0);    // its cell and exit
+    slot0 = -1;
+  }
+  refine<T>(a.TR, X0, slot0, ta0, ga0, tb0, gb0, c, ovf, sp, 0, emit);
 }
 
 __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
