@@ -288,6 +288,24 @@ int trevr_compute_flux_background(const trevr_tree *tree, double theta_open, dou
                                   const int32_t *sinks, int64_t n_sinks, void *flux,
                                   int32_t *counters, hipStream_t stream);
 
+/* Ionisation-equilibrium coupling (the Stromgren test of Sec. 3.3 run to its
+ * fixed point): one damped step of on-the-spot photoionisation equilibrium
+ * per particle.  With rate sigma F and recombination alpha_B n_H (1 - x)^2
+ * for neutral fraction x, equilibrium solves x q = (1 - x)^2 with
+ * q = sigma F / (alpha_B n_H); its root in [0, 1] is taken in the form
+ * x_eq = 2 / ((2 + q) + sqrt((2 + q)^2 - 4)).  Then x <- (1 - damping) x +
+ * damping x_eq and kappa = sigma x (the opacity per unit mass for the next
+ * flux, e.g. through trevr_refit_tree).
+ *   flux: device [n], the flux at each particle (input order); n_h: device
+ *   [n] hydrogen number density, or NULL for 1; x: device [n], read and
+ *   written; kappa: device [n], written; all of precision prec.
+ *   dx_max: device, one double: receives max_i |x_eq - x_old|.
+ * sigma >= 0, alpha_B > 0, 0 < damping <= 1.  Asynchronous, allocates
+ * nothing.  Errors: TREVR_E_ARG, _HIP. */
+int trevr_ionisation_update(int64_t n, trevr_prec prec, const void *flux, const void *n_h,
+                            double sigma, double alpha_b, double damping, void *x, void *kappa,
+                            double *dx_max, hipStream_t stream);
+
 /* Refinement below the buckets: a particle trace in the manner of SPHRay
  * (Sec. 2.2.3 and the ray-tracing passage of Sec. 2.3).  Where refinement
  * reaches a bucket and the bucket's own spread still fails the criterion,

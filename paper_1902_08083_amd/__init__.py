@@ -14,9 +14,10 @@ NODE_I_FIELDS = ("first", "count", "depth", "leaf", "parent", "right", "skip", "
 
 from .trevr import (  # noqa: E402
     COUNTER_FIELDS, BatchedPlan, Tree, TrevrError, TrevrFlux, TrevrNotBuilt, autotune, build_tree,
-    compute_flux, compute_flux_adjoint, flux, lib,
+    compute_flux, compute_flux_adjoint, flux, ionisation_equilibrium, ionisation_update, lib,
 )
 
 __all__ = ["BatchedPlan", "autotune", "Tree", "TrevrError", "TrevrFlux", "TrevrNotBuilt", "build_tree", "compute_flux",
-           "compute_flux_adjoint", "flux", "lib", "COUNTER_FIELDS", "NODE_F_FIELDS",
+           "compute_flux_adjoint", "flux", "ionisation_equilibrium", "ionisation_update", "lib",
+           "COUNTER_FIELDS", "NODE_F_FIELDS",
            "NODE_I_FIELDS"]

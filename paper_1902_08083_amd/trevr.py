@@ -69,6 +69,7 @@ EXPORTED = (
     "trevr_refit_tree", "trevr_compute_flux_moments", "trevr_set_bands",
     "trevr_compute_flux_bands", "trevr_set_sph", "trevr_compute_flux_sph", "trevr_export_sph",
     "trevr_compute_flux_variant", "trevr_set_background", "trevr_compute_flux_background",
+    "trevr_ionisation_update",
 )
 
 
@@ -111,6 +112,8 @@ def lib():
     L.trevr_compute_flux_variant.restype = I
     L.trevr_compute_flux_variant.argtypes = [P, D, D, ctypes.c_int32, ctypes.c_int32, D, P, I64,
                                              P, P, P]
+    L.trevr_ionisation_update.restype = I
+    L.trevr_ionisation_update.argtypes = [I64, ctypes.c_int, P, P, D, D, D, P, P, P, P]
     L.trevr_set_background.restype = I
     L.trevr_set_background.argtypes = [P, P, D, P, P]
     L.trevr_compute_flux_background.restype = I
@@ -592,3 +595,47 @@ class BatchedPlan:
         F = self.flux if F is None else F
         return [F[int(self.offsets[b]):int(self.offsets[b + 1])]
                 for b in range(len(self.offsets) - 1)]
+
+
+# ---- ionisation-equilibrium coupling ----------------------------------------
+
+def ionisation_update(flux, x, kappa, sigma, alpha_b, damping=0.5, n_h=None, dx_max=None):
+    """One damped on-the-spot equilibrium step per particle (trevr_ionisation_update):
+    x and kappa (= sigma x) are updated in place; returns the device scalar
+    max |x_eq - x_old|."""
+    dt = x.dtype
+    prec = 1 if dt == torch.float64 else 0
+    for a in (flux, x, kappa) + ((n_h,) if n_h is not None else ()):
+        if a.dtype != dt or not a.is_contiguous() or a.shape != x.shape:
+            raise ValueError("flux, x, kappa (and n_h) must be contiguous, same dtype and shape")
+    d = dx_max if dx_max is not None else torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(lib().trevr_ionisation_update(int(x.shape[0]), prec, _ptr(flux), _ptr(n_h),
+                                         float(sigma), float(alpha_b), float(damping), _ptr(x),
+                                         _ptr(kappa), _ptr(d), _stream()))
+    return d
+
+
+def ionisation_equilibrium(pos, rho, lum, mass, x, sigma, alpha_b, theta_open=0.75,
+                           tau_ref=-1.0, damping=0.5, tol=1e-7, max_iter=200, box_lo=(0.0,) * 3,
+                           box_hi=(1.0,) * 3, bucket_size=8):
+    """Photoionisation equilibrium with the flux as its source term: kappa =
+    sigma x, the flux at every particle, a damped update of x towards the
+    on-the-spot equilibrium for n_H = rho; repeated until max |x_eq - x| < tol.
+    The tree is built once and refit with the new opacities each step.
+    Returns (x, flux, iterations, last max |x_eq - x|)."""
+    x = x.clone().contiguous()
+    kappa = (sigma * x).contiguous()
+    tree = Tree().build(pos, rho, kappa, lum, mass, box_lo, box_hi, bucket_size)
+    F = torch.empty_like(x)
+    d = torch.empty(1, dtype=torch.float64, device=x.device)
+    dx = float("inf")
+    it = 0
+    while it < max_iter:
+        tree.flux(theta_open, tau_ref, out=F)
+        ionisation_update(F, x, kappa, sigma, alpha_b, damping, n_h=rho, dx_max=d)
+        it += 1
+        dx = float(d.item())
+        if dx < tol:
+            break
+        tree.refit(pos, rho, kappa, lum, mass)
+    return x, F, it, dx
