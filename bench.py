@@ -203,6 +203,87 @@ def variants(torch, tree, w, reps=2):
     return out
 
 
+def background_shell(torch, P, reps=3):
+    """A background shell (2^14 sources on a golden-angle spiral of radius 0.49
+    about the box centre, total L = 1) around 2^20 particles of the
+    log-normal field (tau_box 10, no local sources): HIP-event time of the
+    flux with merged background sources on the sphere, against the plain
+    flux, at every particle."""
+    from paper_1902_08083_amd import workloads as W
+    st = torch.cuda.current_stream()
+    n_gas, m = 1 << 20, 1 << 14
+    w = W._pack("bg", *W.lognormal_box(n_gas, 1, 10.0, 21), prec="f32")  # binary32, in [0, 1)
+    pos, rho, kappa, mass = w["pos"], w["rho"], w["kappa"], w["mass"]
+    lum = np.zeros(n_gas)
+    k = np.arange(m) + 0.5
+    z = 1.0 - 2.0 * k / m
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * k
+    sh = 0.5 + 0.49 * np.stack([np.sqrt(1 - z * z) * np.cos(phi),
+                                np.sqrt(1 - z * z) * np.sin(phi), z], 1)
+    P_ = np.vstack([pos, sh])
+    R_ = np.r_[rho, np.ones(m)]
+    K_ = np.r_[kappa, np.zeros(m)]
+    L_ = np.r_[lum, np.full(m, 1.0 / m)]
+    M_ = np.r_[mass, np.zeros(m)]
+    d = lambda a: torch.as_tensor(a, dtype=torch.float32, device="cuda")  # noqa: E731
+    tree = P.build_tree(d(P_), d(R_), d(K_), d(L_), d(M_))
+    flags = torch.as_tensor(np.r_[np.zeros(n_gas, np.uint8), np.ones(m, np.uint8)],
+                            device="cuda")
+    tree.set_background((0.5, 0.5, 0.5), 0.49, flags)
+
+    def t_of(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            fn()
+            b.record(st)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms))
+
+    tb = t_of(lambda: tree.flux_background(0.75, 0.1))
+    tp = t_of(lambda: tree.flux(0.75, 0.1))
+    n = n_gas + m
+    return {"workload": "lognormal2e20_shell2e14_f32", "background_ms": tb, "plain_ms": tp,
+            "sink_fluxes_per_s": n / (tb * 1e-3)}
+
+
+def stromgren_run(torch, P, n1=64):
+    """Ionisation equilibrium around one source in uniform hydrogen on a
+    jittered 64^3 grid (Stromgren radius 0.25, two grid spacings per neutral
+    mean free path), binary64: flux (tau_ref < 0), update and refit per
+    iteration until max |x_eq - x| < 1e-7."""
+    rng = np.random.default_rng(6)
+    g = (np.stack(np.meshgrid(*[np.arange(n1)] * 3, indexing="ij"), -1).reshape(-1, 3) + 0.5
+         + 0.3 * (rng.random((n1 ** 3, 3)) - 0.5)) / n1
+    pos = np.vstack([g, [[0.5, 0.5, 0.5]]])
+    n = pos.shape[0]
+    RS, ab = 0.25, 1.0
+    ndot = 4.0 * np.pi / 3.0 * RS ** 3 * ab
+    sigma = n1 / 2.0
+    lum = np.zeros(n)
+    lum[-1] = ndot
+    mass = np.r_[np.full(n - 1, 1.0 / (n - 1)), 0.0]
+    r = np.linalg.norm(pos - 0.5, axis=1)
+    x0 = np.where(r < RS, 1e-3, 1.0)
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, F, it, dx = P.ionisation_equilibrium(d(pos), d(np.ones(n)), d(lum), d(mass), d(x0),
+                                            sigma, ab, 0.75, -1.0)
+    torch.cuda.synchronize()
+    s = time.perf_counter() - t0
+    xg = x.cpu().numpy()[:-1]
+    balance = float(np.sum(ab * (1.0 - xg) ** 2) / xg.size / ndot)
+    return {"workload": "stromgren_64cubed_f64", "particles": n, "iterations": it,
+            "last_dx": dx, "seconds": s, "ms_per_iteration": s * 1e3 / it,
+            "photon_balance": balance}
+
+
 def adjoint_ratio(torch, P, reps=3):
     from paper_1902_08083_amd import workloads as W
     w = W.c5()
@@ -429,6 +510,11 @@ def main():
     if not args.no_vector:
         log("particle trace below the buckets on the same workload")
         out["sph"] = sph(torch, tree, w)
+    if not args.no_vector:
+        log("background shell around 2^20 particles")
+        out["background_shell"] = background_shell(torch, P)
+        log("ionisation equilibrium (Stromgren) at 64^3")
+        out["stromgren"] = stromgren_run(torch, P)
     if not args.no_adjoint:
         log("adjoint ratio on the 2^20 workload")
         out["adjoint"] = adjoint_ratio(torch, P)
