@@ -149,7 +149,8 @@ int trevr_tree_info(const trevr_tree *tree, trevr_tree_info_t *info);
  *   theta_open >= 0; tau_ref any (negative: refine to buckets always,
  *   +infinity: never refine).
  *   sinks: device, n_sinks particle indices, or NULL for every particle (then
- *   n_sinks must equal n and flux[i] belongs to particle i).  An index
+ *   n_sinks must equal n and flux[i] belongs to particle i); n_sinks = 0 is
+ *   an empty evaluation whatever sinks is.  An index
  *   outside [0, n) is not evaluated: its flux is NaN and its counters -1
  *   (in the adjoint it contributes nothing).
  *   flux: device, n_sinks, precision of the tree.

@@ -54,7 +54,8 @@ static int check_walk(const trevr_tree *t, double theta, double tau_ref, const i
   if (!(theta >= 0) || !std::isfinite(theta)) return fail(TREVR_E_ARG, "theta_open must be >= 0");
   if (std::isnan(tau_ref)) return fail(TREVR_E_ARG, "tau_ref is NaN");
   if (n_sinks < 0) return fail(TREVR_E_ARG, "n_sinks < 0");
-  if (!sinks && n_sinks != t->n) return fail(TREVR_E_ARG, "sinks NULL needs n_sinks == n");
+  if (!sinks && n_sinks != t->n && n_sinks != 0)
+    return fail(TREVR_E_ARG, "sinks NULL needs n_sinks == n");
   if (n_sinks >= (int64_t)1 << 31) return fail(TREVR_E_CAPACITY, "too many sinks");
   return TREVR_OK;
 }
