@@ -58,7 +58,7 @@ struct FluxArgs {
   T *flux_vec;  // [3][n_sinks]: the vector flux (kernels with MOM >= 1)
   T *flux_mom;  // [6][n_sinks]: the second moment xx, yy, zz, xy, xz, yz (MOM == 2)
   // opacity bands (kernels with NBND > 0): a.TR then carries the largest band
-  // spread; each band's cell alpha is band_alpha[b][cell]
+  // spread; a cell's alpha per band is band_alpha[cell][b] (4 per cell)
   const T *__restrict__ band_alpha;
   int32_t n_bands;
   T *flux_bands;  // [n_bands][n_sinks]
@@ -277,14 +277,23 @@ template <typename T>
 struct BandSum {
   static constexpr bool kLight = false;
   static constexpr bool kVar = false;
-  const T *ba;
-  int64_t m;
+  const T *ba;  // [cell][4]
   int nb;
   double tau[kMaxBands] = {0.0, 0.0, 0.0, 0.0};
   __device__ __forceinline__ void operator()(int node, int, double, double l, double, int,
                                              double, int, double) {
+    T v[kMaxBands];
+    if constexpr (sizeof(T) == 4) {  // the cell's bands in one 16-byte load
+      const float4 q = reinterpret_cast<const float4 *>(ba)[node];
+      v[0] = q.x;
+      v[1] = q.y;
+      v[2] = q.z;
+      v[3] = q.w;
+    } else {
+      for (int b = 0; b < kMaxBands; ++b) v[b] = ba[(int64_t)kMaxBands * node + b];
+    }
     for (int b = 0; b < kMaxBands; ++b)
-      if (b < nb) tau[b] += (double)ba[(int64_t)b * m + node] * l;
+      if (b < nb) tau[b] += (double)v[b] * l;
   }
 };
 
@@ -1325,7 +1334,6 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         } else if constexpr (NBND > 0) {  // one traversal, one tau per band
           BandSum<T> bsum;
           bsum.ba = a.band_alpha;
-          bsum.m = a.m;
           bsum.nb = a.n_bands;
           trace_pieces<T>(a, C, keyC, depthC, tk, c, bsum);
           for (int b = 0; b < kMaxBands; ++b)

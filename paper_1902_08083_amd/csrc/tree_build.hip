@@ -729,12 +729,16 @@ __global__ void k_band_internal(const BfsNode *lvl, int cnt, const int32_t *righ
   A[p] = A[p + 1] + A[right[p]];
 }
 
+// band_alpha is [m][4]: a cell's bands side by side (one 16-byte load in
+// binary32), unused bands zero.
 template <typename T>
 __global__ void k_band_pack(const double *alpha, const double *dalpha, int64_t m, int first,
-                            T *band_alpha, double *dmax) {
+                            int band, T *band_alpha, double *dmax) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= m) return;
-  band_alpha[p] = (T)alpha[p];
+  if (first)
+    for (int b = 0; b < 4; ++b) band_alpha[4 * p + b] = (T)0;
+  band_alpha[4 * p + band] = (T)alpha[p];
   const double d = (double)(T)dalpha[p];
   dmax[p] = first || d > dmax[p] ? d : dmax[p];
 }
@@ -772,7 +776,7 @@ static int bands_typed(trevr_tree *t, int nb, const T *kb, hipStream_t s) {
   TREVR_HIP(hipStreamSynchronize(s));
   if (herr & ERR_NONFINITE) return fail(TREVR_E_NONFINITE, "non-finite band opacity");
   if (herr & ERR_VALUE) return fail(TREVR_E_VALUE, "negative band opacity");
-  TREVR_HIP(t->band_alpha.ensure(sizeof(T) * mm * nb));
+  TREVR_HIP(t->band_alpha.ensure(sizeof(T) * mm * 4));
   TREVR_HIP(t->band_dmax.ensure(8 * mm));
   TREVR_HIP(t->band_trace.ensure(sizeof(TraceRecT<T>) * mm));
   DevBuf *scr[] = {&t->bs_A, &t->bs_alpha, &t->bs_amin_d, &t->bs_amax_d, &t->bs_dalpha};
@@ -805,9 +809,8 @@ static int bands_typed(trevr_tree *t, int nb, const T *kb, hipStream_t s) {
     for (int d = nlev - 1; d >= 0; --d)
       k_bounds<<<nblk(t->level_cnt[d]), 256, 0, s>>>(bfs + t->level_off[d],
                                                       (int)t->level_cnt[d], P);
-    k_band_pack<T><<<nblk(m), 256, 0, s>>>(P.alpha, P.dalpha, m, b == 0,
-                                           t->band_alpha.as<T>() + (size_t)b * (size_t)m,
-                                           t->band_dmax.as<double>());
+    k_band_pack<T><<<nblk(m), 256, 0, s>>>(P.alpha, P.dalpha, m, b == 0, b,
+                                           t->band_alpha.as<T>(), t->band_dmax.as<double>());
   }
   k_band_records<T><<<nblk(m), 256, 0, s>>>(t->trace.as<TraceRecT<T>>(),
                                             t->band_dmax.as<double>(), m,
