@@ -5,6 +5,7 @@ times (default launch shapes).
     moment and three opacity bands at every sink in one launch; the oracle
     evaluates a seeded sample of sinks (within 1e-5 of the flux in binary32
     transport, counters identical for the bands);
+  * the same workload with each walk variant, sampled sinks against the oracle;
   * the same workload with the particle trace below the buckets (smoothing
     lengths 1.2 (m / rho)^(1/3)), sampled sinks against the oracle;
   * 2^20 particles (the adjoint workload): the recording flux and the taped
@@ -109,3 +110,19 @@ def test_c3_full_size_sph_sampled():
     Fo, Co = to.flux_sph(th, tr, sinks=sample, nthreads=NTHREADS)
     assert np.array_equal(C[sample].astype(np.int64), Co)
     assert np.max(np.abs(F[sample] - Fo) / Fo) <= 1e-5
+
+
+def test_c3_full_size_walk_variants_sampled():
+    _note("c3 full size (2^21): walk variants; sampled")
+    w = W.c3()
+    th, tr = w["theta"], w["tau_ref"]
+    tg, to = _trees(w)
+    sample = np.sort(np.random.default_rng(13).choice(w["pos"].shape[0], size=128,
+                                                      replace=False))
+    for om, rm, tmax in ((1, 0, np.inf), (2, 0, np.inf), (0, 1, np.inf), (0, 0, 10.0)):
+        F, C = tg.flux_variant(th, tr, om, rm, tmax, counters=True)
+        F, C = F.double().cpu().numpy(), C.cpu().numpy()
+        Fo, Co = to.flux_variant(th, tr, om, rm, tmax, sinks=sample, nthreads=NTHREADS)
+        if np.isinf(tmax):
+            assert np.array_equal(C[sample].astype(np.int64), Co), (om, rm)
+        assert np.all(np.abs(F[sample] - Fo) <= 1e-5 * Fo), (om, rm, tmax)
