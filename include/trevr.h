@@ -24,8 +24,18 @@
  *    message is available from trevr_last_error() (per host thread).  The
  *    library never aborts and never prints.
  *  - Calls that take a stream enqueue their work on it and return without
- *    waiting, except trevr_build_tree, which waits on its stream.
+ *    waiting, except the set-up and export calls (trevr_build_tree,
+ *    trevr_refit_tree, trevr_set_bands, trevr_set_sph, trevr_set_background,
+ *    trevr_export_tree, trevr_export_sph), which wait on their stream.
  *  - Calls on one tree handle must not overlap in time.
+ *
+ * Entry points: the tree (create, build, refit, info, export); the flux and
+ * its counters; the adjoint, plain and from a recording flux (tape); the
+ * vector flux and the second moment; several opacity bands on one
+ * traversal; the particle trace below the buckets; the walk variants
+ * (per-bucket or Gasoline opening, top-down ray walk, early termination);
+ * the background shell; one step of photoionisation equilibrium; launch
+ * shapes of the walk kernels.
  */
 #ifndef TREVR_H
 #define TREVR_H
