@@ -249,7 +249,8 @@ constexpr int kSlotSrc = 64;
 // the refinement step (see refine_branchy).
 struct TauSum {
   static constexpr bool kLight = false;
-  static constexpr bool kVar = false;  // walk variants: top-down walk, early stop
+  static constexpr bool kVar = false;   // walk variants: top-down walk, early stop
+  static constexpr bool kCount = true;  // per-ray counters of pieces and steps
   double tau = 0.0;
   __device__ __forceinline__ void operator()(int, int, double alpha, double l, double, int,
                                              double, int, double) {
@@ -257,9 +258,15 @@ struct TauSum {
   }
 };
 
+// The same sum without the counters (a flux call that asks for none).
+struct TauSumNC : TauSum {
+  static constexpr bool kCount = false;
+};
+
 // The same sum in the adjoint's first pass.
 struct TauSumA : TauSum {
   static constexpr bool kLight = true;
+  static constexpr bool kCount = false;
 };
 
 // The sum of the walk variants: the tracer stops once tau passes tau_max
@@ -277,6 +284,7 @@ template <typename T>
 struct BandSum {
   static constexpr bool kLight = false;
   static constexpr bool kVar = false;
+  static constexpr bool kCount = true;
   const T *ba;  // [cell][4]
   int nb;
   double tau[kMaxBands] = {0.0, 0.0, 0.0, 0.0};
@@ -408,6 +416,7 @@ template <typename T>
 struct SphSum {
   static constexpr bool kLight = false;
   static constexpr bool kVar = false;
+  static constexpr bool kCount = true;
   const int64_t *off;
   const int32_t *nb;
   const P4<T> *pos;
@@ -528,6 +537,7 @@ __device__ __forceinline__ void sph_jobs(SphSum<T> &ss, const RayCtx &c, int lan
 struct Scatter {
   static constexpr bool kLight = true;
   static constexpr bool kVar = false;
+  static constexpr bool kCount = false;
   double g;        // weight * flux contribution of the ray
   double dtdy[3];  // d tau / d y
   double u[3];     // per axis: sum of alpha t over entry crossings minus exit crossings
@@ -611,12 +621,12 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
   do {
     const TraceRecT<T> rec = tr_open(raw);
     const double l = c.r * (ctb - cta);
-    c.n_trace++;
+    if constexpr (Emit::kCount) c.n_trace++;
     const int right = rax_right(rec.right_ax);
     const bool split_it = (right != 0) & ((double)rec.dalpha * l > c.tau_ref);
     int ncur = cur;
     if (!split_it) {
-      if (l > 0) c.n_seg++;
+      if constexpr (Emit::kCount) c.n_seg += l > 0;
       emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb,
            right == 0 ? (double)rec.dalpha : -1.0);
       go = sp > base;
@@ -678,7 +688,7 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
   for (;;) {
     const TraceRecT<T> rec = tr_open(raw);
     const double l = c.r * (ctb - cta);
-    c.n_trace++;
+    if constexpr (Emit::kCount) c.n_trace++;
     const int right = rax_right(rec.right_ax);
     const bool split_it = (right != 0) & ((double)rec.dalpha * l > c.tau_ref);
     // Every lane evaluates the split; the next state is selected below.
@@ -760,7 +770,7 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
     // writes device memory then does not delay it).
     raw = tr_fetch(TR, done ? cur : ncur);
     if (!split_it) {
-      if (l > 0) c.n_seg++;
+      if constexpr (Emit::kCount) c.n_seg += l > 0;
       emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb,
            right == 0 ? (double)rec.dalpha : -1.0);
     }
@@ -791,7 +801,7 @@ __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
                                             double ta, int ga, double tb, int gb, RayCtx &c,
                                             StackSpill &ovf, int &sp, Emit &emit) {
   const double l = c.r * (tb - ta);
-  c.n_trace++;
+  if constexpr (Emit::kCount) c.n_trace++;
   if ((double)rP.dalpha * l > c.tau_ref) {
     if (sp + 2 <= c.kr - 2) {  // room in the LDS part, two entries kept for refinement
       stack_push(c, ovf, sp++, X, gb, tb);
@@ -801,7 +811,7 @@ __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
     }
     return;
   }
-  if (l > 0) c.n_seg++;
+  if constexpr (Emit::kCount) c.n_seg += l > 0;
   emit(P, slot, (double)rP.alpha, l, ta, ga, tb, gb, -1.0);
 }
 
@@ -853,9 +863,9 @@ template <typename T, typename Emit>
 __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int depthC,
                              const SinkCtx &sk, RayCtx &c, Emit &emit) {
   if (C == sk.S) {
-    c.n_trace++;
+    if constexpr (Emit::kCount) c.n_trace++;
     const double l = c.r * (1.0 - 0.0);
-    if (l > 0) c.n_seg++;
+    if constexpr (Emit::kCount) c.n_seg += l > 0;
     emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, 1.0, -1, sk.spreadS);
     return;
   }
@@ -935,9 +945,9 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     }
   }
   {
-    c.n_trace++;
+    if constexpr (Emit::kCount) c.n_trace++;
     const double l = c.r * (tP - 0.0);
-    if (l > 0) c.n_seg++;
+    if constexpr (Emit::kCount) c.n_seg += l > 0;
     emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, tP, gP, sk.spreadS);
   }
   // source side, [tQ, 1]: C's ancestors below A are found walking down from
@@ -989,7 +999,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     // leave them untraced).
     for (int X = C;;) {  // a plane parallel to the ray passes the interval to one child
       const TraceRecT<T> rX = load_tr(a.TR, X);
-      c.n_trace++;
+      if constexpr (Emit::kCount) c.n_trace++;
       const int right = rax_right(rX.right_ax);
       if (!((right != 0) & ((double)rX.dalpha * 0.0 > c.tau_ref))) {
         emit(X, X == C ? slot0 : -1, (double)rX.alpha, 0.0, tQ, gQ, 1.0, -1,
@@ -1078,7 +1088,7 @@ constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source,
 // queue order, so a sink's sum is in its own walk order whatever the other
 // sinks of the wave are.
 template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0, int NBND = 0, int SPH = 0,
-          int VAR = 0>
+          int VAR = 0, bool CNT = true>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
@@ -1323,7 +1333,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         c.n_seg = 0;
         c.n_trace = 0;
         ray_setup(c, (double)yx, (double)yy, (double)yz);
-        std::conditional_t<ADJ, TauSumA, TauSum> ts;
+        std::conditional_t<ADJ, TauSumA, std::conditional_t<CNT, TauSum, TauSumNC>> ts;
         if constexpr (SPH > 0) {  // particle trace below the buckets
           ss.c = &c;
           ss.tau_ref = c.tau_ref;
@@ -1379,10 +1389,12 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           }
         }
         if (!ADJ) {
-          __hip_atomic_fetch_add(&s_cnt[owner], c.n_seg, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
-          __hip_atomic_fetch_add(&s_cnt[64 + owner], c.n_trace, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
+          if (CNT) {
+            __hip_atomic_fetch_add(&s_cnt[owner], c.n_seg, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __hip_atomic_fetch_add(&s_cnt[64 + owner], c.n_trace, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+          }
         } else {
           Scatter sc;
           sc.g = wg * f;
@@ -1605,7 +1617,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         if (w.L != (T)0) {
           bool acc = false;
           if (mine) {
-            n_open++;
+            if (CNT) n_open++;
             double g[3];
             for (int q3 = 0; q3 < 3; ++q3) {
               const double u = (double)w.lo[q3] - xo[q3];
@@ -1638,7 +1650,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           openm = active & ~accm;
           // queue invariant: qn < 64 here, so a visit's cell rays fit
           if (acc) {
-            n_rays++;
+            if (CNT) n_rays++;
             const int slot = (qh + qn + __popcll(accm & below)) & (kQueue - 1);
             s_qe[slot] = n;
             s_qo[slot] = (uint8_t)lane;
@@ -1653,8 +1665,10 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                                !(pj.x == me.x && pj.y == me.y && pj.z == me.z);
               const uint64_t um = __ballot(use);
               if (use) {
-                n_rays++;
-                n_psrc++;
+                if (CNT) {
+                  n_rays++;
+                  n_psrc++;
+                }
                 const int slot = (qh + qn + __popcll(um & below)) & (kQueue - 1);
                 s_qe[slot] = (int32_t)((uint32_t)kk | kQParticle);
                 s_qo[slot] = (uint8_t)lane;
@@ -1726,15 +1740,15 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
 // share a SIMD (better latency hiding) at the price of spills; the launch
 // shape picks one (waves per SIMD = workgroups per CU x waves per workgroup
 // / 4, at least 3).
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ), occ_hn(3, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ), occ_hn(3, ADJ), 0, 0, 0, 0, CNT>(a);
 }
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ), occ_hn(4, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ), occ_hn(4, ADJ), 0, 0, 0, 0, CNT>(a);
 }
 // The flux with the vector flux, at the 4-wave budget.
 template <typename T>
@@ -1766,20 +1780,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     FluxArgs<T> a) {
   walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 2>(a);
 }
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ), occ_hn(5, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ), occ_hn(5, ADJ), 0, 0, 0, 0, CNT>(a);
 }
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_walk6(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ), occ_hn(6, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ), occ_hn(6, ADJ), 0, 0, 0, 0, CNT>(a);
 }
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_walk8(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ), occ_hn(8, ADJ)>(a);
+  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ), occ_hn(8, ADJ), 0, 0, 0, 0, CNT>(a);
 }
 
 __global__ void k_zero_i32(int32_t *p, int n) {
@@ -1923,16 +1937,30 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   // waves per workgroup <= 4 x wps, so the workgroup fits the CU's LDS
   const size_t shmem = (size_t)waves * occ_lds<ADJ>(wps);
   if (shmem > kLdsPerCu) return fail(TREVR_E_ARG, "launch shape needs more LDS than a CU has");
-  if (wps == 8)
-    k_walk8<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
-  else if (wps == 6)
-    k_walk6<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
-  else if (wps == 5)
-    k_walk5<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
-  else if (wps == 4)
-    k_walk4<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
-  else
-    k_walk<T, ADJ><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  // per-sink counters only when asked for (the adjoint never keeps them)
+  if (!ADJ && a.counters) {
+    if (wps == 8)
+      k_walk8<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    else if (wps == 6)
+      k_walk6<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    else if (wps == 5)
+      k_walk5<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    else if (wps == 4)
+      k_walk4<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    else
+      k_walk<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  } else {
+    if (wps == 8)
+      k_walk8<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    else if (wps == 6)
+      k_walk6<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    else if (wps == 5)
+      k_walk5<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    else if (wps == 4)
+      k_walk4<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    else
+      k_walk<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  }
   TREVR_HIP(hipGetLastError());
   return TREVR_OK;
 }
