@@ -333,7 +333,8 @@ int trevr_ionisation_update(int64_t n, trevr_prec prec, const void *flux, const 
  * bucket's absorber list (4 B per entry, typically 100-200 entries per bucket)
  * and per-particle and per-cell data (24-40 B per particle, 12-16 B per cell),
  * owned by the tree.  Waits on `stream`.  Errors: TREVR_E_ARG, _STATE,
- * _NONFINITE, _VALUE, _HIP.  A build or a refit drops the smoothing lengths.
+ * _NONFINITE, _VALUE, _CAPACITY (the lists would not fit in the free device
+ * memory), _HIP.  A build or a refit drops the smoothing lengths.
  * trevr_compute_flux_sph: as trevr_compute_flux (arguments, counters, NaN for
  * an invalid sink index), with the particle trace below the buckets.  Runs a
  * 3-wave kernel whatever the launch shape.  Asynchronous, allocates nothing.

@@ -1027,6 +1027,14 @@ static int sph_typed(trevr_tree *t, const T *h, hipStream_t s) {
   int64_t total = 0;
   TREVR_HIP(hipMemcpyAsync(&total, off + m, 8, hipMemcpyDeviceToHost, s));
   TREVR_HIP(hipStreamSynchronize(s));
+  {  // the lists must fit in the free device memory (beyond what they hold now)
+    size_t free_b = 0, total_b = 0;
+    TREVR_HIP(hipMemGetInfo(&free_b, &total_b));
+    if ((double)total * 4.0 > 0.9 * (double)(free_b + t->sph_nb.bytes))
+      return fail(TREVR_E_CAPACITY,
+                  "absorber lists (" + std::to_string(total) +
+                      " entries) exceed the free device memory: smoothing lengths too large");
+  }
   TREVR_HIP(t->sph_nb.ensure(4 * (size_t)(total > 0 ? total : 1)));
   if (m > 0) lists(off, t->sph_nb.as<int32_t>());
   TREVR_HIP(hipGetLastError());
