@@ -251,6 +251,7 @@ struct TauSum {
   static constexpr bool kLight = false;
   static constexpr bool kVar = false;   // walk variants: top-down walk, early stop
   static constexpr bool kCount = true;  // per-ray counters of pieces and steps
+  static constexpr bool kTags = false;  // the planes that bound each piece (adjoint scatter)
   double tau = 0.0;
   __device__ __forceinline__ void operator()(int, int, double alpha, double l, double, int,
                                              double, int, double) {
@@ -285,6 +286,7 @@ struct BandSum {
   static constexpr bool kLight = false;
   static constexpr bool kVar = false;
   static constexpr bool kCount = true;
+  static constexpr bool kTags = false;
   const T *ba;  // [cell][4]
   int nb;
   double tau[kMaxBands] = {0.0, 0.0, 0.0, 0.0};
@@ -417,6 +419,7 @@ struct SphSum {
   static constexpr bool kLight = false;
   static constexpr bool kVar = false;
   static constexpr bool kCount = true;
+  static constexpr bool kTags = false;
   const int64_t *off;
   const int32_t *nb;
   const P4<T> *pos;
@@ -538,6 +541,7 @@ struct Scatter {
   static constexpr bool kLight = true;
   static constexpr bool kVar = false;
   static constexpr bool kCount = false;
+  static constexpr bool kTags = true;
   double g;        // weight * flux contribution of the ray
   double dtdy[3];  // d tau / d y
   double u[3];     // per axis: sum of alpha t over entry crossings minus exit crossings
@@ -664,7 +668,7 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
       const int g0 = cut_a ? ax : cga;
       const bool has_near = par || t1 > cta;
       const bool has_far = !par && ctb > t0;
-      if (has_near && has_far) stack_push(c, ovf, sp++, farc, cgb, ctb);
+      if (has_near && has_far) stack_push(c, ovf, sp++, farc, Emit::kTags ? cgb : -1, ctb);
       go = has_near || has_far;  // neither: an empty interval (only at the top call)
       ncur = has_near ? nearc : farc;
       cta = has_near ? cta : t0;
@@ -712,13 +716,14 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
     // not the lane pushes; reads of the two top slots are clamped in range.
     {
       const int kw = sp < c.kr ? sp : c.kr - 1;
-      const int32_t wv = (int32_t)((uint32_t)farc | ((uint32_t)(cgb + 1) << 30));
+      const int tg = Emit::kTags ? cgb : -1;
+      const int32_t wv = (int32_t)((uint32_t)farc | ((uint32_t)(tg + 1) << 30));
       if (sp < c.kr) {
         ((lds_i32 *)c.stn)[kw * kWave] = wv;
         ((lds_d *)c.stb)[kw * kWave] = ctb;
       } else if (push) {
         ovf.e[sp - c.kr].node = farc;
-        ovf.e[sp - c.kr].tag = cgb;
+        ovf.e[sp - c.kr].tag = tg;
         ovf.e[sp - c.kr].tb = ctb;
       }
     }
@@ -804,8 +809,8 @@ __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
   if constexpr (Emit::kCount) c.n_trace++;
   if ((double)rP.dalpha * l > c.tau_ref) {
     if (sp + 2 <= c.kr - 2) {  // room in the LDS part, two entries kept for refinement
-      stack_push(c, ovf, sp++, X, gb, tb);
-      stack_push(c, ovf, sp++, kMark, ga, ta);
+      stack_push(c, ovf, sp++, X, Emit::kTags ? gb : -1, tb);
+      stack_push(c, ovf, sp++, kMark, Emit::kTags ? ga : -1, ta);
     } else {
       refine<T>(TR, X, -1, ta, ga, tb, gb, c, ovf, sp, sp, emit);
     }
