@@ -244,9 +244,13 @@ constexpr int kSlotSrc = 64;
 // A policy receives each piece as (cell, slot, alpha, length, entry t and
 // plane, exit t and plane, spread) -- spread: for a bucket, its record's
 // spread field (the particle spread in the particle-trace kernel's records),
-// -1 for other cells.
-// Forward policy: tau = sum alpha l (eq. tausum).  kLight picks the form of
-// the refinement step (see refine_branchy).
+// -1 for other cells.  Its traits shape the tracer at compile time: kLight
+// picks the form of the refinement step (see refine_branchy); kVar enables
+// the walk variants' top-down walk and early stop (a stop() member); kCount
+// keeps the per-ray counters of pieces and steps; kTags carries the planes
+// that bound each piece through the stack (the entry and exit plane
+// arguments are -1 or stale without it).
+// Forward policy: tau = sum alpha l (eq. tausum).
 struct TauSum {
   static constexpr bool kLight = false;
   static constexpr bool kVar = false;   // walk variants: top-down walk, early stop
