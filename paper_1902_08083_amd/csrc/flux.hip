@@ -418,6 +418,35 @@ struct SphRay {
   }
 };
 
+// A bucket piece traced by its own lane (a ray's jobs beyond kSphJobs; rare).
+// Out of line, so that the tracer's many emit sites stay small; the ray comes
+// by value.
+template <typename T>
+__device__ __attribute__((noinline)) double sph_piece_lane(
+    const int64_t *off, const int32_t *nb, const P4<T> *pos, const double *mk, int node,
+    double ta, double tb, double x0, double x1, double x2, double d0, double d1, double d2,
+    double r, double r2, int self) {
+  SphRay g;
+  g.xi[0] = x0;
+  g.xi[1] = x1;
+  g.xi[2] = x2;
+  g.d[0] = d0;
+  g.d[1] = d1;
+  g.d[2] = d2;
+  g.r = r;
+  g.r2 = r2;
+  g.self = self;
+  g.finish();
+  const int64_t e = off[node + 1];
+  const float taf = (float)ta, tbf = (float)tb;
+  double tau = 0.0;
+  for (int64_t k = off[node]; k < e; ++k) {
+    const int j = nb[k];
+    if (g.reaches(pos, j, taf, tbf)) tau += g.exact(pos, mk, j, ta, tb);
+  }
+  return tau;
+}
+
 template <typename T>
 struct SphSum {
   static constexpr bool kLight = false;
@@ -452,21 +481,8 @@ struct SphSum {
       ++nj;
       return;
     }
-    SphRay g;
-    for (int a = 0; a < 3; ++a) {
-      g.xi[a] = c->xi[a];
-      g.d[a] = c->d[a];
-    }
-    g.r = c->r;
-    g.r2 = c->r2;
-    g.self = self;
-    g.finish();
-    const int64_t e = off[node + 1];
-    const float taf = (float)ta, tbf = (float)tb;
-    for (int64_t k = off[node]; k < e; ++k) {
-      const int j = nb[k];
-      if (g.reaches(pos, j, taf, tbf)) tau += g.exact(pos, mk, j, ta, tb);
-    }
+    tau += sph_piece_lane<T>(off, nb, pos, mk, node, ta, tb, c->xi[0], c->xi[1], c->xi[2],
+                             c->d[0], c->d[1], c->d[2], c->r, c->r2, self);
   }
 };
 
