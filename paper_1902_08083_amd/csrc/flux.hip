@@ -315,12 +315,15 @@ struct BandSum {
 // line at impact parameter b, in units of h: G(beta, s) is the integral of
 // w(sqrt(beta^2 + u^2)) over u in [0, s], s >= 0.  w is a polynomial in q on
 // q < 1 and on 1 <= q < 2, and along the line the integrals of q^0 and q^2 are
-// polynomials in u, those of q and q^3 closed forms with asinh(u / beta).
+// polynomials in u, those of q and q^3 closed forms with asinh(u / beta),
+// taken as log(s + q) - log(beta) (lnb: log(beta), shared by a line's
+// evaluations; the term is scaled by beta^2, so the difference's rounding
+// stays at the level of the other terms').
 // in_out: the inner and the outer polynomial's primitive at s (q = |(beta, s)|).
-__device__ __forceinline__ void m4_prims(double beta, double b2, double s, double &p_in,
-                                         double &p_out) {
+__device__ __forceinline__ void m4_prims(double beta, double b2, double lnb, double s,
+                                         double &p_in, double &p_out) {
   const double q = sqrt(b2 + s * s);
-  const double as = beta > 0.0 ? asinh(s / beta) : 0.0;
+  const double as = beta > 0.0 ? log(s + q) - lnb : 0.0;
   const double i1 = 0.5 * (s * q + b2 * as);
   const double i2 = b2 * s + (s * s * s) / 3.0;
   const double i3 = 0.125 * (s * q * (2.0 * s * s + 5.0 * b2)) + 0.375 * (b2 * b2) * as;
@@ -329,12 +332,12 @@ __device__ __forceinline__ void m4_prims(double beta, double b2, double s, doubl
 }
 // G at |v|, with the sign of v (G is odd in s); s1, s2: where q = 1, 2 along
 // the line (s1 = 0 when beta >= 1), k_io = inner - outer primitive at s1.
-__device__ __forceinline__ double m4_g(double beta, double b2, double v, double s1, double s2,
-                                       double k_io) {
+__device__ __forceinline__ double m4_g(double beta, double b2, double lnb, double v, double s1,
+                                       double s2, double k_io) {
   double s = fabs(v);
   s = s < s2 ? s : s2;
   double p_in, p_out;
-  m4_prims(beta, b2, s, p_in, p_out);
+  m4_prims(beta, b2, lnb, s, p_in, p_out);
   const double g = s <= s1 ? p_in : k_io + p_out;
   return v < 0.0 ? -g : g;
 }
@@ -346,14 +349,16 @@ __device__ __forceinline__ double m4_line(double b, double h, double u0, double 
   const double s2 = sqrt(4.0 - b2);
   const double v0 = u0 / h, v1 = u1 / h;
   if (v0 >= s2 || v1 <= -s2) return 0.0;  // the piece misses the support
+  const double lnb = beta > 0.0 ? log(beta) : 0.0;
   double s1 = 0.0, k_io = 0.0;
   if (b2 < 1.0) {
     s1 = sqrt(1.0 - b2);
     double p_in, p_out;
-    m4_prims(beta, b2, s1, p_in, p_out);
+    m4_prims(beta, b2, lnb, s1, p_in, p_out);
     k_io = p_in - p_out;
   }
-  const double g = m4_g(beta, b2, v1, s1, s2, k_io) - m4_g(beta, b2, v0, s1, s2, k_io);
+  const double g =
+      m4_g(beta, b2, lnb, v1, s1, s2, k_io) - m4_g(beta, b2, lnb, v0, s1, s2, k_io);
   return g / (M_PI * h * h);
 }
 
