@@ -276,8 +276,10 @@ struct TauSumA : TauSum {
 
 // The sum of the walk variants: the tracer stops once tau passes tau_max
 // (pieces add non-negative terms, so the ray's full tau would too).
+template <bool C = true>
 struct TauVar : TauSum {
   static constexpr bool kVar = true;
+  static constexpr bool kCount = C;
   double tau_max;
   __device__ __forceinline__ bool stop() const { return tau > tau_max; }
 };
@@ -285,11 +287,11 @@ struct TauVar : TauSum {
 // Band policy: one tau per opacity band; a piece's alpha is that band's cell
 // value (the record's own alpha is not used).
 constexpr int kMaxBands = 4;
-template <typename T>
+template <typename T, bool C = true>
 struct BandSum {
   static constexpr bool kLight = false;
   static constexpr bool kVar = false;
-  static constexpr bool kCount = true;
+  static constexpr bool kCount = C;
   static constexpr bool kTags = false;
   const T *ba;  // [cell][4]
   int nb;
@@ -452,11 +454,11 @@ __device__ __attribute__((noinline)) double sph_piece_lane(
   return tau;
 }
 
-template <typename T>
+template <typename T, bool C = true>
 struct SphSum {
   static constexpr bool kLight = false;
   static constexpr bool kVar = false;
-  static constexpr bool kCount = true;
+  static constexpr bool kCount = C;
   static constexpr bool kTags = false;
   const int64_t *off;
   const int32_t *nb;
@@ -500,8 +502,8 @@ struct SphSum {
 // to the job's lane.  Called by all lanes of the wave together; c is the
 // lane's ray.
 constexpr int kSphBuf = 1024;
-template <typename T>
-__device__ __forceinline__ void sph_jobs(SphSum<T> &ss, const RayCtx &c, int lane,
+template <typename T, bool C>
+__device__ __forceinline__ void sph_jobs(SphSum<T, C> &ss, const RayCtx &c, int lane,
                                          int32_t *buf) {
   const uint64_t below = (1ull << lane) - 1;
   lds_i32 *lb = (lds_i32 *)buf;
@@ -1330,7 +1332,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         if (busy) tau_rec = a.tape[(int64_t)tblk * 64 + lane];
         tcur = a.tape_next[tblk];
       }
-      SphSum<T> ss;       // (SPH) the particle trace, with its jobs for the wave
+      SphSum<T, CNT> ss;  // (SPH) the particle trace, with its jobs for the wave
       double sph_L = 0.0;
       ss.off = a.sph_off;
       ss.nb = a.sph_nb;
@@ -1372,7 +1374,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           ts.tau = ss.tau;
           sph_L = (double)L;
         } else if constexpr (NBND > 0) {  // one traversal, one tau per band
-          BandSum<T> bsum;
+          BandSum<T, CNT> bsum;
           bsum.ba = a.band_alpha;
           bsum.nb = a.n_bands;
           trace_pieces<T>(a, C, keyC, depthC, tk, c, bsum);
@@ -1380,7 +1382,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
             if (b < a.n_bands)
               fb[b] = ((double)L * exp(-bsum.tau[b])) / ((4.0 * M_PI) * c.r2);
         } else if constexpr (VAR > 0) {  // walk variants, with the early stop
-          TauVar tv;
+          TauVar<CNT> tv;
           tv.tau_max = a.tau_max;
           trace_pieces<T>(a, C, keyC, depthC, tk, c, tv);
           ts.tau = tv.tau;
@@ -1455,7 +1457,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       if constexpr (SPH > 0) {  // the round's particle-trace jobs, by the whole wave
         const bool had = ss.nj > 0;
         static_assert(SPH == 0 || KR * 64 * 8 >= kSphBuf * 4, "job buffer in the stack's LDS");
-        sph_jobs<T>(ss, c, lane, reinterpret_cast<int32_t *>(s_stb));
+        sph_jobs<T, CNT>(ss, c, lane, reinterpret_cast<int32_t *>(s_stb));
         if (had) f = (sph_L * exp(-ss.tau)) / ((4.0 * M_PI) * c.r2);
       }
       if (ADJ) {
@@ -1781,34 +1783,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ), occ_hn(4, ADJ), 0, 0, 0, 0, CNT>(a);
 }
 // The flux with the vector flux, at the 4-wave budget.
-template <typename T>
+template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4v(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(4, false), occ_kr(4, false), occ_hn(4, false), 1>(a);
+  walk_body<T, false, occ_ks(4, false), occ_kr(4, false), occ_hn(4, false), 1, 0, 0, 0, CNT>(a);
 }
 // The flux per opacity band, at the 3-wave budget.
-template <typename T>
+template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3b(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, kMaxBands>(a);
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, kMaxBands, 0, 0,
+            CNT>(a);
 }
 // The flux with the walk variants, at the 3-wave budget.
-template <typename T>
+template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3x(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, 0, 0, 1>(a);
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, 0, 0, 1, CNT>(a);
 }
 // The flux with the sub-bucket particle trace, at the 3-wave budget.
-template <typename T>
+template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3s(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, 0, 1>(a);
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, 0, 1, 0, CNT>(a);
 }
 // The flux with the vector flux and the second moment, at the 3-wave budget.
-template <typename T>
+template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3m(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 2>(a);
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 2, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
@@ -1925,7 +1928,10 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
-      k_walk3b<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      if (a.counters)
+        k_walk3b<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      else
+        k_walk3b<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -1933,7 +1939,10 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
-      k_walk3x<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      if (a.counters)
+        k_walk3x<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      else
+        k_walk3x<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -1941,7 +1950,10 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
-      k_walk3s<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      if (a.counters)
+        k_walk3s<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      else
+        k_walk3s<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -1949,7 +1961,10 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
-      k_walk3m<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      if (a.counters)
+        k_walk3m<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+      else
+        k_walk3m<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -1957,7 +1972,10 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       const int bpc = L.blocks_per_cu * waves > 16 ? 16 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
-      k_walk4v<T><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(4), s>>>(a);
+      if (a.counters)
+        k_walk4v<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(4), s>>>(a);
+      else
+        k_walk4v<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(4), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
