@@ -1264,6 +1264,8 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     int qh = 0, qn = 0;  // the queue: first entry, entries (wave-uniform)
     int live = -1;       // the walk's path is s_path[0 .. live]
     int tprev = -1;      // recording: the set's last block
+    int tpre = 0;        // recording: lane 0's block for the next round, taken ahead
+    bool tpre_ok = false;
     int tcur = -1;       // replay: the set's next block
     if (!ADJ && a.tape_mode == 1 && lane == 0) a.tape_head[set] = -1;
     if (replay) tcur = a.tape_head[set];
@@ -1307,8 +1309,15 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       int tblk = -1;     // this round's tape block
       bool rp = false;   // tau from the tape
       if (!ADJ && a.tape_mode == 1) {
-        int b = 0;
-        if (lane == 0) b = atomicAdd(a.tape_ctr, 1);
+        // This round's block was taken a round ahead, so that the atomic's
+        // return is not waited for on the spot; the numbers a wave takes still
+        // increase (the set's last one taken ahead goes unused).
+        int b = tpre;
+        if (lane == 0) {
+          if (!tpre_ok) b = atomicAdd(a.tape_ctr, 1);
+          tpre = atomicAdd(a.tape_ctr, 1);
+        }
+        tpre_ok = true;
         b = __builtin_amdgcn_readfirstlane(b);
         if (b < a.tape_cap) {  // blocks come in increasing order, so a full tape stays full
           if (lane == 0) {
