@@ -284,7 +284,7 @@ def stromgren_run(torch, P, n1=64):
             "photon_balance": balance}
 
 
-def adjoint_ratio(torch, P, reps=3):
+def adjoint_ratio(torch, P, reps=5):
     from paper_1902_08083_amd import workloads as W
     w = W.c5()
     pos, rho, kappa, lum, mass = to_dev(w, torch)
