@@ -15,7 +15,10 @@ times (default launch shapes).
     only through their products);
   * the same 2^20 workload with the loss on a seeded sample of sinks only: the
     taped adjoint's gradients at every particle against the oracle's adjoint
-    of those sinks (within 1e-5, floored at 1e-6 of the largest entry).
+    of those sinks (within 1e-5, floored at 1e-6 of the largest entry);
+  * 2^20 particles of the log-normal field inside a 2^14-source background
+    shell (the benchmark's background workload): sampled sinks against the
+    oracle, counters identical.
 """
 import os
 
@@ -156,3 +159,32 @@ def test_c3_full_size_walk_variants_sampled():
         if np.isinf(tmax):
             assert np.array_equal(C[sample].astype(np.int64), Co), (om, rm)
         assert np.all(np.abs(F[sample] - Fo) <= 1e-5 * Fo), (om, rm, tmax)
+
+
+def test_background_shell_full_size_sampled():
+    _note("2^20 particles + 2^14-source background shell: sampled")
+    n_gas, m = 1 << 20, 1 << 14
+    w = W._pack("bg", *W.lognormal_box(n_gas, 1, 10.0, 21), prec="f32")
+    k = np.arange(m) + 0.5
+    z = 1.0 - 2.0 * k / m
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * k
+    sh = 0.5 + 0.49 * np.stack([np.sqrt(1 - z * z) * np.cos(phi),
+                                np.sqrt(1 - z * z) * np.sin(phi), z], 1)
+    arrs = [np.vstack([w["pos"], sh]), np.r_[w["rho"], np.ones(m)],
+            np.r_[w["kappa"], np.zeros(m)], np.r_[np.zeros(n_gas), np.full(m, 1.0 / m)],
+            np.r_[w["mass"], np.zeros(m)]]
+    arrs = [a.astype(np.float32) for a in arrs]
+    flags = np.r_[np.zeros(n_gas, np.uint8), np.ones(m, np.uint8)]
+    tg = P.build_tree(*[torch.as_tensor(a, device="cuda") for a in arrs])
+    tg.set_background((0.5, 0.5, 0.5), 0.49, torch.as_tensor(flags, device="cuda"))
+    F, C = tg.flux_background(0.75, 0.1, counters=True)
+    F, C = F.double().cpu().numpy(), C.cpu().numpy()
+    to = OracleTree(*[a.astype(np.float64) for a in arrs], mirror32=True)
+    to.set_background((0.5, 0.5, 0.5), 0.49, flags)
+    sample = np.sort(np.random.default_rng(14).choice(n_gas, size=128, replace=False))
+    Fo, Co = to.flux_background(0.75, 0.1, sinks=sample, nthreads=NTHREADS)
+    assert np.array_equal(C[sample].astype(np.int64), Co)
+    rel = np.abs(F[sample] - Fo) / Fo
+    _note("worst rel err %.3g" % rel.max())
+    assert rel.max() <= 1e-5
+    assert np.all(np.isfinite(F)) and np.all(F[:n_gas] > 0)
