@@ -27,6 +27,10 @@ NODE_F_FIELDS = (
     "SLx0", "SLx1", "SLx2", "alpha", "alpha_min", "alpha_max", "dalpha",
     "xl0", "xl1", "xl2", "lc", "lfar",
 )
+TRANSPORT_FIELDS = (
+    "lo0", "lo1", "lo2", "hi0", "hi1", "hi2", "split", "xl0", "xl1", "xl2", "lc", "lfar",
+    "alpha", "dalpha",
+)
 NODE_I_FIELDS = ("first", "count", "depth", "leaf", "parent", "right", "skip", "axis")
 COUNTER_FIELDS = ("n_open", "n_rays", "n_psrc", "n_seg", "n_trace")
 
@@ -61,6 +65,8 @@ def lib():
         L.oracle_axis.restype = ctypes.c_int
         L.oracle_axis.argtypes = [P, ctypes.c_int]
         L.oracle_export.argtypes = [P] * 6
+        L.oracle_export_transport.restype = ctypes.c_int
+        L.oracle_export_transport.argtypes = [P] * 4
         L.oracle_flux.restype = ctypes.c_int
         L.oracle_flux.argtypes = [P, ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
                                   ctypes.c_int, P, P, P]
@@ -166,6 +172,20 @@ class OracleTree:
             out[f] = node_i[:, j].copy()
         for j, f in enumerate(NODE_F_FIELDS):
             out[f] = node_f[:, j].copy()
+        return out
+
+    def export_transport(self):
+        """The values the walk reads: per cell the box, split plane, centre of
+        luminosity, luminosity, far-vertex distance, alpha and its spread, and
+        per particle the position and luminosity -- binary64, or each rounded
+        once to binary32 in mirror mode."""
+        node_t = np.empty((self.m, len(TRANSPORT_FIELDS)), np.float64)
+        pos = np.empty((self.n, 3), np.float64)
+        lum = np.empty(self.n, np.float64)
+        lib().oracle_export_transport(self._h, _ptr(node_t), _ptr(pos), _ptr(lum))
+        out = {f: node_t[:, j].copy() for j, f in enumerate(TRANSPORT_FIELDS)}
+        out["pos"] = pos
+        out["lum"] = lum
         return out
 
     def flux(self, theta, tau_ref, sinks=None, nthreads=0, with_g=False):

@@ -501,6 +501,36 @@ int oracle_export(void *h, int64_t *perm, int64_t *leaf_of, int64_t *node_i,
   return 0;
 }
 
+/* Export of the values the walk reads (the transport copy): binary64, or, in
+ * mirror mode, each rounded once to binary32 from its binary64 value.
+ * ORACLE_NT per node: lo[3], hi[3], split, x_L[3], L_C, l_far, alpha,
+ * alpha_max - alpha_min.  pos receives the particle positions and lum the
+ * luminosities the walk reads (input order, 3 and 1 per particle). */
+#define ORACLE_NT 14
+int oracle_export_transport(void *h, double *node_t, double *pos, double *lum) {
+  const otree *t = (const otree *)h;
+  for (int64_t id = 0; id < t->m && node_t; ++id) {
+    const onode *p = &t->nd[id];
+    double *o = node_t + ORACLE_NT * id;
+    for (int a = 0; a < 3; ++a) {
+      o[0 + a] = p->t_lo[a];
+      o[3 + a] = p->t_hi[a];
+      o[7 + a] = p->t_xl[a];
+    }
+    o[6] = p->t_split;
+    o[10] = p->t_lc;
+    o[11] = p->t_lfar;
+    o[12] = p->t_alpha;
+    o[13] = p->t_dalpha;
+  }
+  for (int64_t i = 0; i < t->n; ++i) {
+    if (pos)
+      for (int a = 0; a < 3; ++a) pos[3 * i + a] = t->x[3 * i + a];
+    if (lum) lum[i] = t->lum[i];
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------ the walk ---- */
 
 typedef struct {
