@@ -190,7 +190,7 @@ struct RayCtx {
   double r, r2;
   double tau_ref;
   int n_seg, n_trace;
-  int pm;  // per axis a: bit a set if d_a == 0, bit a + 4 if d_a < 0
+  int pm;  // per axis a: bit a set if d_a == 0, bit a + 4 if d_a <= 0 (near half upper)
   // the lane's refinement stack in LDS (stride 64): kr entries, deeper ones
   // spill to private memory
   int32_t *stn;  // pending cell | (tag + 1) << 30
@@ -683,20 +683,19 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
       const double s = (double)rec.split;
       const double xax = sel3(c.xi, ax);
       const double ts = (s - xax) * sel3(c.inv, ax);
-      const bool par = (c.pm >> ax) & 1;                        // parallel to the plane
-      const bool up = par ? xax >= s : (c.pm >> (ax + 4)) & 1;  // near half is the upper child
+      const bool up = (c.pm >> (ax + 4)) & 1;  // near half is the upper child
       const int nearc = up ? right : cur + 1;
       const int farc = up ? cur + 1 : right;
-      const bool cut_b = !par && ts < ctb;  // the plane ends the near part
-      const bool cut_a = !par && ts > cta;  // the plane starts the far part
+      const bool cut_b = ts < ctb;      // the plane ends the near part
+      const bool cut_a = !(ts <= cta);  // the plane starts the far part (also for NaN)
       const double t1 = cut_b ? ts : ctb;
       const int g1 = cut_b ? ax : cgb;
       const double t0 = cut_a ? ts : cta;
       const int g0 = cut_a ? ax : cga;
-      const bool has_near = par || t1 > cta;
-      const bool has_far = !par && ctb > t0;
+      const bool has_near = t1 > cta;
+      const bool has_far = ctb > t0;
       if (has_near && has_far) stack_push(c, ovf, sp++, farc, Emit::kTags ? cgb : -1, ctb);
-      go = has_near || has_far;  // neither: an empty interval (only at the top call)
+      go = has_near || has_far;  // one of them: refinement's intervals are never empty
       ncur = has_near ? nearc : farc;
       cta = has_near ? cta : t0;
       cga = has_near ? cga : g0;
@@ -727,14 +726,13 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
     const double s = (double)rec.split;
     const double xax = sel3(c.xi, ax);
     const double ts = (s - xax) * sel3(c.inv, ax);
-    const bool par = (c.pm >> ax) & 1;                        // parallel to the plane
-    const bool up = par ? xax >= s : (c.pm >> (ax + 4)) & 1;  // near half is the upper child
-    const bool cut_b = !par && ts < ctb;           // the plane ends the near part
-    const bool cut_a = !par && ts > cta;           // the plane starts the far part
+    const bool up = (c.pm >> (ax + 4)) & 1;  // near half is the upper child
+    const bool cut_b = ts < ctb;             // the plane ends the near part
+    const bool cut_a = !(ts <= cta);         // the plane starts the far part (also for NaN)
     const double t1 = cut_b ? ts : ctb;
     const double t0 = cut_a ? ts : cta;
-    const bool has_near = par || t1 > cta;
-    const bool has_far = !par && ctb > t0;
+    const bool has_near = t1 > cta;
+    const bool has_far = ctb > t0;
     const int nearc = up ? right : cur + 1;
     const int farc = up ? cur + 1 : right;
     const bool push = split_it & has_near & has_far;
@@ -806,7 +804,7 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
       emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb,
            right == 0 ? (double)rec.dalpha : -1.0);
     }
-    if (done) return;  // no entry left; an empty interval only at the top call
+    if (done) return;  // no entry left
     cur = ncur;
     cta = ncta;
     ctb = nctb;
@@ -881,11 +879,15 @@ __device__ __forceinline__ void ray_setup(RayCtx &c, double y0, double y1, doubl
   c.d[0] = y0 - c.xi[0];
   c.d[1] = y1 - c.xi[1];
   c.d[2] = y2 - c.xi[2];
-  for (int q = 0; q < 3; ++q) c.inv[q] = c.d[q] != 0.0 ? 1.0 / c.d[q] : 0.0;
+  // 1/d_a, and -infinity where the ray is parallel to the axis's planes: the
+  // refinement step's crossing is then -inf, +inf or NaN (sink below, above
+  // or on the plane) and its comparisons send the whole interval to the
+  // child on the sink's side, the upper one on the plane
+  for (int q = 0; q < 3; ++q) c.inv[q] = c.d[q] != 0.0 ? 1.0 / c.d[q] : -INFINITY;
   c.r2 = (c.d[0] * c.d[0] + c.d[1] * c.d[1]) + c.d[2] * c.d[2];
   c.r = sqrt(c.r2);
   c.pm = 0;
-  for (int q = 0; q < 3; ++q) c.pm |= (c.d[q] == 0.0 ? 1 << q : 0) | (c.d[q] < 0.0 ? 16 << q : 0);
+  for (int q = 0; q < 3; ++q) c.pm |= (c.d[q] == 0.0 ? 1 << q : 0) | (c.d[q] <= 0.0 ? 16 << q : 0);
 }
 
 // Reverse ray trace from the sink (t = 0) to the source in cell C (t = 1),
@@ -1022,13 +1024,14 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     if (emit.stop()) return;
   int X0 = C, slot0 = kSlotSrc + depthC, ga0 = gQ, gb0 = -1;
   double ta0 = tQ, tb0 = 1.0;
-  if (!(1.0 > tQ) && sp > 0) {
+  if (!(1.0 > tQ)) {
     // The source point lies on the meeting cell's plane, so C's interval is
-    // empty.  C's steps are taken here as refine takes them (each counted;
-    // a zero-length piece at the first cell that does not split), and the
-    // refinement starts from the top job instead, with the rest of the jobs
-    // under it (refine ends at an empty interval that it splits, which would
-    // leave them untraced).
+    // empty.  C's steps are taken here (each counted; a zero-length piece at
+    // the first cell that does not split; a plane parallel to the ray passes
+    // the interval to the child on the sink's side, the upper one on the
+    // plane), and the refinement starts from the top job instead, with the
+    // rest of the jobs under it.  Refinement thus only ever sees non-empty
+    // intervals, which the parallel-plane form of its step relies on.
     for (int X = C;;) {  // a plane parallel to the ray passes the interval to one child
       const TraceRecT<T> rX = load_tr(a.TR, X);
       if constexpr (Emit::kCount) c.n_trace++;
@@ -1042,6 +1045,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
       if (!((c.pm >> ax) & 1)) break;  // a crossing plane: both parts are empty
       X = sel3(c.xi, ax) >= (double)rX.split ? right : X + 1;
     }
+    if (sp == 0) return;
     int mark;
     stack_pop(c, ovf, --sp, mark, ga0, ta0);  // the job's marker: its entry
     stack_pop(c, ovf, --sp, X0, gb0, tb0);    // its cell and exit
@@ -1456,7 +1460,8 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           sc.hmask = HN - 1;
           sc.u[0] = sc.u[1] = sc.u[2] = 0.0;
           trace_pieces<T>(a, C, keyC, depthC, tk, c, sc);
-          for (int q3 = 0; q3 < 3; ++q3) sc.dtdy[q3] += c.r * c.inv[q3] * sc.u[q3];
+          for (int q3 = 0; q3 < 3; ++q3)  // no crossings (u = 0) along an axis with d = 0
+            if (!((c.pm >> q3) & 1)) sc.dtdy[q3] += c.r * c.inv[q3] * sc.u[q3];
           sv[0] = sc.g / (double)L;  // d loss / d L of the source
           if (!psrc)                 // d loss / d x_L of the cell
             for (int q3 = 0; q3 < 3; ++q3)
