@@ -86,6 +86,14 @@ typedef struct {
   double *bg_pos; /* [m][3] */
 } otree;
 
+/* The mirror of binary32 transport: every value the walk reads is rounded
+ * once to binary32, and the ray's geometry (direction, 1/d, r^2, r, plane
+ * crossings, piece lengths) is computed in binary32, which tr() gives here by
+ * rounding each binary64 operation on binary32 operands: for +, -, *, / and
+ * sqrt that equals the correctly rounded binary32 operation, since binary64
+ * carries more than twice binary32's precision plus two bits.  The products
+ * alpha l and (alpha_max - alpha_min) l of two binary32 values, and the sums
+ * of tau and the flux, are exact or binary64 in both modes. */
 static double tr(const otree *t, double v) {
   return t->mirror32 ? (double)(float)v : v;
 }
@@ -820,7 +828,7 @@ static void refine(osink *c, oray *ry, int64_t X, double ta, int taga,
                    double tb, int tagb) {
   const otree *t = c->t;
   const onode *p = &t->nd[X];
-  double l = ry->r * (tb - ta);
+  double l = tr(t, ry->r * tr(t, tb - ta));
   c->n_trace++;
   if (p->leaf || !(spread(c, X) * l > c->tau_ref)) {
     add_piece(c, ry, X, ta, taga, tb, tagb, l);
@@ -833,7 +841,7 @@ static void refine(osink *c, oray *ry, int64_t X, double ta, int taga,
     refine(c, ry, c->xi[ax] >= s ? R : L, ta, taga, tb, tagb);
     return;
   }
-  double ts = (s - c->xi[ax]) * ry->inv[ax];
+  double ts = tr(t, tr(t, s - c->xi[ax]) * ry->inv[ax]);
   int64_t nearc = ry->d[ax] > 0 ? L : R;
   int64_t farc = ry->d[ax] > 0 ? R : L;
   double t1 = tb;
@@ -858,7 +866,7 @@ static void refine(osink *c, oray *ry, int64_t X, double ta, int taga,
  * refinement test the sibling is refined instead. */
 static void chain_piece(osink *c, oray *ry, int64_t P, int64_t X, double ta,
                         int taga, double tb, int tagb) {
-  double l = ry->r * (tb - ta);
+  double l = tr(c->t, ry->r * tr(c->t, tb - ta));
   c->n_trace++;
   if (spread(c, P) * l > c->tau_ref) {
     refine(c, ry, X, ta, taga, tb, tagb);
@@ -877,11 +885,12 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
   oray ry;
   memset(&ry, 0, sizeof ry);
   for (int a = 0; a < 3; ++a) {
-    ry.d[a] = y[a] - c->xi[a];
-    ry.inv[a] = ry.d[a] != 0.0 ? 1.0 / ry.d[a] : 0.0;
+    ry.d[a] = tr(t, y[a] - c->xi[a]);
+    ry.inv[a] = ry.d[a] != 0.0 ? tr(t, 1.0 / ry.d[a]) : 0.0;
   }
-  ry.r2 = (ry.d[0] * ry.d[0] + ry.d[1] * ry.d[1]) + ry.d[2] * ry.d[2];
-  ry.r = sqrt(ry.r2);
+  ry.r2 = tr(t, tr(t, tr(t, ry.d[0] * ry.d[0]) + tr(t, ry.d[1] * ry.d[1])) +
+                    tr(t, ry.d[2] * ry.d[2]));
+  ry.r = tr(t, sqrt(ry.r2));
   const int64_t S = c->S;
   if (C == S) {
     c->n_trace++;
@@ -903,7 +912,7 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
     double tA;
     int gA;
     if (ry.d[axA] != 0.0) {
-      tA = (sA - c->xi[axA]) * ry.inv[axA];
+      tA = tr(t, tr(t, sA - c->xi[axA]) * ry.inv[axA]);
       gA = axA;
       if (tA < 0.0) {
         tA = 0.0;
@@ -928,7 +937,7 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
       int64_t sib = b ? P + 1 : t->nd[P].right;
       double dax = ry.d[ax];
       if (dax != 0.0 && ((!b && dax > 0) || (b && dax < 0))) {
-        double tc = (t->nd[P].t_split - c->xi[ax]) * ry.inv[ax];
+        double tc = tr(t, tr(t, t->nd[P].t_split - c->xi[ax]) * ry.inv[ax]);
         int gc = ax;
         if (tc < 0.0) {
           tc = 0.0;
@@ -943,7 +952,7 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
       P = child;
     }
     c->n_trace++;
-    add_piece(c, &ry, S, 0.0, -1, tP, gP, ry.r * (tP - 0.0));
+    add_piece(c, &ry, S, 0.0, -1, tP, gP, tr(t, ry.r * tr(t, tP - 0.0)));
     /* source side: [tA, 1] lies in A's child toward C; walk down to C */
     double tQ = tA;
     int gQ = gA;
@@ -955,7 +964,7 @@ static void trace_ray(osink *c, int64_t C, const double y[3], double L,
       int64_t sib = b ? Q + 1 : t->nd[Q].right;
       double dax = ry.d[ax];
       if (dax != 0.0 && ((b && dax > 0) || (!b && dax < 0))) {
-        double tc = (t->nd[Q].t_split - c->xi[ax]) * ry.inv[ax];
+        double tc = tr(t, tr(t, t->nd[Q].t_split - c->xi[ax]) * ry.inv[ax]);
         int gc = ax;
         if (tc > 1.0) {
           tc = 1.0;

@@ -13,9 +13,12 @@
 // cell A of the sink bucket S and the source cell C, walk down from A toward
 // S and toward C, and wherever the ray lies in a chain cell's other half use
 // that chain cell's average unless (alpha_max - alpha_min) l > tau_ref, in
-// which case the other half is refined recursively (eq. refcrit).  All
-// geometry and sums are binary64 with no contraction; cell data come from the
-// transport records (binary32 or binary64).
+// which case the other half is refined recursively (eq. refcrit).  The ray's
+// geometry (direction, 1/d, r^2, r, plane crossings t, piece lengths l) is
+// computed in the transport precision T, binary32 or binary64, each operation
+// correctly rounded and none contracted; the refinement criterion's product
+// and each term alpha l are exact binary64 products of T values, and tau and
+// the flux are summed in binary64.  Cell data come from the transport records.
 //
 // The tracer hands every piece (cell, alpha, length, end points) to a policy:
 // the forward sums tau; the adjoint, which re-runs the identical tracer,
@@ -100,8 +103,9 @@ struct FluxArgs {
 
 // v[a] for a in {0, 1, 2} as two selects: the three values are passed
 // separately so that the ray's per-axis arrays stay in registers.
-__device__ __forceinline__ double pick3(int a, double v0, double v1, double v2) {
-  const double v01 = a == 0 ? v0 : v1;
+template <typename G>
+__device__ __forceinline__ G pick3(int a, G v0, G v1, G v2) {
+  const G v01 = a == 0 ? v0 : v1;
   return a == 2 ? v2 : v01;
 }
 #define sel3(v, a) pick3((a), (v)[0], (v)[1], (v)[2])
@@ -185,26 +189,33 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// The ray, in the geometry precision G (the transport precision).
+template <typename G>
 struct RayCtx {
-  double xi[3], d[3], inv[3];
-  double r, r2;
+  G xi[3], d[3], inv[3];
+  G r, r2;
   double tau_ref;
   int n_seg, n_trace;
   int pm;  // per axis a: bit a set if d_a == 0, bit a + 4 if d_a <= 0 (near half upper)
   // the lane's refinement stack in LDS (stride 64): kr entries, deeper ones
-  // spill to private memory
-  int32_t *stn;  // pending cell | (tag + 1) << 30
-  double *stb;   // its exit parameter
+  // spill to private memory.  An entry is a pending cell | (tag + 1) << 30
+  // and its exit parameter: in binary32 both in one 8-byte word (st), in
+  // binary64 in two arrays (stn, stb).
+  int32_t *stn;
+  double *stb;
+  uint64_t *st;
   int kr;
 };
 
+template <typename G>
 struct StackEntry {
   int32_t node, tag;
-  double tb;
+  G tb;
 };
 // The deeper part of the lane's stack (rarely reached), in private memory.
+template <typename G>
 struct StackSpill {
-  StackEntry e[kRefineStack];
+  StackEntry<G> e[kRefineStack];
 };
 
 // A stack entry whose cell is kMark opens a deferred refinement job: its tag
@@ -212,24 +223,44 @@ struct StackSpill {
 // cell and the exit.  Cell indices stay below kMark (the build checks).
 constexpr int kMark = 0x3fffffff;
 
-__device__ __forceinline__ void stack_push(RayCtx &c, StackSpill &ovf, int k, int node, int tag,
-                                           double t) {
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+// LDS slot k of the lane's stack: write an entry (e = cell | (tag + 1) << 30)
+// and read one back.
+__device__ __forceinline__ void st_write(const RayCtx<float> &c, int k, uint32_t e, float t) {
+  ((lds_u64 *)c.st)[k * kWave] = (uint64_t)e | ((uint64_t)__float_as_uint(t) << 32);
+}
+__device__ __forceinline__ void st_write(const RayCtx<double> &c, int k, uint32_t e, double t) {
+  ((lds_i32 *)c.stn)[k * kWave] = (int32_t)e;
+  ((lds_d *)c.stb)[k * kWave] = t;
+}
+__device__ __forceinline__ void st_read(const RayCtx<float> &c, int k, uint32_t &e, float &t) {
+  const uint64_t v = ((lds_u64 *)c.st)[k * kWave];
+  e = (uint32_t)v;
+  t = __uint_as_float((uint32_t)(v >> 32));
+}
+__device__ __forceinline__ void st_read(const RayCtx<double> &c, int k, uint32_t &e, double &t) {
+  e = (uint32_t)((lds_i32 *)c.stn)[k * kWave];
+  t = ((lds_d *)c.stb)[k * kWave];
+}
+template <typename G>
+__device__ __forceinline__ void stack_push(RayCtx<G> &c, StackSpill<G> &ovf, int k, int node,
+                                           int tag, G t) {
   if (k < c.kr) {
-    ((lds_i32 *)c.stn)[k * kWave] = (int32_t)((uint32_t)node | ((uint32_t)(tag + 1) << 30));
-    ((lds_d *)c.stb)[k * kWave] = t;
+    st_write(c, k, (uint32_t)node | ((uint32_t)(tag + 1) << 30), t);
   } else {
     ovf.e[k - c.kr].node = node;
     ovf.e[k - c.kr].tag = tag;
     ovf.e[k - c.kr].tb = t;
   }
 }
-__device__ __forceinline__ void stack_pop(const RayCtx &c, const StackSpill &ovf, int k, int &node,
-                                          int &tag, double &t) {
+template <typename G>
+__device__ __forceinline__ void stack_pop(const RayCtx<G> &c, const StackSpill<G> &ovf, int k,
+                                          int &node, int &tag, G &t) {
   if (k < c.kr) {
-    const uint32_t e = (uint32_t)((lds_i32 *)c.stn)[k * kWave];
+    uint32_t e;
+    st_read(c, k, e, t);
     node = (int)(e & 0x3fffffffu);
     tag = (int)(e >> 30) - 1;
-    t = ((lds_d *)c.stb)[k * kWave];
   } else {
     node = ovf.e[k - c.kr].node;
     tag = ovf.e[k - c.kr].tag;
@@ -464,7 +495,7 @@ struct SphSum {
   const int32_t *nb;
   const P4<T> *pos;
   const double *mk;
-  const RayCtx *c;  // the lane's ray (xi, d, r, r2)
+  const RayCtx<T> *c;  // the lane's ray (xi, d, r, r2)
   double tau_ref;
   int self;  // the receiving particle (sorted index)
   double tau = 0.0;
@@ -503,7 +534,7 @@ struct SphSum {
 // lane's ray.
 constexpr int kSphBuf = 1024;
 template <typename T, bool C>
-__device__ __forceinline__ void sph_jobs(SphSum<T, C> &ss, const RayCtx &c, int lane,
+__device__ __forceinline__ void sph_jobs(SphSum<T, C> &ss, const RayCtx<T> &c, int lane,
                                          int32_t *buf) {
   const uint64_t below = (1ull << lane) - 1;
   lds_i32 *lb = (lds_i32 *)buf;
@@ -525,11 +556,11 @@ __device__ __forceinline__ void sph_jobs(SphSum<T, C> &ss, const RayCtx &c, int 
       tb = __shfl(tb, L);
       SphRay g;  // the job lane's ray
       for (int a = 0; a < 3; ++a) {
-        g.xi[a] = __shfl(c.xi[a], L);
-        g.d[a] = __shfl(c.d[a], L);
+        g.xi[a] = (double)__shfl(c.xi[a], L);
+        g.d[a] = (double)__shfl(c.d[a], L);
       }
-      g.r = __shfl(c.r, L);
-      g.r2 = __shfl(c.r2, L);
+      g.r = (double)__shfl(c.r, L);
+      g.r2 = (double)__shfl(c.r2, L);
       g.self = __shfl(ss.self, L);
       g.finish();
       const float taf = (float)ta, tbf = (float)tb;
@@ -640,31 +671,31 @@ struct Scatter {
 // the light form is the faster one in the adjoint kernel (both passes), the
 // branching form in the forward kernel.
 template <typename T, typename Emit>
-__device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
-                               double ta, int ga, double tb, int gb, RayCtx &c, StackSpill &ovf,
-                               int sp0, int base, Emit &emit) {
+__device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, T ta,
+                               int ga, T tb, int gb, RayCtx<T> &c, StackSpill<T> &ovf, int sp0,
+                               int base, Emit &emit) {
   int sp = sp0;
   int cur = X;
-  double cta = ta, ctb = tb;
+  T cta = ta, ctb = tb;
   int cga = ga, cgb = gb;
   TrRaw<T> raw = tr_fetch(TR, cur);
   bool go = true;
   do {
     const TraceRecT<T> rec = tr_open(raw);
-    const double l = c.r * (ctb - cta);
+    const T l = c.r * (ctb - cta);
     if constexpr (Emit::kCount) c.n_trace++;
     const int right = rax_right(rec.right_ax);
-    const bool split_it = (right != 0) & ((double)rec.dalpha * l > c.tau_ref);
+    const bool split_it = (right != 0) & ((double)rec.dalpha * (double)l > c.tau_ref);
     int ncur = cur;
     if (!split_it) {
       if constexpr (Emit::kCount) c.n_seg += l > 0;
-      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb,
-           right == 0 ? (double)rec.dalpha : -1.0);
+      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, (double)l, (double)cta, cga,
+           (double)ctb, cgb, right == 0 ? (double)rec.dalpha : -1.0);
       go = sp > base;
       if constexpr (Emit::kVar) go = go && !emit.stop();
       if (go) {
         int nd, tg;
-        double tt;
+        T tt;
         stack_pop(c, ovf, --sp, nd, tg, tt);
         if (nd == kMark) {  // a deferred job: its entry, then its cell and exit
           cta = tt;
@@ -680,17 +711,17 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
       }
     } else {
       const int ax = rax_axis(rec.right_ax);
-      const double s = (double)rec.split;
-      const double xax = sel3(c.xi, ax);
-      const double ts = (s - xax) * sel3(c.inv, ax);
+      const T s = rec.split;
+      const T xax = sel3(c.xi, ax);
+      const T ts = (s - xax) * sel3(c.inv, ax);
       const bool up = (c.pm >> (ax + 4)) & 1;  // near half is the upper child
       const int nearc = up ? right : cur + 1;
       const int farc = up ? cur + 1 : right;
       const bool cut_b = ts < ctb;      // the plane ends the near part
       const bool cut_a = !(ts <= cta);  // the plane starts the far part (also for NaN)
-      const double t1 = cut_b ? ts : ctb;
+      const T t1 = cut_b ? ts : ctb;
       const int g1 = cut_b ? ax : cgb;
-      const double t0 = cut_a ? ts : cta;
+      const T t0 = cut_a ? ts : cta;
       const int g0 = cut_a ? ax : cga;
       const bool has_near = t1 > cta;
       const bool has_far = ctb > t0;
@@ -707,30 +738,30 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
   } while (go);
 }
 template <typename T, typename Emit>
-__device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, double ta,
-                             int ga, double tb, int gb, RayCtx &c, StackSpill &ovf, int sp0,
+__device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, T ta,
+                             int ga, T tb, int gb, RayCtx<T> &c, StackSpill<T> &ovf, int sp0,
                              int base, Emit &emit) {
   int sp = sp0;
   int cur = X;
-  double cta = ta, ctb = tb;
+  T cta = ta, ctb = tb;
   int cga = ga, cgb = gb;
   TrRaw<T> raw = tr_fetch(TR, cur);
   for (;;) {
     const TraceRecT<T> rec = tr_open(raw);
-    const double l = c.r * (ctb - cta);
+    const T l = c.r * (ctb - cta);
     if constexpr (Emit::kCount) c.n_trace++;
     const int right = rax_right(rec.right_ax);
-    const bool split_it = (right != 0) & ((double)rec.dalpha * l > c.tau_ref);
+    const bool split_it = (right != 0) & ((double)rec.dalpha * (double)l > c.tau_ref);
     // Every lane evaluates the split; the next state is selected below.
     const int ax = rax_axis(rec.right_ax);
-    const double s = (double)rec.split;
-    const double xax = sel3(c.xi, ax);
-    const double ts = (s - xax) * sel3(c.inv, ax);
+    const T s = rec.split;
+    const T xax = sel3(c.xi, ax);
+    const T ts = (s - xax) * sel3(c.inv, ax);
     const bool up = (c.pm >> (ax + 4)) & 1;  // near half is the upper child
     const bool cut_b = ts < ctb;             // the plane ends the near part
     const bool cut_a = !(ts <= cta);         // the plane starts the far part (also for NaN)
-    const double t1 = cut_b ? ts : ctb;
-    const double t0 = cut_a ? ts : cta;
+    const T t1 = cut_b ? ts : ctb;
+    const T t0 = cut_a ? ts : cta;
     const bool has_near = t1 > cta;
     const bool has_far = ctb > t0;
     const int nearc = up ? right : cur + 1;
@@ -740,12 +771,9 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
     // The slot above the top is free, so the LDS part is written whether or
     // not the lane pushes; reads of the two top slots are clamped in range.
     {
-      const int kw = sp < c.kr ? sp : c.kr - 1;
       const int tg = Emit::kTags ? cgb : -1;
-      const int32_t wv = (int32_t)((uint32_t)farc | ((uint32_t)(tg + 1) << 30));
       if (sp < c.kr) {
-        ((lds_i32 *)c.stn)[kw * kWave] = wv;
-        ((lds_d *)c.stb)[kw * kWave] = ctb;
+        st_write(c, sp, (uint32_t)farc | ((uint32_t)(tg + 1) << 30), ctb);
       } else if (push) {
         ovf.e[sp - c.kr].node = farc;
         ovf.e[sp - c.kr].tag = tg;
@@ -753,19 +781,18 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
       }
     }
     int nd1, tg1, nd2, tg2;
-    double tt1, tt2;
+    T tt1, tt2;
     {
       const int k1 = sp - 1, k2 = sp - 2;
       const int r1 = k1 < 0 ? 0 : k1 < c.kr ? k1 : c.kr - 1;
       const int r2 = k2 < 0 ? 0 : k2 < c.kr ? k2 : c.kr - 1;
-      const uint32_t e1 = (uint32_t)((lds_i32 *)c.stn)[r1 * kWave];
-      const uint32_t e2 = (uint32_t)((lds_i32 *)c.stn)[r2 * kWave];
+      uint32_t e1, e2;
+      st_read(c, r1, e1, tt1);
+      st_read(c, r2, e2, tt2);
       nd1 = (int)(e1 & 0x3fffffffu);
       tg1 = (int)(e1 >> 30) - 1;
-      tt1 = ((lds_d *)c.stb)[r1 * kWave];
       nd2 = (int)(e2 & 0x3fffffffu);
       tg2 = (int)(e2 >> 30) - 1;
-      tt2 = ((lds_d *)c.stb)[r2 * kWave];
       if (pop && k1 >= c.kr) {
         nd1 = ovf.e[k1 - c.kr].node;
         tg1 = ovf.e[k1 - c.kr].tag;
@@ -780,7 +807,7 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
     const bool job = pop & (nd1 == kMark);  // a deferred job: its entry, then its cell and exit
     const bool done = split_it ? !(has_near | has_far) : !pop;
     int ncur;
-    double ncta, nctb;
+    T ncta, nctb;
     int ncga, ncgb;
     if (split_it) {
       ncur = has_near ? nearc : farc;
@@ -801,8 +828,8 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
     raw = tr_fetch(TR, done ? cur : ncur);
     if (!split_it) {
       if constexpr (Emit::kCount) c.n_seg += l > 0;
-      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, l, cta, cga, ctb, cgb,
-           right == 0 ? (double)rec.dalpha : -1.0);
+      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, (double)l, (double)cta, cga,
+           (double)ctb, cgb, right == 0 ? (double)rec.dalpha : -1.0);
     }
     if (done) return;  // no entry left
     cur = ncur;
@@ -814,8 +841,8 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
 }
 template <typename T, typename Emit>
 __device__ __forceinline__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
-                                       double ta, int ga, double tb, int gb, RayCtx &c,
-                                       StackSpill &ovf, int sp0, int base, Emit &emit) {
+                                       T ta, int ga, T tb, int gb, RayCtx<T> &c,
+                                       StackSpill<T> &ovf, int sp0, int base, Emit &emit) {
   if constexpr (Emit::kLight)
     refine_light<T>(TR, X, top_slot, ta, ga, tb, gb, c, ovf, sp0, base, emit);
   else
@@ -827,12 +854,12 @@ __device__ __forceinline__ void refine(const TraceRecT<T> *__restrict__ TR, int 
 // that all of a ray's refinement runs in one loop after its chains.
 template <typename T, typename Emit>
 __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
-                                            const TraceRecT<T> &rP, int P, int slot, int X,
-                                            double ta, int ga, double tb, int gb, RayCtx &c,
-                                            StackSpill &ovf, int &sp, Emit &emit) {
-  const double l = c.r * (tb - ta);
+                                            const TraceRecT<T> &rP, int P, int slot, int X, T ta,
+                                            int ga, T tb, int gb, RayCtx<T> &c,
+                                            StackSpill<T> &ovf, int &sp, Emit &emit) {
+  const T l = c.r * (tb - ta);
   if constexpr (Emit::kCount) c.n_trace++;
-  if ((double)rP.dalpha * l > c.tau_ref) {
+  if ((double)rP.dalpha * (double)l > c.tau_ref) {
     if (sp + 2 <= c.kr - 2) {  // room in the LDS part, two entries kept for refinement
       stack_push(c, ovf, sp++, X, Emit::kTags ? gb : -1, tb);
       stack_push(c, ovf, sp++, kMark, Emit::kTags ? ga : -1, ta);
@@ -842,7 +869,7 @@ __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
     return;
   }
   if constexpr (Emit::kCount) c.n_seg += l > 0;
-  emit(P, slot, (double)rP.alpha, l, ta, ga, tb, gb, -1.0);
+  emit(P, slot, (double)rP.alpha, (double)l, (double)ta, ga, (double)tb, gb, -1.0);
 }
 
 // The sink's bucket and where its ancestors are kept: depths <= dpre are
@@ -875,7 +902,8 @@ __device__ __forceinline__ int sink_anc(const TraceRecT<T> *__restrict__ TR, con
   return node;
 }
 
-__device__ __forceinline__ void ray_setup(RayCtx &c, double y0, double y1, double y2) {
+template <typename G>
+__device__ __forceinline__ void ray_setup(RayCtx<G> &c, G y0, G y1, G y2) {
   c.d[0] = y0 - c.xi[0];
   c.d[1] = y1 - c.xi[1];
   c.d[2] = y2 - c.xi[2];
@@ -883,11 +911,12 @@ __device__ __forceinline__ void ray_setup(RayCtx &c, double y0, double y1, doubl
   // refinement step's crossing is then -inf, +inf or NaN (sink below, above
   // or on the plane) and its comparisons send the whole interval to the
   // child on the sink's side, the upper one on the plane
-  for (int q = 0; q < 3; ++q) c.inv[q] = c.d[q] != 0.0 ? 1.0 / c.d[q] : -INFINITY;
+  for (int q = 0; q < 3; ++q) c.inv[q] = c.d[q] != G(0) ? G(1) / c.d[q] : -G(INFINITY);
   c.r2 = (c.d[0] * c.d[0] + c.d[1] * c.d[1]) + c.d[2] * c.d[2];
   c.r = sqrt(c.r2);
   c.pm = 0;
-  for (int q = 0; q < 3; ++q) c.pm |= (c.d[q] == 0.0 ? 1 << q : 0) | (c.d[q] <= 0.0 ? 16 << q : 0);
+  for (int q = 0; q < 3; ++q)
+    c.pm |= (c.d[q] == G(0) ? 1 << q : 0) | (c.d[q] <= G(0) ? 16 << q : 0);
 }
 
 // Reverse ray trace from the sink (t = 0) to the source in cell C (t = 1),
@@ -895,43 +924,43 @@ __device__ __forceinline__ void ray_setup(RayCtx &c, double y0, double y1, doubl
 // meeting cell down), the sink's bucket, source chain, the source cell.
 template <typename T, typename Emit>
 __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int depthC,
-                             const SinkCtx &sk, RayCtx &c, Emit &emit) {
+                             const SinkCtx &sk, RayCtx<T> &c, Emit &emit) {
   if (C == sk.S) {
     if constexpr (Emit::kCount) c.n_trace++;
-    const double l = c.r * (1.0 - 0.0);
+    const T l = c.r * (T(1) - T(0));
     if constexpr (Emit::kCount) c.n_seg += l > 0;
-    emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, 1.0, -1, sk.spreadS);
+    emit(sk.S, sk.depthS, sk.alphaS, (double)l, 0.0, -1, 1.0, -1, sk.spreadS);
     return;
   }
-  StackSpill ovf;
+  StackSpill<T> ovf;
   int sp = 0;  // deferred refinement jobs on the lane's stack
   const int ad = __clzll((long long)(sk.keyS ^ keyC)) - 1;  // depth of the meeting cell
   const int A = sink_anc<T>(a.TR, sk, ad);
   if constexpr (Emit::kVar) {
     if (a.ray_mode == 1) {  // top down: the meeting cell holds the whole ray
-      refine<T>(a.TR, A, -1, 0.0, -1, 1.0, -1, c, ovf, 0, 0, emit);
+      refine<T>(a.TR, A, -1, T(0), -1, T(1), -1, c, ovf, 0, 0, emit);
       return;
     }
   }
   const TraceRecT<T> rA = load_tr(a.TR, A);
   const int axA = rax_axis(rA.right_ax);
   const int sr = (int)((sk.keyS >> (62 - ad)) & 1);
-  const double dA = sel3(c.d, axA);
-  double tA;
+  const T dA = sel3(c.d, axA);
+  T tA;
   int gA = -1;
-  if (dA != 0.0) {
-    tA = ((double)rA.split - sel3(c.xi, axA)) * sel3(c.inv, axA);
+  if (dA != T(0)) {
+    tA = (rA.split - sel3(c.xi, axA)) * sel3(c.inv, axA);
     gA = axA;
-    if (tA < 0.0) {
-      tA = 0.0;
+    if (tA < T(0)) {
+      tA = T(0);
       gA = -1;
     }
-    if (tA > 1.0) {
-      tA = 1.0;
+    if (tA > T(1)) {
+      tA = T(1);
       gA = -1;
     }
   } else {
-    tA = sr ? 1.0 : 0.0;  // ray in the plane: it belongs to the upper side
+    tA = sr ? T(1) : T(0);  // ray in the plane: it belongs to the upper side
   }
   // Chain levels where the ray crosses into (sink side) or arrives from
   // (source side) the other half.  The split axis depends on the depth only,
@@ -940,10 +969,10 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   uint64_t mS = 0, mC = 0;
   for (int q = 0; q < 3; ++q) {
     const uint64_t axm = sk.axm[q];
-    if (c.d[q] > 0.0) {
+    if (c.d[q] > T(0)) {
       mS |= axm & ~sk.keyS;
       mC |= axm & keyC;
-    } else if (c.d[q] < 0.0) {
+    } else if (c.d[q] < T(0)) {
       mS |= axm & sk.keyS;
       mC |= axm & ~keyC;
     }
@@ -953,7 +982,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   mS &= below_A & ~((1ull << (63 - sk.depthS)) - 1);
   mC &= below_A & ~((1ull << (63 - depthC)) - 1);
   // sink side, [0, tP], shallowest level first
-  double tP = tA;
+  T tP = tA;
   int gP = gA;
   while (mS) {
     if constexpr (Emit::kVar)
@@ -965,10 +994,10 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     const TraceRecT<T> rP = load_tr(a.TR, P);
     const int b = (int)((sk.keyS >> (62 - dd)) & 1);
     const int ax = rax_axis(rP.right_ax);
-    double tc = ((double)rP.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
+    T tc = (rP.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
     int gc = ax;
-    if (tc < 0.0) {
-      tc = 0.0;
+    if (tc < T(0)) {
+      tc = T(0);
       gc = -1;
     }
     if (tc < tP) {
@@ -980,15 +1009,15 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   }
   {
     if constexpr (Emit::kCount) c.n_trace++;
-    const double l = c.r * (tP - 0.0);
+    const T l = c.r * (tP - T(0));
     if constexpr (Emit::kCount) c.n_seg += l > 0;
-    emit(sk.S, sk.depthS, sk.alphaS, l, 0.0, -1, tP, gP, sk.spreadS);
+    emit(sk.S, sk.depthS, sk.alphaS, (double)l, 0.0, -1, (double)tP, gP, sk.spreadS);
   }
   // source side, [tQ, 1]: C's ancestors below A are found walking down from
   // A along C's path bits.  A lower child is the next cell in depth-first
   // order, so only the levels where the path turns to the upper child, or
   // where the ray crosses, need their record.
-  double tQ = tA;
+  T tQ = tA;
   int gQ = gA;
   uint64_t stops = (keyC & below_A & ~((1ull << (63 - depthC)) - 1)) | mC;
   int Q = ((keyC >> (62 - ad)) & 1) ? rax_right(rA.right_ax) : A + 1;  // at depth ad + 1
@@ -1004,10 +1033,10 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     const int b = (int)((keyC >> (62 - dd)) & 1);
     if ((mC >> pos) & 1) {
       const int ax = rax_axis(rQ.right_ax);
-      double tc = ((double)rQ.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
+      T tc = (rQ.split - sel3(c.xi, ax)) * sel3(c.inv, ax);
       int gc = ax;
-      if (tc > 1.0) {
-        tc = 1.0;
+      if (tc > T(1)) {
+        tc = T(1);
         gc = -1;
       }
       if (tc > tQ) {
@@ -1023,8 +1052,8 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   if constexpr (Emit::kVar)
     if (emit.stop()) return;
   int X0 = C, slot0 = kSlotSrc + depthC, ga0 = gQ, gb0 = -1;
-  double ta0 = tQ, tb0 = 1.0;
-  if (!(1.0 > tQ)) {
+  T ta0 = tQ, tb0 = T(1);
+  if (!(T(1) > tQ)) {
     // The source point lies on the meeting cell's plane, so C's interval is
     // empty.  C's steps are taken here (each counted; a zero-length piece at
     // the first cell that does not split; a plane parallel to the ray passes
@@ -1037,13 +1066,13 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
       if constexpr (Emit::kCount) c.n_trace++;
       const int right = rax_right(rX.right_ax);
       if (!((right != 0) & ((double)rX.dalpha * 0.0 > c.tau_ref))) {
-        emit(X, X == C ? slot0 : -1, (double)rX.alpha, 0.0, tQ, gQ, 1.0, -1,
+        emit(X, X == C ? slot0 : -1, (double)rX.alpha, 0.0, (double)tQ, gQ, 1.0, -1,
              right == 0 ? (double)rX.dalpha : -1.0);
         break;
       }
       const int ax = rax_axis(rX.right_ax);
       if (!((c.pm >> ax) & 1)) break;  // a crossing plane: both parts are empty
-      X = sel3(c.xi, ax) >= (double)rX.split ? right : X + 1;
+      X = sel3(c.xi, ax) >= rX.split ? right : X + 1;
     }
     if (sp == 0) return;
     int mark;
@@ -1160,11 +1189,14 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       s_hv[j] = 0.0;
     }
   }
-  RayCtx c;
+  RayCtx<T> c;
   c.tau_ref = a.tau_ref;
+  // the stack's LDS (KR x 64 x 12 bytes): binary32 entries are 8 bytes, so
+  // half as many again fit
   c.stn = s_stn + lane;
   c.stb = s_stb + lane;
-  c.kr = KR;
+  c.st = reinterpret_cast<uint64_t *>(s_stb) + lane;
+  c.kr = sizeof(T) == 4 ? KR * 3 / 2 : KR;
   // a replay needs every block of the recording
   const bool replay = ADJ && a.tape_mode == 2 && *a.tape_ctr <= a.tape_cap;
   int chunk = -1, sub = a.group;
@@ -1372,12 +1404,12 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         }
         const uint64_t keyC = a.key[C];
         const int depthC = a.ndepth[C];
-        c.xi[0] = (double)ox;
-        c.xi[1] = (double)oy;
-        c.xi[2] = (double)oz;
+        c.xi[0] = ox;
+        c.xi[1] = oy;
+        c.xi[2] = oz;
         c.n_seg = 0;
         c.n_trace = 0;
-        ray_setup(c, (double)yx, (double)yy, (double)yz);
+        ray_setup(c, yx, yy, yz);
         std::conditional_t<ADJ, TauSumA, std::conditional_t<CNT, TauSum, TauSumNC>> ts;
         if constexpr (SPH > 0) {  // particle trace below the buckets
           ss.c = &c;
@@ -1393,7 +1425,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           trace_pieces<T>(a, C, keyC, depthC, tk, c, bsum);
           for (int b = 0; b < kMaxBands; ++b)
             if (b < a.n_bands)
-              fb[b] = ((double)L * exp(-bsum.tau[b])) / ((4.0 * M_PI) * c.r2);
+              fb[b] = ((double)L * exp(-bsum.tau[b])) / ((4.0 * M_PI) * (double)c.r2);
         } else if constexpr (VAR > 0) {  // walk variants, with the early stop
           TauVar<CNT> tv;
           tv.tau_max = a.tau_max;
@@ -1405,13 +1437,14 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           trace_pieces<T>(a, C, keyC, depthC, tk, c, ts);
         }
         if (!ADJ && tblk >= 0) a.tape[(int64_t)tblk * 64 + lane] = ts.tau;
-        f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * c.r2);
+        f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * (double)c.r2);
         if constexpr (VAR > 0) {
           if (a.bg_pos && !psrc) {  // a merged background cell radiates from the sphere
             const P4<T> b = a.bg_pos[id];
             if (b.L != (T)0) {
-              const double e0 = (double)b.x - c.xi[0], e1 = (double)b.y - c.xi[1],
-                           e2 = (double)b.z - c.xi[2];
+              const double e0 = (double)b.x - (double)c.xi[0],
+                           e1 = (double)b.y - (double)c.xi[1],
+                           e2 = (double)b.z - (double)c.xi[2];
               const double r2f = (e0 * e0 + e1 * e1) + e2 * e2;
               f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * r2f);
             }
@@ -1421,7 +1454,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         if (MOM >= 1) {
           double nv[3];
           for (int q3 = 0; q3 < 3; ++q3) {
-            nv[q3] = -c.d[q3] / c.r;
+            nv[q3] = -(double)c.d[q3] / (double)c.r;
             fv[q3] = f * nv[q3];
           }
           if (MOM == 2) {
@@ -1444,11 +1477,11 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           Scatter sc;
           sc.g = wg * f;
           for (int q3 = 0; q3 < 3; ++q3)
-            sc.dtdy[q3] = psrc ? 0.0 : (ts.tau / c.r) * (c.d[q3] / c.r);
-          sc.r = c.r;
-          sc.inv[0] = c.inv[0];
-          sc.inv[1] = c.inv[1];
-          sc.inv[2] = c.inv[2];
+            sc.dtdy[q3] = psrc ? 0.0 : (ts.tau / (double)c.r) * ((double)c.d[q3] / (double)c.r);
+          sc.r = (double)c.r;
+          sc.inv[0] = (double)c.inv[0];
+          sc.inv[1] = (double)c.inv[1];
+          sc.inv[2] = (double)c.inv[2];
           sc.abar = a.abar;
           sc.acc_s = acc_s;
           sc.acc_p = acc_p;
@@ -1461,18 +1494,18 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           sc.u[0] = sc.u[1] = sc.u[2] = 0.0;
           trace_pieces<T>(a, C, keyC, depthC, tk, c, sc);
           for (int q3 = 0; q3 < 3; ++q3)  // no crossings (u = 0) along an axis with d = 0
-            if (!((c.pm >> q3) & 1)) sc.dtdy[q3] += c.r * c.inv[q3] * sc.u[q3];
+            if (!((c.pm >> q3) & 1)) sc.dtdy[q3] += (double)c.r * (double)c.inv[q3] * sc.u[q3];
           sv[0] = sc.g / (double)L;  // d loss / d L of the source
           if (!psrc)                 // d loss / d x_L of the cell
             for (int q3 = 0; q3 < 3; ++q3)
-              sv[1 + q3] = sc.g * (-2.0 * c.d[q3] / c.r2 - sc.dtdy[q3]);
+              sv[1 + q3] = sc.g * (-2.0 * (double)c.d[q3] / (double)c.r2 - sc.dtdy[q3]);
         }
       }
       if constexpr (SPH > 0) {  // the round's particle-trace jobs, by the whole wave
         const bool had = ss.nj > 0;
         static_assert(SPH == 0 || KR * 64 * 8 >= kSphBuf * 4, "job buffer in the stack's LDS");
         sph_jobs<T, CNT>(ss, c, lane, reinterpret_cast<int32_t *>(s_stb));
-        if (had) f = (sph_L * exp(-ss.tau)) / ((4.0 * M_PI) * c.r2);
+        if (had) f = (sph_L * exp(-ss.tau)) / ((4.0 * M_PI) * (double)c.r2);
       }
       if (ADJ) {
         // Rays of one source are adjacent in the queue (a visited cell's

@@ -1,26 +1,35 @@
 """Pins of the oracle's binary32 mirror mode (CPU only).
 
 In binary32 transport the library stores the values its walk reads rounded
-once (round to nearest even) from the binary64 build values, and does every
-operation in binary64.  The oracle's mirror mode must read exactly those
-values:
+once (round to nearest even) from the binary64 build values, computes each
+ray's geometry -- direction, 1/d, r^2, r, plane crossings
+t = (s - x) (1/d), piece lengths l = r (t_b - t_a) -- in binary32, and forms
+the refinement criterion's product and every term alpha l as exact binary64
+products, summed in binary64.  The oracle's mirror mode must do exactly that:
 
   * every transport field equals binary32 of its binary64 value -- the cell
     box, split plane, centre of luminosity, luminosity, far-vertex distance,
     alpha, and the spread alpha_max - alpha_min rounded from its binary64
     value (not the difference of the rounded bounds); positions and
     luminosities are the binary32 inputs;
-  * optically thin, theta_open = 0: the all-pairs sum of L / (4 pi r^2) over
-    the binary32 positions and luminosities (eq. simpint);
-  * uniform medium with kappa rho exact in binary32: tau = kappa rho r per ray;
-  * theta_open = 0 with refinement always on: tau is the exact integral of the
-    bucket-wise constant field, each bucket at binary32 of its alpha (brute
-    force over buckets);
-  * tau_ref = infinity: the walk-up field with binary32 alphas (brute force);
+  * optically thin, theta_open = 0: the all-pairs sum of L / (4 pi r^2) with
+    r^2 the binary32 sum of binary32 squares of binary32 differences
+    (eq. simpint), to 1e-13;
+  * theta_open = 0 with refinement always on: the pieces are the buckets the
+    segment crosses, each from the largest binary32 crossing of its entry
+    faces to the smallest of its exit faces (clamped to [0, 1]), l the
+    binary32 r (t_b - t_a), alpha the bucket's binary32 alpha (brute force over
+    buckets, eq. tauint), to 1e-12;
+  * uniform medium with kappa rho exact in binary32: the binary32 pieces tile
+    the ray, so tau = kappa rho r to within the rounding of r and of each
+    piece (6 units of 2^-24 plus a margin);
+  * tau_ref = infinity: the walk-up field with binary32 alphas (brute force),
+    to within the shift of each piece boundary by binary32 rounding;
   * against the binary64 oracle on the same binary32-valued inputs at
-    theta_open = 0 and tau_ref < 0 (identical decisions), the flux differs by
-    no more than the rounding of alpha allows: |tau32 - tau64| <= 2^-24 tau,
-    so |F32 / F64 - 1| <= exp(2^-24 tau_max) - 1;
+    theta_open = 0 and tau_ref < 0 (the same refinement), each ray's tau
+    differs by no more than binary32 rounding allows: 2^-24 tau from alpha,
+    and from the geometry 7 u tau plus 5 u r times the total variation of
+    alpha along the ray (u = 2^-24);
   * every merged cell passes eq. openangle, and each of its ancestors fails
     it, on the binary32 values; every unrefined piece of a cell that is not a
     bucket passes eq. refcrit with the binary32 spread.
@@ -36,6 +45,51 @@ import _brute as B
 from oracle.oracle import OracleTree, TRANSPORT_FIELDS
 
 F32 = lambda a: np.asarray(a, np.float64).astype(np.float32).astype(np.float64)  # noqa: E731
+U = 2.0 ** -24
+
+
+def _r2_f32(x, y):
+    """r^2 of the segment x -> y as binary32 does it: binary32 differences,
+    squares and sums, ((d0 d0 + d1 d1) + d2 d2)."""
+    d = np.asarray(y, np.float32) - np.asarray(x, np.float32)
+    dd = d * d
+    return (dd[..., 0] + dd[..., 1]) + dd[..., 2], d
+
+
+def _all_pairs_f32(pos, lum, sinks=None):
+    """sum over other sources of L / (4 pi r^2), r^2 in binary32."""
+    p32 = np.asarray(pos, np.float32)
+    l32 = F32(lum)
+    src = np.nonzero(l32 > 0)[0]
+    sinks = np.arange(p32.shape[0]) if sinks is None else np.asarray(sinks)
+    out = np.zeros(sinks.size)
+    for q, i in enumerate(sinks):
+        r2, _ = _r2_f32(p32[i], p32[src])
+        ok = r2 > 0
+        out[q] = np.sum(l32[src][ok] / (4.0 * math.pi * r2[ok].astype(np.float64)))
+    return out
+
+
+def _leaf_pieces_f32(x, y, leaf_lo, leaf_hi):
+    """Each bucket's piece of the segment x -> y in binary32: t = (face - x)
+    (1/d) per face, entry the largest entry crossing (and 0), exit the smallest
+    exit crossing (and 1); l = r (t_b - t_a).  Returns (t_a, t_b, l) per bucket
+    (l = 0 where not crossed)."""
+    x32 = np.asarray(x, np.float32)
+    r2, d = _r2_f32(x32, np.asarray(y, np.float32))
+    assert np.all(d != 0)
+    inv = np.float32(1.0) / d
+    r = np.sqrt(r2)
+    lo = np.asarray(leaf_lo, np.float32)
+    hi = np.asarray(leaf_hi, np.float32)
+    t_lo = (lo - x32) * inv
+    t_hi = (hi - x32) * inv
+    ent = np.where(d > 0, t_lo, t_hi)
+    ext = np.where(d > 0, t_hi, t_lo)
+    ta = np.maximum(np.float32(0), ent.max(axis=1))
+    tb = np.minimum(np.float32(1), ext.min(axis=1))
+    l = np.where(tb > ta, r * (tb - ta), np.float32(0))
+    return ta, tb, l.astype(np.float64), float(r)
 
 
 def _field(n, seed, n_src, f32_pos=False):
@@ -84,11 +138,12 @@ def test_mirror32_thin_all_pairs():
     pos, rho, kappa, lum, mass = _field(1200, 32, 300)
     t = OracleTree(pos, rho, 0 * kappa, lum, mass, bucket_size=8, mirror32=True)
     F, C = t.flux(0.0, 0.1)
-    ref = B.all_pairs_flux(F32(pos), F32(lum))
+    ref = _all_pairs_f32(pos, lum)
     np.testing.assert_allclose(F, ref, rtol=1e-13, atol=0)
-    # the unrounded sum is farther away than that: the test sees the rounding
-    raw = B.all_pairs_flux(pos, lum)
-    assert np.max(np.abs(raw / F - 1.0)) > 1e-9
+    # binary64 geometry on the rounded inputs is farther away than that, and
+    # so are the unrounded inputs: the test sees each rounding
+    assert np.max(np.abs(B.all_pairs_flux(F32(pos), F32(lum)) / F - 1.0)) > 1e-9
+    assert np.max(np.abs(B.all_pairs_flux(pos, lum) / F - 1.0)) > 1e-9
     assert np.array_equal(C[:, 1], C[:, 2])
 
 
@@ -104,11 +159,14 @@ def test_mirror32_uniform_medium(theta, tau_ref):
     for i in (0, 9, 1500, 2999):
         log = t.ray_log(theta, tau_ref, i)
         r = np.linalg.norm(log["y"] - p32[i], axis=1)
-        np.testing.assert_allclose(log["tau"], kr * r, rtol=1e-13, atol=1e-15)
+        # binary32 r: 3.5 u; each piece r (t_b - t_a): 2 u; the pieces tile [0, 1]
+        np.testing.assert_allclose(log["tau"], kr * r, rtol=8 * U, atol=1e-15)
     if theta == 0.0:
         s = np.arange(0, n, 41)
         F, _ = t.flux(theta, tau_ref, sinks=s)
-        np.testing.assert_allclose(F, B.all_pairs_flux(p32, F32(lum), kr, sinks=s), rtol=1e-12)
+        rmax = math.sqrt(3.0)
+        ref = B.all_pairs_flux(p32, F32(lum), kr, sinks=s)
+        np.testing.assert_allclose(F, ref, rtol=8 * U * (1 + kr * rmax) + 4 * U)
 
 
 def _leaf_field(pos32, nb, mass, rho, kappa, round_alpha):
@@ -120,7 +178,7 @@ def _leaf_field(pos32, nb, mass, rho, kappa, round_alpha):
 
 
 @pytest.mark.parametrize("nb", [1, 6])
-def test_mirror32_full_limit_exact_leaf_integration(nb):
+def test_mirror32_full_limit_binary32_leaf_pieces(nb):
     pos, rho, kappa, lum, mass = _field(300, 34, 60)
     t = OracleTree(pos, rho, kappa, lum, mass, bucket_size=nb, mirror32=True)
     p32, l32 = F32(pos), F32(lum)
@@ -128,25 +186,30 @@ def test_mirror32_full_limit_exact_leaf_integration(nb):
     lv = B.leaves(ref)
     llo = np.array([nd["lo"] for nd in lv])
     lhi = np.array([nd["hi"] for nd in lv])
+    assert np.array_equal(F32(llo), llo) and np.array_equal(F32(lhi), lhi)
     lal = np.array([nd["alpha"] for nd in lv])
     lal64 = np.array([nd["alpha"] for nd in B.leaves(
         _leaf_field(p32, nb, mass, rho, kappa, round_alpha=False))])
     F, C = t.flux(0.0, -1.0)
-    worst64 = 0.0
+    worst_alpha = worst_geom = 0.0
     for i in range(0, 300, 7):
         log = t.ray_log(0.0, -1.0, i)
         f = 0.0
         nseg = 0
         for src, tau in zip(log["src"], log["tau"]):
-            ex, k = B.exact_tau_leaf_field(p32[i], p32[src], llo, lhi, lal)
+            _, _, l, _ = _leaf_pieces_f32(p32[i], p32[src], llo, lhi)
+            ex = float(np.sum(lal * l))
             assert math.isclose(tau, ex, rel_tol=1e-12, abs_tol=1e-14)
-            ex64, _ = B.exact_tau_leaf_field(p32[i], p32[src], llo, lhi, lal64)
-            worst64 = max(worst64, abs(tau - ex64) / ex64)
-            nseg += k
-            f += l32[src] * math.exp(-ex) / (4 * math.pi * np.sum((p32[src] - p32[i]) ** 2))
+            # binary64 alphas, or binary64 geometry, would not pass that check
+            worst_alpha = max(worst_alpha, abs(tau - float(np.sum(lal64 * l))) / tau)
+            ex64, _ = B.exact_tau_leaf_field(p32[i], p32[src], llo, lhi, lal)
+            worst_geom = max(worst_geom, abs(tau - ex64) / tau)
+            nseg += int(np.count_nonzero(l > 0))
+            r2, _ = _r2_f32(p32[i], p32[src])
+            f += l32[src] * math.exp(-ex) / (4 * math.pi * float(r2))
         assert C[i, 3] == nseg
         assert math.isclose(F[i], f, rel_tol=1e-12)
-    assert worst64 > 1e-10  # the binary64 alphas would not pass the 1e-12 check
+    assert worst_alpha > 1e-10 and worst_geom > 1e-10
 
 
 @pytest.mark.parametrize("theta", [0.0, 0.75])
@@ -157,28 +220,46 @@ def test_mirror32_never_refine_limit(theta):
     e = t.export()
     ref = _leaf_field(p32, 4, mass, rho, kappa, round_alpha=True)
     assert len(ref) == t.m
+    amax = max(nd["alpha"] for nd in ref)
+    worst = 0.0
     for i in range(0, 400, 13):
         log = t.ray_log(theta, math.inf, i)
         S = e["leaf_of"][i]
+        C_ = t.flux(theta, math.inf, sinks=[i])[1][0]
         for C, y, tau in zip(log["C"], log["y"], log["tau"]):
             ex = B.walk_up_tau(ref, S, C, p32[i], y)
-            assert math.isclose(tau, ex, rel_tol=1e-12, abs_tol=1e-14)
+            r = float(np.linalg.norm(y - p32[i]))
+            # each piece boundary t moves by at most 4 u, each length by 5.5 u
+            bound = 6 * U * ex + 2 * 4 * U * r * amax * (C_[3] + 2)
+            assert abs(tau - ex) <= bound, (tau, ex, bound)
+            worst = max(worst, abs(tau - ex) / ex)
+    assert worst > 1e-12
 
 
-def test_mirror32_against_binary64_within_alpha_rounding():
-    pos, rho, kappa, lum, mass = _field(1500, 36, 400, f32_pos=True)
+def test_mirror32_against_binary64_within_binary32_rounding():
+    pos, rho, kappa, lum, mass = _field(800, 36, 200, f32_pos=True)
     lum = F32(lum)
-    sinks = np.arange(0, 1500, 5)
     o32 = OracleTree(pos, rho, kappa, lum, mass, bucket_size=8, mirror32=True)
     o64 = OracleTree(pos, rho, kappa, lum, mass, bucket_size=8, mirror32=False)
-    F32_, C32 = o32.flux(0.0, -1.0, sinks=sinks)
-    F64_, C64, G = o64.flux(0.0, -1.0, sinks=sinks, with_g=True)
-    assert np.array_equal(C32, C64)  # theta 0 and tau_ref < 0: no decision depends on rounding
-    rel = np.abs(F32_ / F64_ - 1.0)
-    taus = np.concatenate([o64.ray_log(0.0, -1.0, int(i))["tau"] for i in sinks])
-    bound = math.expm1(2.0 ** -24 * float(np.max(taus))) + 1e-14
-    assert np.all(rel <= bound), (rel.max(), bound)
-    assert rel.max() > 1e-12  # the mirror does round alpha
+    ref = _leaf_field(pos, 8, mass, rho, kappa, round_alpha=False)
+    lv = B.leaves(ref)
+    llo = np.array([nd["lo"] for nd in lv])
+    lhi = np.array([nd["hi"] for nd in lv])
+    lal = np.array([nd["alpha"] for nd in lv])
+    worst = 0.0
+    for i in range(0, 800, 23):
+        g32 = o32.ray_log(0.0, -1.0, i)
+        g64 = o64.ray_log(0.0, -1.0, i)
+        assert np.array_equal(g32["src"], g64["src"])  # theta 0: the same rays
+        for src, t32, t64 in zip(g32["src"], g32["tau"], g64["tau"]):
+            ta, tb, l, r = _leaf_pieces_f32(pos[i], pos[src], llo, lhi)
+            on = l > 0
+            a_seq = lal[on][np.argsort(ta[on])]
+            tv = float(np.sum(np.abs(np.diff(np.r_[0.0, a_seq, 0.0]))))
+            bound = U * t64 + 7 * U * t64 + 5 * U * r * tv + 1e-15
+            assert abs(t32 - t64) <= bound, (t32, t64, bound)
+            worst = max(worst, abs(t32 - t64) / t64)
+    assert worst > 1e-12  # the mirror does round
 
 
 @pytest.mark.parametrize("theta,tau_ref", [(0.5, 0.05), (0.75, 0.1), (1.0, 0.3)])
