@@ -38,6 +38,9 @@ METRIC = "sink fluxes/s + cell visits/s at 2^21 particles; fwd+adjoint vs fwd ti
 # position, bucket and flux (20 B)
 BYTES_OPEN, BYTES_TRACE, BYTES_PSRC, BYTES_SINK = 24, 12, 16, 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_flux_c3.json")
+# MI355X VALU issue: 256 compute units x 4 SIMDs, one wave64 VALU instruction
+# per SIMD every 4 cycles (16 lanes per cycle) at 2.4 GHz
+VALU_PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 FLUX_SRC = os.path.join(ROOT, "paper_1902_08083_amd", "csrc", "flux.hip")
 
 
@@ -77,9 +80,9 @@ def timed_steps(torch, P, w, steps, warmup, tree):
     return (t1 - t0) * 1e3 / steps, float(np.mean(flux_ms)), flux
 
 
-def counters_run(torch, tree, w):
+def counters_run(P, tree, w):
     _, C = tree.flux(w["theta"], w["tau_ref"], counters=True)
-    return C.to(torch.int64).sum(0).cpu().numpy()
+    return P.sum_counters(C).cpu().numpy()
 
 
 def vector_flux(torch, tree, w, reps=3):
@@ -307,15 +310,19 @@ def adjoint_ratio(torch, P, reps=5):
         return float(np.median(ms))
 
     t_f = t_of(lambda: tree.flux(w["theta"], w["tau_ref"]))
-    # the differentiable path: the forward records each ray's tau, the adjoint
-    # reads it and traces every ray once
+    # the differentiable path (store mode): the forward records each ray's
+    # tau, the adjoint reads it and traces every ray once
     t_ft = t_of(lambda: tree.flux(w["theta"], w["tau_ref"], tape=True))
     t_at = t_of(lambda: tree.adjoint_taped(gF))
-    # the adjoint on its own, tracing every ray twice
-    t_a = t_of(lambda: tree.adjoint(w["theta"], w["tau_ref"], gF))
+    # recompute mode: the adjoint on its own, tracing every ray twice, in
+    # caller scratch (no allocation)
+    scratch = torch.empty(tree.adjoint_scratch_size(P.ADJ_RECOMPUTE), dtype=torch.uint8,
+                          device="cuda")
+    t_a = t_of(lambda: tree.adjoint(w["theta"], w["tau_ref"], gF, mode=P.ADJ_RECOMPUTE,
+                                    scratch=scratch))
     return {"workload": w["name"], "fwd_ms": t_f, "fwd_taped_ms": t_ft, "adj_taped_ms": t_at,
             "fwd_plus_adj_over_fwd": (t_ft + t_at) / t_f,
-            "adj_two_pass_ms": t_a, "fwd_plus_adj_two_pass_over_fwd": (t_f + t_a) / t_f}
+            "adj_recompute_ms": t_a, "fwd_plus_adj_recompute_over_fwd": (t_f + t_a) / t_f}
 
 
 def batched(torch, P, reps=5):
@@ -349,15 +356,15 @@ def batched(torch, P, reps=5):
             "build_plus_tune_s": t_setup}
 
 
-def cpu_baseline(w, target_s=10.0):
-    """The oracle (binary64, OpenMP over sinks) on this host: full tree build
-    plus the flux at a seeded sample of sinks, scaled to sink fluxes/s."""
+def cpu_baseline(w, target_s=10.0, target_1core_s=8.0):
+    """The oracle (binary32 mirror, OpenMP over sinks) on this host: full tree
+    build plus the flux at a seeded sample of sinks, scaled to sink fluxes/s;
+    on every host core this process may use, and on one core."""
     from oracle.oracle import OracleTree
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    cores = min(cores, 16)
     f64 = lambda a: np.asarray(a, np.float64)  # noqa: E731
     t0 = time.perf_counter()
     o = OracleTree(f64(w["pos"]), f64(w["rho"]), f64(w["kappa"]), f64(w["lum"]), f64(w["mass"]),
@@ -365,19 +372,28 @@ def cpu_baseline(w, target_s=10.0):
     t_build = time.perf_counter() - t0
     n = w["pos"].shape[0]
     rng = np.random.default_rng(7)
-    pilot = rng.choice(n, size=512, replace=False)
-    t0 = time.perf_counter()
-    o.flux(w["theta"], w["tau_ref"], sinks=pilot, nthreads=cores)
-    per = (time.perf_counter() - t0) / pilot.size
-    ns = int(min(n, max(2048, target_s / max(per, 1e-9))))
-    sample = rng.choice(n, size=ns, replace=False)
-    t0 = time.perf_counter()
-    o.flux(w["theta"], w["tau_ref"], sinks=sample, nthreads=cores)
-    t_flux = time.perf_counter() - t0
+
+    def rate(threads, budget_s):
+        pilot = rng.choice(n, size=256 * threads, replace=False)
+        t0 = time.perf_counter()
+        o.flux(w["theta"], w["tau_ref"], sinks=pilot, nthreads=threads)
+        per = (time.perf_counter() - t0) / pilot.size
+        ns = int(min(n, max(256 * threads, budget_s / max(per, 1e-9))))
+        sample = rng.choice(n, size=ns, replace=False)
+        t0 = time.perf_counter()
+        o.flux(w["theta"], w["tau_ref"], sinks=sample, nthreads=threads)
+        return ns, time.perf_counter() - t0
+
+    ns, t_flux = rate(cores, target_s)
+    ns1, t_flux1 = rate(1, target_1core_s)
     t_full = t_build + t_flux * n / ns
+    t_full1 = t_build + t_flux1 * n / ns1
     return {"value": n / t_full, "unit": "sink fluxes/s", "cores": cores, "kind": "oracle",
-            "sample": "full tree build (%.1f s) + flux at %d seeded random sinks of %d (%.1f s), "
-                      "scaled to all sinks" % (t_build, ns, n, t_flux)}
+            "sample": "full tree build (%.1f s) + flux at %d seeded random sinks of %d on %d "
+                      "threads (%.1f s), scaled to all sinks" % (t_build, ns, n, cores, t_flux),
+            "one_core": {"value": n / t_full1, "unit": "sink fluxes/s", "cores": 1,
+                         "sample": "the same build + flux at %d seeded random sinks on 1 thread "
+                                   "(%.1f s), scaled to all sinks" % (ns1, t_flux1)}}
 
 
 def walk_kernel_name(launch):
@@ -390,16 +406,17 @@ def walk_kernel_name(launch):
     return "trevr::k_walk%s<float, false, false>" % ("" if wps == 3 else str(wps))
 
 
-def recorded_traffic(launch_key):
-    """HBM bytes per flux launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source and launch."""
+def recorded_counters(launch_key):
+    """The committed rocprofv3 counter summary of the flux launch (HBM bytes,
+    VALU instructions and lane cycles per launch), if it was taken on the
+    current kernel source and launch; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = json.load(open(TRAFFIC_FILE))
     src = hashlib.sha256(open(FLUX_SRC, "rb").read()).hexdigest()
     if rec.get("flux_hip_sha256") != src or rec.get("launch") != launch_key:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
 
 
 def main():
@@ -460,7 +477,7 @@ def main():
     log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
     ms_step, ms_flux, flux = timed_steps(torch, P, w, args.steps, args.warmup, tree)
     log("step %.2f ms, flux kernel %.2f ms" % (ms_step, ms_flux))
-    tot = counters_run(torch, tree, w)
+    tot = counters_run(P, tree, w)
     n_open, n_rays, n_psrc, n_seg, n_trace = [int(v) for v in tot]
     visits = n_open + n_trace
     alg_bytes = (BYTES_OPEN * n_open + BYTES_TRACE * n_trace + BYTES_PSRC * n_psrc
@@ -469,7 +486,15 @@ def main():
     launch = tree.get_launch()
     launch_key = "%d/%d/%d" % (launch["blocks_per_cu"], launch["waves_per_block"],
                                launch["chunk"])
-    traffic = recorded_traffic(launch_key)
+    rec = recorded_counters(launch_key)
+    traffic = None if rec is None else rec.get("hbm_bytes_per_launch")
+    valu = None
+    if rec is not None and rec.get("sq_insts_valu"):
+        issue = rec["sq_insts_valu"] / (ms_flux * 1e-3) / VALU_PEAK_WAVE_INSTR_PER_S
+        valu = {"issue_frac": issue,
+                "lane_util": rec["sq_thread_cycles_valu"] / (64.0 * rec["sq_insts_valu"]),
+                "insts_per_launch": rec["sq_insts_valu"],
+                "peak_wave_instr_per_s": VALU_PEAK_WAVE_INSTR_PER_S}
     info = tree.info()
     out = {
         "metric": METRIC,
@@ -482,7 +507,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": w["name"], "n_particles": n, "n_sources": int((w["lum"] > 0).sum()),
                    "n_sinks": n, "theta_open": w["theta"], "tau_ref": w["tau_ref"],
@@ -494,10 +519,13 @@ def main():
         "sink_fluxes_per_s_flux_only": n / (ms_flux * 1e-3),
         "per_sink": {"n_open": n_open / n, "n_rays": n_rays / n, "n_psrc": n_psrc / n,
                      "n_seg": n_seg / n, "n_trace": n_trace / n},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        # frac: the algorithmic bytes of every cell visit over 8 TB/s; bound:
+        # what the counters show limits the kernel, the VALU's instruction
+        # issue (the real HBM traffic is a few per cent of peak)
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": walk_kernel_name(launch),
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes, "valu": valu},
     }
     if not args.no_vector:
         log("vector flux on the same workload")

@@ -17,9 +17,12 @@
  *    caller; the library never frees or retains it beyond the call, except
  *    where stated.  Host arrays are read during the call only.
  *  - Floating-point arrays are float (TREVR_F32) or double (TREVR_F64) as
- *    the particle set's precision says.  In TREVR_F32 the tree stores its
- *    cell data rounded to binary32 ("transport") and all arithmetic is
- *    binary64; TREVR_F64 stores binary64.
+ *    the particle set's precision says.  In TREVR_F32 ("binary32
+ *    transport") the tree stores its cell data rounded to binary32 from the
+ *    binary64 build values, each ray's geometry (direction, 1/d, r^2, r, plane
+ *    crossings, piece lengths) is binary32, the refinement test and every
+ *    alpha l term are exact binary64 products, and optical depths and fluxes
+ *    are summed in binary64.  TREVR_F64 is binary64 throughout.
  *  - Every function returns a trevr_status (0 = success).  On failure a
  *    message is available from trevr_last_error() (per host thread).  The
  *    library never aborts and never prints.
@@ -173,25 +176,62 @@ int trevr_compute_flux(const trevr_tree *tree, double theta_open, double tau_ref
                        const int32_t *sinks, int64_t n_sinks, void *flux, int32_t *counters,
                        hipStream_t stream);
 
+/* How the adjoint meets the forward's rays (none stores segment lists):
+ *   TREVR_ADJ_RECOMPUTE: one kernel traces every ray twice, once for its
+ *     optical depth and once to scatter d loss / d alpha over its pieces
+ *     (segments recomputed, nothing stored per ray);
+ *   TREVR_ADJ_STORE: a recording flux stores each ray's optical depth (8 B
+ *     per ray), then the adjoint traces each ray once, for the scatter;
+ *   TREVR_ADJ_AUTO: STORE while the tree holds no recording of the caller's
+ *     (trevr_compute_flux_taped) and the tape fits in half the free device
+ *     memory, else RECOMPUTE; scratch owned by the tree. */
+typedef enum { TREVR_ADJ_AUTO = 0, TREVR_ADJ_RECOMPUTE = 1, TREVR_ADJ_STORE = 2 } trevr_adjoint_mode;
+
 /* Gradient of  sum_k grad_flux[k] * flux[k]  (flux as trevr_compute_flux
  * returns it for the same arguments) with respect to every particle's rho,
  * kappa and lum, with every accept / open / refine decision of the forward
- * held fixed.  Merged sources contribute through their luminosity and their
- * centre of luminosity.  No segment is stored.  While the tree holds no
- * recording (trevr_compute_flux_taped) and a tape of one optical depth per
- * ray fits in half the free device memory, a recording flux and the taped
- * adjoint run (each ray traced once for tau and once for the scatter), using
- * the tape as scratch; else one kernel traces every ray twice and a recording
- * is left as it is.
+ * held fixed (Sec. 2.2.1-2.2.3: alpha = sum m kappa / sum m/rho of each
+ * piece's cell, the merged sources' L_C and centre of luminosity).  Merged
+ * sources contribute through their luminosity and their centre of
+ * luminosity.
  *   grad_flux: device, n_sinks.  grad_rho, grad_kappa, grad_lum: device, n
  *   each (overwritten; zero for massless particles' rho and kappa).
- * Uses scratch owned by the tree, allocated on first use and when the tape
- * grows (such a call is not graph-capturable).  Asynchronous.  Errors:
- * TREVR_E_ARG, _STATE, _HIP. */
+ *   mode: a trevr_adjoint_mode.
+ *   scratch: NULL, or device memory of scratch_bytes >= what
+ *   trevr_adjoint_scratch_size returns for this mode and n_sinks, 8-byte
+ *   aligned, owned by the caller and not retained.  With caller scratch the
+ *   call allocates nothing, never waits and only launches kernels (it can be
+ *   captured in a HIP graph); STORE then keeps its tape in the scratch and
+ *   leaves the tree's recording as it is.  With scratch NULL the tree's own
+ *   scratch is used, allocated on first use and when the tape grows (such a
+ *   call is not capturable); STORE then uses the tree's tape and drops a
+ *   recording of the caller's.  AUTO takes no caller scratch.
+ * Asynchronous.  Errors: TREVR_E_ARG (mode out of range, scratch with AUTO or
+ * misaligned), TREVR_E_CAPACITY (scratch_bytes too small), _STATE, _HIP. */
 int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_ref,
                                const int32_t *sinks, int64_t n_sinks, const void *grad_flux,
-                               void *grad_rho, void *grad_kappa, void *grad_lum,
-                               hipStream_t stream);
+                               void *grad_rho, void *grad_kappa, void *grad_lum, int32_t mode,
+                               void *scratch, size_t scratch_bytes, hipStream_t stream);
+
+/* Device scratch that trevr_compute_flux_adjoint needs in `mode` for
+ * n_sinks sinks on the built tree: RECOMPUTE 8 (5 m + n) bytes (per cell
+ * d loss / d alpha, d loss / d L_C and d loss / d x_L; per particle the
+ * single sources' d loss / d L), STORE that plus the recording's flux, the
+ * tape's per-set heads and a tape of 516 B per 64 rays, sized as the tree
+ * sizes its own (the last recording's block count plus a quarter, or 1024
+ * rays per sink); AUTO 0 (it takes none).  A smaller STORE scratch that still
+ * holds one tape block per 64 sinks is accepted: a recording that outgrows
+ * it makes the adjoint trace each ray twice (same result).  Host, no wait.
+ * Errors: TREVR_E_ARG, _STATE. */
+int trevr_adjoint_scratch_size(const trevr_tree *tree, int32_t mode, int64_t n_sinks,
+                               size_t *bytes);
+
+/* Totals of per-sink counters (as trevr_compute_flux writes them, [n_sinks][5])
+ * over the sinks, skipping invalid sinks (-1): totals, device int64 [5],
+ * overwritten.  cell visits = totals[0] + totals[4].  Asynchronous, allocates
+ * nothing.  Errors: TREVR_E_ARG, _HIP. */
+int trevr_sum_counters(const int32_t *counters, int64_t n_sinks, int64_t *totals,
+                       hipStream_t stream);
 
 /* Flux and net radiation flux at the sinks (Sec. 2.1, eq. simpflux):
  * everything trevr_compute_flux computes, and in addition the vector sum over
@@ -311,6 +351,8 @@ int trevr_compute_flux_background(const trevr_tree *tree, double theta_open, dou
  *   [n] hydrogen number density, or NULL for 1; x: device [n], read and
  *   written; kappa: device [n], written; all of precision prec.
  *   dx_max: device, one double: receives max_i |x_eq - x_old|.
+ * With flux NULL only kappa = sigma x is written (x unchanged, dx_max 0):
+ * the opacity of a first flux from given fractions.
  * sigma >= 0, alpha_B > 0, 0 < damping <= 1.  Asynchronous, allocates
  * nothing.  Errors: TREVR_E_ARG, _HIP. */
 int trevr_ionisation_update(int64_t n, trevr_prec prec, const void *flux, const void *n_h,

@@ -13,11 +13,12 @@ NODE_F_FIELDS = (
 NODE_I_FIELDS = ("first", "count", "depth", "leaf", "parent", "right", "skip", "axis")
 
 from .trevr import (  # noqa: E402
-    COUNTER_FIELDS, BatchedPlan, Tree, TrevrError, TrevrFlux, TrevrNotBuilt, autotune, build_tree,
-    compute_flux, compute_flux_adjoint, flux, ionisation_equilibrium, ionisation_update, lib,
+    ADJ_AUTO, ADJ_RECOMPUTE, ADJ_STORE, COUNTER_FIELDS, BatchedPlan, Tree, TrevrError, TrevrFlux,
+    TrevrNotBuilt, autotune, build_tree, compute_flux, compute_flux_adjoint, flux,
+    ionisation_equilibrium, ionisation_update, lib, sum_counters,
 )
 
-__all__ = ["BatchedPlan", "autotune", "Tree", "TrevrError", "TrevrFlux", "TrevrNotBuilt", "build_tree", "compute_flux",
+__all__ = ["ADJ_AUTO", "ADJ_RECOMPUTE", "ADJ_STORE", "BatchedPlan", "autotune", "Tree",
+           "TrevrError", "TrevrFlux", "TrevrNotBuilt", "build_tree", "compute_flux",
            "compute_flux_adjoint", "flux", "ionisation_equilibrium", "ionisation_update", "lib",
-           "COUNTER_FIELDS", "NODE_F_FIELDS",
-           "NODE_I_FIELDS"]
+           "sum_counters", "COUNTER_FIELDS", "NODE_F_FIELDS", "NODE_I_FIELDS"]

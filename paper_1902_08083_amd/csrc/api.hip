@@ -47,16 +47,23 @@ static int check_particles(const trevr_particles *p) {
   return TREVR_OK;
 }
 
-static int check_walk(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
-                      int64_t n_sinks) {
-  if (!t) return fail(TREVR_E_ARG, "tree is NULL");
-  if (!t->built) return fail(TREVR_E_STATE, "tree holds no built tree");
+// The walk's arguments; those that need no tree are checked first (so that
+// they can be tested without a device).
+static int check_walk_args(double theta, double tau_ref, int64_t n_sinks) {
   if (!(theta >= 0) || !std::isfinite(theta)) return fail(TREVR_E_ARG, "theta_open must be >= 0");
   if (std::isnan(tau_ref)) return fail(TREVR_E_ARG, "tau_ref is NaN");
   if (n_sinks < 0) return fail(TREVR_E_ARG, "n_sinks < 0");
+  if (n_sinks >= (int64_t)1 << 31) return fail(TREVR_E_CAPACITY, "too many sinks");
+  return TREVR_OK;
+}
+static int check_walk(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                      int64_t n_sinks) {
+  const int rc = check_walk_args(theta, tau_ref, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (!t) return fail(TREVR_E_ARG, "tree is NULL");
+  if (!t->built) return fail(TREVR_E_STATE, "tree holds no built tree");
   if (!sinks && n_sinks != t->n && n_sinks != 0)
     return fail(TREVR_E_ARG, "sinks NULL needs n_sinks == n");
-  if (n_sinks >= (int64_t)1 << 31) return fail(TREVR_E_CAPACITY, "too many sinks");
   return TREVR_OK;
 }
 
@@ -125,9 +132,9 @@ int trevr_tree_create(trevr_tree **out) {
 void trevr_tree_destroy(trevr_tree *tree) { delete tree; }
 
 int trevr_build_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream) {
-  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
-  int rc = trevr::check_particles(p);
+  int rc = trevr::check_particles(p);  // host-side fields first
   if (rc != TREVR_OK) return rc;
+  if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
   return trevr::build_tree_impl(tree, p, stream);
 }
 
@@ -155,11 +162,11 @@ int trevr_compute_flux_variant(const trevr_tree *tree, double theta_open, double
                                int32_t open_mode, int32_t ray_mode, double tau_max,
                                const int32_t *sinks, int64_t n_sinks, void *flux,
                                int32_t *counters, hipStream_t stream) {
-  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
-  if (rc != TREVR_OK) return rc;
   if (open_mode < 0 || open_mode > 2) return trevr::fail(TREVR_E_ARG, "open_mode must be 0, 1 or 2");
   if (ray_mode < 0 || ray_mode > 1) return trevr::fail(TREVR_E_ARG, "ray_mode must be 0 or 1");
   if (!(tau_max > 0)) return trevr::fail(TREVR_E_ARG, "tau_max must be > 0 (or +infinity)");
+  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+  if (rc != TREVR_OK) return rc;
   if (n_sinks > 0 && !flux) return trevr::fail(TREVR_E_ARG, "flux is NULL");
   return trevr::flux_variant_impl(tree, theta_open, tau_ref, open_mode, ray_mode, tau_max, sinks,
                                   n_sinks, flux, counters, stream);
@@ -216,10 +223,10 @@ int trevr_export_sph(const trevr_tree *tree, int64_t *n_entries, int64_t *offset
 }
 
 int trevr_refit_tree(trevr_tree *tree, const trevr_particles *p, hipStream_t stream) {
+  int rc = trevr::check_particles(p);  // host-side fields first
+  if (rc != TREVR_OK) return rc;
   if (!tree) return trevr::fail(TREVR_E_ARG, "tree is NULL");
   if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");
-  int rc = trevr::check_particles(p);
-  if (rc != TREVR_OK) return rc;
   if (p->n != tree->n || p->prec != tree->prec || p->n_boxes != tree->n_boxes ||
       p->bucket_size != tree->nb)
     return trevr::fail(TREVR_E_ARG, "n, precision, boxes or bucket size differ from the build");
@@ -308,32 +315,62 @@ int trevr_reserve_tape(trevr_tree *tree, int64_t blocks) {
 
 int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_ref,
                                const int32_t *sinks, int64_t n_sinks, const void *grad_flux,
-                               void *grad_rho, void *grad_kappa, void *grad_lum,
-                               hipStream_t stream) {
-  int rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
+                               void *grad_rho, void *grad_kappa, void *grad_lum, int32_t mode,
+                               void *scratch, size_t scratch_bytes, hipStream_t stream) {
+  if (mode < TREVR_ADJ_AUTO || mode > TREVR_ADJ_STORE)
+    return trevr::fail(TREVR_E_ARG, "mode must be TREVR_ADJ_AUTO, _RECOMPUTE or _STORE");
+  if (scratch && mode == TREVR_ADJ_AUTO)
+    return trevr::fail(TREVR_E_ARG, "TREVR_ADJ_AUTO takes no caller scratch");
+  if (scratch && ((uintptr_t)scratch & 7u))
+    return trevr::fail(TREVR_E_ARG, "scratch must be 8-byte aligned");
+  int rc = trevr::check_walk_args(theta_open, tau_ref, n_sinks);
+  if (rc != TREVR_OK) return rc;
+  if (n_sinks > 0 && !grad_flux) return trevr::fail(TREVR_E_ARG, "grad_flux is NULL");
+  rc = trevr::check_walk(tree, theta_open, tau_ref, sinks, n_sinks);
   if (rc != TREVR_OK) return rc;
   if (tree->n > 0 && (!grad_rho || !grad_kappa || !grad_lum))
     return trevr::fail(TREVR_E_ARG, "a gradient output is NULL");
-  if (n_sinks > 0 && !grad_flux) return trevr::fail(TREVR_E_ARG, "grad_flux is NULL");
   return trevr::adjoint_impl(tree, theta_open, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
-                             grad_kappa, grad_lum, stream);
+                             grad_kappa, grad_lum, mode, scratch, scratch_bytes, stream);
 }
 
-static int set_launch_checked(trevr_tree *tree, const trevr_launch *cfg, trevr_launch &dst) {
-  if (!tree || !cfg) return trevr::fail(TREVR_E_ARG, "NULL argument");
+int trevr_adjoint_scratch_size(const trevr_tree *tree, int32_t mode, int64_t n_sinks,
+                               size_t *bytes) {
+  if (!tree || !bytes) return trevr::fail(TREVR_E_ARG, "tree or bytes is NULL");
+  if (!tree->built) return trevr::fail(TREVR_E_STATE, "tree holds no built tree");
+  if (mode < TREVR_ADJ_AUTO || mode > TREVR_ADJ_STORE)
+    return trevr::fail(TREVR_E_ARG, "mode must be TREVR_ADJ_AUTO, _RECOMPUTE or _STORE");
+  if (n_sinks < 0 || n_sinks >= (int64_t)1 << 31) return trevr::fail(TREVR_E_ARG, "bad n_sinks");
+  return trevr::adjoint_scratch_size_impl(tree, mode, n_sinks, bytes);
+}
+
+int trevr_sum_counters(const int32_t *counters, int64_t n_sinks, int64_t *totals,
+                       hipStream_t stream) {
+  if (n_sinks < 0 || !totals || (n_sinks > 0 && !counters))
+    return trevr::fail(TREVR_E_ARG, "NULL array or negative n_sinks");
+  return trevr::sum_counters_impl(counters, n_sinks, totals, stream);
+}
+
+static int check_launch(const trevr_launch *cfg) {
+  if (!cfg) return trevr::fail(TREVR_E_ARG, "NULL argument");
   if (cfg->blocks_per_cu < 1 || cfg->blocks_per_cu > 32)
     return trevr::fail(TREVR_E_ARG, "blocks_per_cu must be 1..32");
   if (cfg->waves_per_block < 1 || cfg->waves_per_block > 16)
     return trevr::fail(TREVR_E_ARG, "waves_per_block must be 1..16");
   if (cfg->chunk < 64 || cfg->chunk % 64 != 0 || cfg->chunk > 4096)
     return trevr::fail(TREVR_E_ARG, "chunk must be a multiple of 64 in 64..4096");
-  dst = *cfg;
+  return TREVR_OK;
+}
+static int set_launch_checked(trevr_tree *tree, const trevr_launch *cfg, trevr_launch *dst) {
+  int rc = check_launch(cfg);  // the shape first
+  if (rc != TREVR_OK) return rc;
+  if (!tree) return trevr::fail(TREVR_E_ARG, "NULL argument");
+  *dst = *cfg;
   return TREVR_OK;
 }
 
 int trevr_set_launch(trevr_tree *tree, const trevr_launch *cfg) {
-  return tree ? set_launch_checked(tree, cfg, tree->launch)
-              : trevr::fail(TREVR_E_ARG, "NULL argument");
+  return set_launch_checked(tree, cfg, tree ? &tree->launch : nullptr);
 }
 
 int trevr_get_launch(const trevr_tree *tree, trevr_launch *cfg) {
@@ -343,8 +380,7 @@ int trevr_get_launch(const trevr_tree *tree, trevr_launch *cfg) {
 }
 
 int trevr_set_adjoint_launch(trevr_tree *tree, const trevr_launch *cfg) {
-  return tree ? set_launch_checked(tree, cfg, tree->launch_adj)
-              : trevr::fail(TREVR_E_ARG, "NULL argument");
+  return set_launch_checked(tree, cfg, tree ? &tree->launch_adj : nullptr);
 }
 
 int trevr_get_adjoint_launch(const trevr_tree *tree, trevr_launch *cfg) {

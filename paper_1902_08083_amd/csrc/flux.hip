@@ -1886,6 +1886,24 @@ __global__ void k_zero_f64(double *p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+// Totals of the per-sink counters: a grid-stride sum per thread, a wave sum,
+// one 64-bit atomic per wave and counter.  Invalid sinks (-1) are skipped.
+__global__ void k_zero_i64(int64_t *p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+__global__ void k_sum_counters(const int32_t *c, int64_t n, int64_t *tot) {
+  int64_t s[5] = {0, 0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (c[5 * i] >= 0)
+      for (int k = 0; k < 5; ++k) s[k] += c[5 * i + k];
+  for (int k = 0; k < 5; ++k) {
+    for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_xor(s[k], o);
+    if ((threadIdx.x & 63) == 0 && s[k] != 0)
+      atomicAdd((unsigned long long *)&tot[k], (unsigned long long)s[k]);
+  }
+}
+
 // A cell without absorbing mass took its parent's alpha: its adjoint goes to
 // the parent (one level, deepest first).
 __global__ void k_adj_empty_up(const BfsNode *lvl, int cnt, const double *B,
@@ -2060,36 +2078,51 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   return TREVR_OK;
 }
 
-template <typename T, bool ADJ>
-static void set_tape(const trevr_tree *t, FluxArgs<T> &a, int mode) {
+// A tape of per-ray optical depths: the tree's own, or one laid out in a
+// caller's scratch buffer.
+struct TapeBufs {
+  double *tape;     // [cap][64]
+  int32_t *next;    // [cap]
+  int32_t *head;    // [64-sink sets]
+  int32_t *ctr;     // blocks taken
+  int64_t cap;      // blocks
+};
+static TapeBufs tree_tape(const trevr_tree *t) {
+  return TapeBufs{t->tape.as<double>(), t->tape_next.as<int32_t>(), t->tape_head.as<int32_t>(),
+                  t->tape_ctr.as<int32_t>(), t->tape_cap};
+}
+
+template <typename T>
+static void set_tape(FluxArgs<T> &a, int mode, const TapeBufs *tb) {
   a.tape_mode = mode;
   if (mode == 0) return;
-  a.tape = t->tape.as<double>();
-  a.tape_next = t->tape_next.as<int32_t>();
-  a.tape_head = t->tape_head.as<int32_t>();
-  a.tape_ctr = t->tape_ctr.as<int32_t>();
-  a.tape_cap = (int32_t)t->tape_cap;
+  a.tape = tb->tape;
+  a.tape_next = tb->next;
+  a.tape_head = tb->head;
+  a.tape_ctr = tb->ctr;
+  a.tape_cap = (int32_t)tb->cap;
 }
 
 template <typename T>
 static int flux_typed(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                       int64_t n_sinks, void *flux, int32_t *counters, int tape_mode,
-                      hipStream_t s, void *flux_vec = nullptr, void *flux_mom = nullptr) {
+                      const TapeBufs *tb, hipStream_t s, void *flux_vec = nullptr,
+                      void *flux_mom = nullptr) {
   if (n_sinks == 0) return TREVR_OK;
   FluxArgs<T> a = make_args<T, false>(t, theta, tau_ref, sinks, n_sinks);
   a.flux = static_cast<T *>(flux);
   a.flux_vec = static_cast<T *>(flux_vec);
   a.flux_mom = static_cast<T *>(flux_mom);
   a.counters = counters;
-  set_tape<T, false>(t, a, tape_mode);
+  set_tape<T>(a, tape_mode, tb);
   return launch_walk<T, false>(t, a, s);
 }
 
 int flux_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
               int64_t n_sinks, void *flux, int32_t *counters, hipStream_t s) {
   if (t->prec == TREVR_F64)
-    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s);
-  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s);
+    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, nullptr, s);
+  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, nullptr, s);
 }
 
 template <typename T>
@@ -2187,36 +2220,51 @@ int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32
                   int64_t n_sinks, void *flux, void *flux_vec, void *flux_mom,
                   int32_t *counters, hipStream_t s) {
   if (t->prec == TREVR_F64)
-    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s, flux_vec,
-                              flux_mom);
-  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, s, flux_vec,
-                           flux_mom);
+    return flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, nullptr, s,
+                              flux_vec, flux_mom);
+  return flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 0, nullptr, s,
+                           flux_vec, flux_mom);
 }
 
 // Blocks for the next recording: what trevr_reserve_tape set, else the last
 // recording's count plus a quarter (and one per set), else a first guess of
-// 1024 rays per sink; `fits` tells whether that fits in half the free device
-// memory (beyond what the tape already holds), and the capacity is cut to
-// what fits.
-static int tape_blocks(trevr_tree *t, int64_t n_sinks, int64_t &cap, bool &fits) {
+// 1024 rays per sink.
+static int64_t tape_want(const trevr_tree *t, int64_t n_sinks) {
   const int64_t sets = (n_sinks + 63) / 64;
   const int64_t used = t->tape_used_h ? *(volatile int32_t *)t->tape_used_h : 0;
-  cap = t->tape_reserve > 0 ? t->tape_reserve
-                            : used > 0 ? used + used / 4 + sets : sets * 1024 + sets;
+  int64_t cap = t->tape_reserve > 0 ? t->tape_reserve
+                                    : used > 0 ? used + used / 4 + sets : sets * 1024 + sets;
+  if (cap > INT32_MAX - 65536) cap = INT32_MAX - 65536;
+  return cap < 1 ? 1 : cap;
+}
+// The same, cut to what fits in half the free device memory (beyond what the
+// tree's tape already holds); `fits` tells whether it was cut.
+static int tape_blocks(trevr_tree *t, int64_t n_sinks, int64_t &cap, bool &fits) {
+  cap = tape_want(t, n_sinks);
   size_t free_b = 0, total_b = 0;
   TREVR_HIP(hipMemGetInfo(&free_b, &total_b));
   const size_t per = 64 * sizeof(double) + sizeof(int32_t);
   const int64_t fit = (int64_t)((free_b / 2 + t->tape.bytes + t->tape_next.bytes) / per);
   fits = cap <= fit;
   if (!fits && t->tape_reserve <= 0) cap = fit;
-  if (cap > INT32_MAX - 65536) cap = INT32_MAX - 65536;
   if (cap < 1) cap = 1;
   return TREVR_OK;
 }
 
-// The recording flux: sizes the tape (the last recording's block count plus a
-// quarter, or a first guess of 1024 rays per sink within half the free
-// memory), then records.  A recording that outgrows its tape is left
+// A recording flux into the tape `tb`: the block counter is cleared by a
+// kernel (capturable), then the walk records one tau per ray.
+static int record_into(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+                       int64_t n_sinks, void *flux, int32_t *counters, const TapeBufs &tb,
+                       hipStream_t s) {
+  k_zero_i32<<<1, 64, 0, s>>>(tb.ctr, 1);
+  return t->prec == TREVR_F64
+             ? flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 1, &tb, s)
+             : flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 1, &tb, s);
+}
+
+// The recording flux on the tree's tape: sizes it (the last recording's block
+// count plus a quarter, or a first guess of 1024 rays per sink within half the
+// free memory), then records.  A recording that outgrows its tape is left
 // incomplete; the adjoint then traces twice, and the next recording is sized
 // from this one's count, which reaches the host asynchronously.
 int flux_taped_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
@@ -2239,10 +2287,7 @@ int flux_taped_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *
   TREVR_HIP(t->tape_head.ensure((size_t)(sets > 0 ? sets : 1) * sizeof(int32_t)));
   TREVR_HIP(t->tape_ctr.ensure(sizeof(int32_t)));
   t->tape_cap = cap;
-  k_zero_i32<<<1, 64, 0, s>>>(t->tape_ctr.as<int32_t>(), 1);
-  int rc = t->prec == TREVR_F64
-               ? flux_typed<double>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 1, s)
-               : flux_typed<float>(t, theta, tau_ref, sinks, n_sinks, flux, counters, 1, s);
+  int rc = record_into(t, theta, tau_ref, sinks, n_sinks, flux, counters, tree_tape(t), s);
   if (rc != TREVR_OK) return rc;
   TREVR_HIP(hipMemcpyAsync(t->tape_used_h, t->tape_ctr.p, sizeof(int32_t),
                            hipMemcpyDeviceToHost, s));
@@ -2254,16 +2299,22 @@ int flux_taped_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *
   return TREVR_OK;
 }
 
+// The adjoint's accumulators: per cell d loss / d alpha, d loss / d L_C and
+// d loss / d x_L (5 m doubles), per particle d loss / d L of single sources.
+struct AdjBufs {
+  double *node;  // [5][m]
+  double *part;  // [n]
+};
+
 template <typename T>
-static int adjoint_typed(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
+static int adjoint_typed(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                          int64_t n_sinks, const void *grad_flux, void *grad_rho,
-                         void *grad_kappa, void *grad_lum, int tape_mode, hipStream_t s) {
+                         void *grad_kappa, void *grad_lum, int tape_mode, const TapeBufs *tb,
+                         const AdjBufs &ab, hipStream_t s) {
   const int64_t m = t->m, n = t->n;
-  TREVR_HIP(t->adj_node.ensure(sizeof(double) * 5 * (size_t)(m > 0 ? m : 1)));
-  TREVR_HIP(t->adj_part.ensure(sizeof(double) * (size_t)(n > 0 ? n : 1)));
-  double *abar = t->adj_node.as<double>();
+  double *abar = ab.node;
   double *lbar = abar + m, *xbar = abar + 2 * m;
-  double *direct = t->adj_part.as<double>();
+  double *direct = ab.part;
   k_zero_f64<<<nblk(5 * m), 256, 0, s>>>(abar, 5 * m);
   if (n > 0) k_zero_f64<<<nblk(n), 256, 0, s>>>(direct, n);
   if (n_sinks > 0) {
@@ -2273,7 +2324,7 @@ static int adjoint_typed(trevr_tree *t, double theta, double tau_ref, const int3
     a.lbar = lbar;
     a.xbar = xbar;
     a.direct = direct;
-    set_tape<T, true>(t, a, tape_mode);
+    set_tape<T>(a, tape_mode, tb);
     int rc = launch_walk<T, true>(t, a, s);
     if (rc != TREVR_OK) return rc;
   }
@@ -2294,44 +2345,162 @@ static int adjoint_typed(trevr_tree *t, double theta, double tau_ref, const int3
   return TREVR_OK;
 }
 
-// The adjoint without a recording: while the tree holds no recording of the
-// caller's, a recording flux and the taped adjoint (each ray traced once for
-// tau, once for the scatter, in two kernels) when the tape fits in half the
-// free device memory; else one kernel that traces every ray twice.  A
-// recording of the caller's is left as it is.
+static int adjoint_dispatch(const trevr_tree *t, double theta, double tau_ref,
+                            const int32_t *sinks, int64_t n_sinks, const void *grad_flux,
+                            void *grad_rho, void *grad_kappa, void *grad_lum, int tape_mode,
+                            const TapeBufs *tb, const AdjBufs &ab, hipStream_t s) {
+  if (t->prec == TREVR_F64)
+    return adjoint_typed<double>(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
+                                 grad_kappa, grad_lum, tape_mode, tb, ab, s);
+  return adjoint_typed<float>(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho, grad_kappa,
+                              grad_lum, tape_mode, tb, ab, s);
+}
+
+static int tree_adj_bufs(trevr_tree *t, AdjBufs &ab) {
+  const int64_t m = t->m, n = t->n;
+  TREVR_HIP(t->adj_node.ensure(sizeof(double) * 5 * (size_t)(m > 0 ? m : 1)));
+  TREVR_HIP(t->adj_part.ensure(sizeof(double) * (size_t)(n > 0 ? n : 1)));
+  ab.node = t->adj_node.as<double>();
+  ab.part = t->adj_part.as<double>();
+  return TREVR_OK;
+}
+
+// Caller scratch layout, each part 256-byte aligned: the accumulators
+// (5 m + n doubles); in store mode then the recording's flux (n_sinks of the
+// tree's precision), the tape's per-set heads (4 B per 64 sinks), its block
+// counter, and the tape itself, cap blocks of 64 taus plus a 4-byte link each.
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+static size_t adj_part_bytes(const trevr_tree *t) {
+  return al256(sizeof(double) * 5 * (size_t)(t->m > 0 ? t->m : 1)) +
+         al256(sizeof(double) * (size_t)(t->n > 0 ? t->n : 1));
+}
+static size_t store_fixed_bytes(const trevr_tree *t, int64_t n_sinks) {
+  const size_t elem = t->prec == TREVR_F64 ? sizeof(double) : sizeof(float);
+  const int64_t sets = (n_sinks + 63) / 64;
+  return al256(elem * (size_t)(n_sinks > 0 ? n_sinks : 1)) +
+         al256(sizeof(int32_t) * (size_t)(sets > 0 ? sets : 1)) + 256;
+}
+static size_t store_block_bytes(int64_t cap) {
+  return al256((size_t)cap * 64 * sizeof(double)) + al256((size_t)cap * sizeof(int32_t));
+}
+
+int adjoint_scratch_size_impl(const trevr_tree *t, int mode, int64_t n_sinks, size_t *bytes) {
+  if (mode == TREVR_ADJ_AUTO) {
+    *bytes = 0;
+  } else if (mode == TREVR_ADJ_RECOMPUTE) {
+    *bytes = adj_part_bytes(t);
+  } else {
+    const int64_t sets = (n_sinks + 63) / 64;
+    int64_t cap = tape_want(t, n_sinks);
+    if (cap < sets) cap = sets;
+    *bytes = adj_part_bytes(t) + store_fixed_bytes(t, n_sinks) + store_block_bytes(cap);
+  }
+  return TREVR_OK;
+}
+
+// Carve the caller's scratch; returns false if it is too small.
+static bool carve(const trevr_tree *t, int mode, int64_t n_sinks, void *scratch, size_t bytes,
+                  AdjBufs &ab, TapeBufs &tb, void *&flux_tmp) {
+  char *p = static_cast<char *>(scratch);
+  const size_t need_adj = adj_part_bytes(t);
+  if (bytes < need_adj) return false;
+  ab.node = reinterpret_cast<double *>(p);
+  ab.part = reinterpret_cast<double *>(p + al256(sizeof(double) * 5 * (size_t)(t->m > 0 ? t->m : 1)));
+  if (mode != TREVR_ADJ_STORE) return true;
+  p += need_adj;
+  size_t left = bytes - need_adj;
+  const size_t fixed = store_fixed_bytes(t, n_sinks);
+  if (left < fixed) return false;
+  const size_t elem = t->prec == TREVR_F64 ? sizeof(double) : sizeof(float);
+  const int64_t sets = (n_sinks + 63) / 64;
+  flux_tmp = p;
+  p += al256(elem * (size_t)(n_sinks > 0 ? n_sinks : 1));
+  tb.head = reinterpret_cast<int32_t *>(p);
+  p += al256(sizeof(int32_t) * (size_t)(sets > 0 ? sets : 1));
+  tb.ctr = reinterpret_cast<int32_t *>(p);
+  p += 256;
+  left -= fixed;
+  // the largest cap whose blocks fit (each block 512 B of taus + 4 B of link)
+  int64_t cap = (int64_t)(left / (64 * sizeof(double) + sizeof(int32_t)));
+  while (cap > 0 && store_block_bytes(cap) > left) --cap;
+  if (cap > INT32_MAX - 65536) cap = INT32_MAX - 65536;
+  if (cap < (sets > 0 ? sets : 1)) return false;
+  tb.tape = reinterpret_cast<double *>(p);
+  tb.next = reinterpret_cast<int32_t *>(p + al256((size_t)cap * 64 * sizeof(double)));
+  tb.cap = cap;
+  return true;
+}
+
+// The adjoint.  AUTO (tree-owned scratch): while the tree holds no recording
+// of the caller's, a recording flux and the taped adjoint (each ray traced
+// once for tau, once for the scatter, in two kernels) when the tape fits in
+// half the free device memory; else one kernel that traces every ray twice;
+// a recording of the caller's is left as it is.  RECOMPUTE: that one kernel.
+// STORE: the recording flux and the taped adjoint, on the tree's tape (which
+// then no longer holds a recording of the caller's) or on one in the
+// caller's scratch.  With caller scratch nothing is allocated, nothing waits,
+// and every step is a kernel launch (graph-capturable).
 int adjoint_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                  int64_t n_sinks, const void *grad_flux, void *grad_rho, void *grad_kappa,
-                 void *grad_lum, hipStream_t s) {
-  if (n_sinks > 0 && !t->tape_ok) {
+                 void *grad_lum, int mode, void *scratch, size_t scratch_bytes, hipStream_t s) {
+  if (scratch) {
+    AdjBufs ab{};
+    TapeBufs tb{};
+    void *flux_tmp = nullptr;
+    if (!carve(t, mode, n_sinks, scratch, scratch_bytes, ab, tb, flux_tmp))
+      return fail(TREVR_E_CAPACITY, "scratch smaller than trevr_adjoint_scratch_size");
+    if (mode == TREVR_ADJ_STORE && n_sinks > 0) {
+      int rc = record_into(t, theta, tau_ref, sinks, n_sinks, flux_tmp, nullptr, tb, s);
+      if (rc != TREVR_OK) return rc;
+      return adjoint_dispatch(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho, grad_kappa,
+                              grad_lum, 2, &tb, ab, s);
+    }
+    return adjoint_dispatch(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho, grad_kappa,
+                            grad_lum, 0, nullptr, ab, s);
+  }
+  bool store = mode == TREVR_ADJ_STORE;
+  if (mode == TREVR_ADJ_AUTO && n_sinks > 0 && !t->tape_ok) {
     int64_t cap = 0;
     bool fits = false;
     int rc = tape_blocks(t, n_sinks, cap, fits);
     if (rc != TREVR_OK) return rc;
-    if (fits) {
-      const size_t elem = t->prec == TREVR_F64 ? sizeof(double) : sizeof(float);
-      TREVR_HIP(t->adj_flux.ensure(elem * (size_t)n_sinks));
-      rc = flux_taped_impl(t, theta, tau_ref, sinks, n_sinks, t->adj_flux.p, nullptr, s);
-      if (rc == TREVR_OK)
-        rc = adjoint_taped_impl(t, grad_flux, grad_rho, grad_kappa, grad_lum, s);
-      t->tape_ok = false;  // the tape served as scratch
-      return rc;
-    }
+    store = fits;
   }
-  if (t->prec == TREVR_F64)
-    return adjoint_typed<double>(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
-                                 grad_kappa, grad_lum, 0, s);
-  return adjoint_typed<float>(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho,
-                              grad_kappa, grad_lum, 0, s);
+  if (store && n_sinks > 0) {
+    const size_t elem = t->prec == TREVR_F64 ? sizeof(double) : sizeof(float);
+    TREVR_HIP(t->adj_flux.ensure(elem * (size_t)n_sinks));
+    int rc = flux_taped_impl(t, theta, tau_ref, sinks, n_sinks, t->adj_flux.p, nullptr, s);
+    if (rc == TREVR_OK) rc = adjoint_taped_impl(t, grad_flux, grad_rho, grad_kappa, grad_lum, s);
+    t->tape_ok = false;  // the tape served as scratch
+    return rc;
+  }
+  AdjBufs ab{};
+  int rc = tree_adj_bufs(t, ab);
+  if (rc != TREVR_OK) return rc;
+  return adjoint_dispatch(t, theta, tau_ref, sinks, n_sinks, grad_flux, grad_rho, grad_kappa,
+                          grad_lum, 0, nullptr, ab, s);
+}
+
+int sum_counters_impl(const int32_t *counters, int64_t n_sinks, int64_t *totals,
+                      hipStream_t s) {
+  k_zero_i64<<<1, 64, 0, s>>>(totals, 5);
+  if (n_sinks > 0) {
+    int64_t blocks = (n_sinks + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_sum_counters<<<(unsigned)blocks, 256, 0, s>>>(counters, n_sinks, totals);
+  }
+  TREVR_HIP(hipGetLastError());
+  return TREVR_OK;
 }
 
 int adjoint_taped_impl(trevr_tree *t, const void *grad_flux, void *grad_rho, void *grad_kappa,
                        void *grad_lum, hipStream_t s) {
-  if (t->prec == TREVR_F64)
-    return adjoint_typed<double>(t, t->tape_theta, t->tape_tau_ref, t->tape_sinks,
-                                 t->tape_n_sinks, grad_flux, grad_rho, grad_kappa, grad_lum, 2,
-                                 s);
-  return adjoint_typed<float>(t, t->tape_theta, t->tape_tau_ref, t->tape_sinks,
-                              t->tape_n_sinks, grad_flux, grad_rho, grad_kappa, grad_lum, 2, s);
+  AdjBufs ab{};
+  int rc = tree_adj_bufs(t, ab);
+  if (rc != TREVR_OK) return rc;
+  const TapeBufs tb = tree_tape(t);
+  return adjoint_dispatch(t, t->tape_theta, t->tape_tau_ref, t->tape_sinks, t->tape_n_sinks,
+                          grad_flux, grad_rho, grad_kappa, grad_lum, 2, &tb, ab, s);
 }
 
 }  // namespace trevr

@@ -39,19 +39,34 @@ __global__ void k_ion_update(int64_t n, const T *flux, const T *n_h, double sigm
 
 __global__ void k_ion_zero(double *p) { *p = 0.0; }
 
+// kappa = sigma x only (the opacity of a first flux from given fractions).
+template <typename T>
+__global__ void k_ion_kappa(int64_t n, double sigma, const T *x, T *kappa) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) kappa[i] = (T)(sigma * (double)x[i]);
+}
+
 }  // namespace trevr
 
 int trevr_ionisation_update(int64_t n, trevr_prec prec, const void *flux, const void *n_h,
                             double sigma, double alpha_b, double damping, void *x, void *kappa,
                             double *dx_max, hipStream_t stream) {
-  if (n < 0 || (n > 0 && (!flux || !x || !kappa)) || !dx_max)
+  if (n < 0 || (n > 0 && (!x || !kappa)) || !dx_max)
     return trevr::fail(TREVR_E_ARG, "NULL array or negative n");
   if (prec != TREVR_F32 && prec != TREVR_F64) return trevr::fail(TREVR_E_ARG, "bad precision");
   if (!(sigma >= 0) || !std::isfinite(sigma) || !(alpha_b > 0) || !std::isfinite(alpha_b) ||
       !(damping > 0 && damping <= 1))
     return trevr::fail(TREVR_E_ARG, "sigma >= 0, alpha_B > 0 and 0 < damping <= 1 required");
   trevr::k_ion_zero<<<1, 1, 0, stream>>>(dx_max);
-  if (n > 0) {
+  if (n > 0 && !flux) {  // kappa = sigma x only
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (prec == TREVR_F64)
+      trevr::k_ion_kappa<double><<<blocks, 256, 0, stream>>>(n, sigma, (const double *)x,
+                                                             (double *)kappa);
+    else
+      trevr::k_ion_kappa<float><<<blocks, 256, 0, stream>>>(n, sigma, (const float *)x,
+                                                            (float *)kappa);
+  } else if (n > 0) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
     if (prec == TREVR_F64)
       trevr::k_ion_update<double><<<blocks, 256, 0, stream>>>(

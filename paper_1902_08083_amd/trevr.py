@@ -69,8 +69,10 @@ EXPORTED = (
     "trevr_refit_tree", "trevr_compute_flux_moments", "trevr_set_bands",
     "trevr_compute_flux_bands", "trevr_set_sph", "trevr_compute_flux_sph", "trevr_export_sph",
     "trevr_compute_flux_variant", "trevr_set_background", "trevr_compute_flux_background",
-    "trevr_ionisation_update",
+    "trevr_ionisation_update", "trevr_adjoint_scratch_size", "trevr_sum_counters",
 )
+
+ADJ_AUTO, ADJ_RECOMPUTE, ADJ_STORE = 0, 1, 2
 
 
 def lib():
@@ -98,7 +100,12 @@ def lib():
     L.trevr_compute_flux.restype = I
     L.trevr_compute_flux.argtypes = [P, D, D, P, I64, P, P, P]
     L.trevr_compute_flux_adjoint.restype = I
-    L.trevr_compute_flux_adjoint.argtypes = [P, D, D, P, I64, P, P, P, P, P]
+    L.trevr_compute_flux_adjoint.argtypes = [P, D, D, P, I64, P, P, P, P, ctypes.c_int32, P,
+                                             ctypes.c_size_t, P]
+    L.trevr_adjoint_scratch_size.restype = I
+    L.trevr_adjoint_scratch_size.argtypes = [P, ctypes.c_int32, I64, ctypes.POINTER(ctypes.c_size_t)]
+    L.trevr_sum_counters.restype = I
+    L.trevr_sum_counters.argtypes = [P, I64, P, P]
     L.trevr_compute_flux_taped.restype = I
     L.trevr_compute_flux_taped.argtypes = [P, D, D, P, I64, P, P, P]
     L.trevr_compute_flux_adjoint_taped.restype = I
@@ -173,6 +180,9 @@ class Tree:
         _check(lib().trevr_tree_create(ctypes.byref(h)))
         self._h = h
         self.n = 0
+        # bumped by every call that changes the cell properties or the tape
+        # (build, refit, a recording flux, an adjoint on the tree's tape)
+        self.generation = 0
         self.prec = None
         self.dtype = None
         self.device = None
@@ -192,6 +202,7 @@ class Tree:
         p, keep = self._particles(pos, rho, kappa, lum, mass, box_lo, box_hi, bucket_size,
                                   box_offsets, device)
         _check(lib().trevr_build_tree(self._h, ctypes.byref(p), _stream()))
+        self.generation += 1
         self._layout = (box_lo, box_hi, bucket_size, box_offsets)
         self._n_bands = 0  # a build drops the bands
         self.n = p.n
@@ -208,6 +219,7 @@ class Tree:
         p, keep = self._particles(pos, rho, kappa, lum, mass, box_lo, box_hi, bucket_size,
                                   box_offsets, self.device)
         _check(lib().trevr_refit_tree(self._h, ctypes.byref(p), _stream()))
+        self.generation += 1
         self._n_bands = 0  # so does a refit
         return self
 
@@ -282,6 +294,7 @@ class Tree:
         _check(fn(self._h, float(theta_open), float(tau_ref), _ptr(s), ns, _ptr(F), _ptr(C),
                   _stream()))
         if tape:
+            self.generation += 1
             self._tape_sinks = s  # the recording reads it again in adjoint_taped
             self._tape_ns = ns
         return (F, C) if counters else F
@@ -409,15 +422,33 @@ class Tree:
         """Tape capacity of later recordings in blocks of 64 rays (0: automatic)."""
         _check(lib().trevr_reserve_tape(self._h, int(blocks)))
 
-    def adjoint(self, theta_open, tau_ref, grad_flux, sinks=None):
+    def adjoint_scratch_size(self, mode, n_sinks=None):
+        """Bytes of caller scratch the adjoint needs in `mode` (ADJ_RECOMPUTE or
+        ADJ_STORE) for n_sinks sinks (default: every particle)."""
+        b = ctypes.c_size_t(0)
+        ns = self.n if n_sinks is None else int(n_sinks)
+        _check(lib().trevr_adjoint_scratch_size(self._h, int(mode), ns, ctypes.byref(b)))
+        return int(b.value)
+
+    def adjoint(self, theta_open, tau_ref, grad_flux, sinks=None, mode=ADJ_AUTO, scratch=None,
+                out=None):
+        """Gradients (rho, kappa, lum) of sum_k grad_flux[k] F_k.  mode: ADJ_AUTO,
+        ADJ_RECOMPUTE (each ray traced twice) or ADJ_STORE (one tau per ray
+        recorded); scratch: a device tensor of at least adjoint_scratch_size
+        bytes (then nothing is allocated and the call can be graph-captured)."""
         s, ns = self._sinks(sinks)
         g = grad_flux.to(device=self.device, dtype=self.dtype).contiguous()
         if g.shape[0] != ns:
             raise ValueError("grad_flux has %d entries, expected %d" % (g.shape[0], ns))
-        outs = [torch.empty(self.n, dtype=self.dtype, device=self.device) for _ in range(3)]
+        outs = out if out is not None else [
+            torch.empty(self.n, dtype=self.dtype, device=self.device) for _ in range(3)]
+        nbytes = 0 if scratch is None else scratch.numel() * scratch.element_size()
         _check(lib().trevr_compute_flux_adjoint(self._h, float(theta_open), float(tau_ref),
                                                 _ptr(s), ns, _ptr(g), _ptr(outs[0]),
-                                                _ptr(outs[1]), _ptr(outs[2]), _stream()))
+                                                _ptr(outs[1]), _ptr(outs[2]), int(mode),
+                                                _ptr(scratch), nbytes, _stream()))
+        if scratch is None and mode != ADJ_RECOMPUTE:
+            self.generation += 1  # the tree's tape served as scratch
         return tuple(outs)
 
     def export(self):
@@ -452,31 +483,55 @@ def compute_flux(tree, theta_open, tau_ref, sinks=None, counters=False, out=None
     return tree.flux(theta_open, tau_ref, sinks, counters, out)
 
 
-def compute_flux_adjoint(tree, theta_open, tau_ref, grad_flux, sinks=None):
-    return tree.adjoint(theta_open, tau_ref, grad_flux, sinks)
+def compute_flux_adjoint(tree, theta_open, tau_ref, grad_flux, sinks=None, mode=ADJ_AUTO,
+                         scratch=None):
+    return tree.adjoint(theta_open, tau_ref, grad_flux, sinks, mode, scratch)
+
+
+def sum_counters(counters):
+    """Totals over the sinks of per-sink counters ([n_sinks, 5] int32, as the
+    flux calls return them): a device int64 tensor of 5 (n_open, n_rays,
+    n_psrc, n_seg, n_trace), invalid sinks skipped."""
+    c = counters.contiguous()
+    if c.dtype != torch.int32 or c.dim() != 2 or c.shape[1] != 5:
+        raise ValueError("counters must be int32 [n_sinks, 5]")
+    tot = torch.empty(5, dtype=torch.int64, device=c.device)
+    _check(lib().trevr_sum_counters(_ptr(c), int(c.shape[0]), _ptr(tot), _stream()))
+    return tot
 
 
 class TrevrFlux(torch.autograd.Function):
     """F = flux(rho, kappa, lum) at fixed positions; backward runs the adjoint
     kernel over the same traversal (decisions held fixed), with each ray's
-    optical depth taken from the forward's recording."""
+    optical depth taken from the forward's recording.  A shared tree may be
+    refit, recorded or used by other calls between this forward and its
+    backward: backward then refits it with this forward's values and records
+    again before the adjoint (the tree holds them afterwards)."""
 
     @staticmethod
     def forward(ctx, rho, kappa, lum, pos, mass, theta_open, tau_ref, bucket_size, sinks,
                 tree=None):
+        vals = (rho.detach(), kappa.detach(), lum.detach())
         if tree is None:
-            tree = build_tree(pos, rho.detach(), kappa.detach(), lum.detach(), mass,
-                              bucket_size=bucket_size, device=pos.device)
+            tree = build_tree(pos, *vals, mass, bucket_size=bucket_size, device=pos.device)
         else:  # a tree built earlier on these positions: new cell properties only
-            tree.refit(pos, rho.detach(), kappa.detach(), lum.detach(), mass)
+            tree.refit(pos, *vals, mass)
         F = tree.flux(theta_open, tau_ref, sinks, tape=True)
         ctx.tree = tree
+        ctx.generation = tree.generation
+        ctx.args = (pos, mass, theta_open, tau_ref, sinks) + vals
         return F
 
     @staticmethod
     def backward(ctx, gF):
-        g_rho, g_kappa, g_lum = ctx.tree.adjoint_taped(gF.contiguous())
+        tree = ctx.tree
+        if tree.generation != ctx.generation:  # the recording is not this forward's
+            pos, mass, theta_open, tau_ref, sinks, rho, kappa, lum = ctx.args
+            tree.refit(pos, rho, kappa, lum, mass)
+            tree.flux(theta_open, tau_ref, sinks, tape=True)
+        g_rho, g_kappa, g_lum = tree.adjoint_taped(gF.contiguous())
         ctx.tree = None
+        ctx.args = None
         return g_rho, g_kappa, g_lum, None, None, None, None, None, None, None
 
 
@@ -602,10 +657,10 @@ class BatchedPlan:
 def ionisation_update(flux, x, kappa, sigma, alpha_b, damping=0.5, n_h=None, dx_max=None):
     """One damped on-the-spot equilibrium step per particle (trevr_ionisation_update):
     x and kappa (= sigma x) are updated in place; returns the device scalar
-    max |x_eq - x_old|."""
+    max |x_eq - x_old|.  With flux None only kappa = sigma x is written."""
     dt = x.dtype
     prec = 1 if dt == torch.float64 else 0
-    for a in (flux, x, kappa) + ((n_h,) if n_h is not None else ()):
+    for a in (x, kappa) + tuple(v for v in (flux, n_h) if v is not None):
         if a.dtype != dt or not a.is_contiguous() or a.shape != x.shape:
             raise ValueError("flux, x, kappa (and n_h) must be contiguous, same dtype and shape")
     d = dx_max if dx_max is not None else torch.empty(1, dtype=torch.float64, device=x.device)
@@ -624,7 +679,8 @@ def ionisation_equilibrium(pos, rho, lum, mass, x, sigma, alpha_b, theta_open=0.
     The tree is built once and refit with the new opacities each step.
     Returns (x, flux, iterations, last max |x_eq - x|)."""
     x = x.clone().contiguous()
-    kappa = (sigma * x).contiguous()
+    kappa = torch.empty_like(x)
+    ionisation_update(None, x, kappa, sigma, alpha_b)  # kappa = sigma x
     tree = Tree().build(pos, rho, kappa, lum, mass, box_lo, box_hi, bucket_size)
     F = torch.empty_like(x)
     d = torch.empty(1, dtype=torch.float64, device=x.device)
