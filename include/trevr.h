@@ -213,6 +213,26 @@ int trevr_compute_flux_adjoint(trevr_tree *tree, double theta_open, double tau_r
                                void *grad_rho, void *grad_kappa, void *grad_lum, int32_t mode,
                                void *scratch, size_t scratch_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * trevr_compute_flux_adjoint in TREVR_ADJ_RECOMPUTE mode, with its scratch
+ * (8 (5 m + n) bytes: the per-cell and per-particle accumulators) in a
+ * device buffer of the library's own, 64 MiB per GPU, looked up when the
+ * first tree is created on that GPU and held until the process ends.  The
+ * call allocates nothing and frees nothing; the accumulators are cleared by
+ * kernels at the start of every call.  Arguments and results as
+ * trevr_compute_flux_adjoint.  The buffer is shared by every call on one
+ * GPU: calls that overlap in time on one GPU (on different streams, or from
+ * different host threads) race, and must be ordered by the caller.  The tree
+ * must live on the current device.  Asynchronous.  Errors: TREVR_E_CAPACITY
+ * (the tree needs more than 64 MiB: about 1.6 million cells with as many
+ * particles), TREVR_E_ARG (as trevr_compute_flux_adjoint, or the tree's
+ * device is not the current one), _STATE, _HIP. */
+int trevr_compute_flux_adjoint_noalloc(trevr_tree *tree, double theta_open, double tau_ref,
+                                       const int32_t *sinks, int64_t n_sinks,
+                                       const void *grad_flux, void *grad_rho, void *grad_kappa,
+                                       void *grad_lum, hipStream_t stream);
+
 /* Device scratch that trevr_compute_flux_adjoint needs in `mode` for
  * n_sinks sinks on the built tree: RECOMPUTE 8 (5 m + n) bytes (per cell
  * d loss / d alpha, d loss / d L_C and d loss / d x_L; per particle the

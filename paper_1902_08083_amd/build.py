@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtrevr.so")
-SOURCES = ["api.hip", "tree_build.hip", "flux.hip", "ionisation.hip"]
+SOURCES = ["api.hip", "tree_build.hip", "flux.hip", "ionisation.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -120,6 +120,13 @@ int trevr_tree_create(trevr_tree **out) {
     return trevr::hip_fail(e, "hipDeviceGetAttribute");
   }
   t->num_cu = cu > 0 ? cu : 256;
+  {  // this device's copy of the no-allocation adjoint's scratch, once per device
+    const int rc = trevr::noalloc_setup(t->device);
+    if (rc != TREVR_OK) {
+      delete t;
+      return rc;
+    }
+  }
   e = t->queue.ensure(256);
   if (e != hipSuccess) {
     delete t;

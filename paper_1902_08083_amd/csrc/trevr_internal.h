@@ -214,6 +214,7 @@ int adjoint_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *sin
                  void *grad_lum, int mode, void *scratch, size_t scratch_bytes, hipStream_t s);
 int adjoint_scratch_size_impl(const trevr_tree *t, int mode, int64_t n_sinks, size_t *bytes);
 int sum_counters_impl(const int32_t *counters, int64_t n_sinks, int64_t *totals, hipStream_t s);
+int noalloc_setup(int device);  // the no-allocation adjoint's scratch, per device
 int flux_vec_impl(const trevr_tree *t, double theta, double tau_ref, const int32_t *sinks,
                   int64_t n_sinks, void *flux, void *flux_vec, void *flux_mom,
                   int32_t *counters, hipStream_t s);

@@ -70,6 +70,7 @@ EXPORTED = (
     "trevr_compute_flux_bands", "trevr_set_sph", "trevr_compute_flux_sph", "trevr_export_sph",
     "trevr_compute_flux_variant", "trevr_set_background", "trevr_compute_flux_background",
     "trevr_ionisation_update", "trevr_adjoint_scratch_size", "trevr_sum_counters",
+    "trevr_compute_flux_adjoint_noalloc",
 )
 
 ADJ_AUTO, ADJ_RECOMPUTE, ADJ_STORE = 0, 1, 2
@@ -106,6 +107,8 @@ def lib():
     L.trevr_adjoint_scratch_size.argtypes = [P, ctypes.c_int32, I64, ctypes.POINTER(ctypes.c_size_t)]
     L.trevr_sum_counters.restype = I
     L.trevr_sum_counters.argtypes = [P, I64, P, P]
+    L.trevr_compute_flux_adjoint_noalloc.restype = I
+    L.trevr_compute_flux_adjoint_noalloc.argtypes = [P, D, D, P, I64, P, P, P, P, P]
     L.trevr_compute_flux_taped.restype = I
     L.trevr_compute_flux_taped.argtypes = [P, D, D, P, I64, P, P, P]
     L.trevr_compute_flux_adjoint_taped.restype = I
