@@ -1,0 +1,181 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration it
+times (default launch shapes), through the C ABI.
+
+  * 2^21 particles, every particle a source (the headline workload): the flux
+    at every sink in one launch, for each point of the theta_open x tau_ref
+    sweep {0.5, 0.75, 1.0} x {0.05, 0.1, 0.2}; the oracle (binary32 mirror)
+    evaluates a seeded 65,536-sink sample (seed 7): fluxes within 1e-5,
+    counters identical;
+  * the same tree exported bit for bit against the oracle's (order,
+    topology, keys, every binary64 cell value);
+  * the 64-box forest (uneven boxes, 2^12..2^17 particles): its export, box by
+    box, bit for bit against each box's own oracle tree, and the forest flux
+    at every sink of every box against each box's oracle, counters identical;
+  * the binary32 path against the pure binary64 oracle on the headline sample
+    (a report: the fraction of sinks within 1e-5, the largest error, sinks
+    whose counters differ), written to gpurun_out/fp32_vs_fp64_c3.json.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import paper_1902_08083_amd as P  # noqa: E402
+from oracle.oracle import OracleTree  # noqa: E402
+from paper_1902_08083_amd import workloads as W  # noqa: E402
+
+NTHREADS = min(16, os.cpu_count() or 1)
+SAMPLE = 65536
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+f64 = lambda a: np.asarray(a, np.float64)  # noqa: E731
+
+
+@pytest.fixture(scope="module")
+def c3():
+    _note("c3 full size: workload, GPU tree, oracle mirror tree")
+    w = W.c3()
+    tg = P.build_tree(*[torch.as_tensor(w[k], device="cuda")
+                        for k in ("pos", "rho", "kappa", "lum", "mass")],
+                      w["box_lo"], w["box_hi"], w["bucket_size"])
+    to = OracleTree(f64(w["pos"]), f64(w["rho"]), f64(w["kappa"]), f64(w["lum"]), f64(w["mass"]),
+                    w["box_lo"], w["box_hi"], w["bucket_size"], mirror32=True)
+    sample = np.sort(np.random.default_rng(7).choice(w["pos"].shape[0], size=SAMPLE,
+                                                     replace=False))
+    return w, tg, to, sample
+
+
+@pytest.mark.parametrize("theta,tau_ref", W.C3_SWEEP)
+def test_c3_sweep_full_size(c3, theta, tau_ref):
+    w, tg, to, sample = c3
+    _note("c3 2^21 theta %g tau_ref %g: every sink on the GPU, %d on the oracle"
+          % (theta, tau_ref, sample.size))
+    Fg, Cg = tg.flux(theta, tau_ref, counters=True)
+    Fg, Cg = Fg.double().cpu().numpy(), Cg.cpu().numpy().astype(np.int64)
+    assert np.all(np.isfinite(Fg)) and np.all(Fg > 0)
+    Fo, Co = to.flux(theta, tau_ref, sinks=sample, nthreads=NTHREADS)
+    rel = np.abs(Fg[sample] - Fo) / Fo
+    _note("max rel %.3g, median %.3g" % (rel.max(), np.median(rel)))
+    assert rel.max() <= 1e-5, (int(sample[np.argmax(rel)]), rel.max())
+    bad = np.nonzero(np.any(Cg[sample] != Co, axis=1))[0]
+    assert bad.size == 0, ("counters differ", sample[bad[:5]], Cg[sample[bad[:5]]], Co[bad[:5]])
+
+
+def _same(g, o, what):
+    assert set(g) == set(o), what
+    for k in o:
+        a, b = np.asarray(g[k]), np.asarray(o[k])
+        assert a.shape == b.shape, (what, k)
+        if b.dtype == np.float64:
+            same = (a == b) | (np.isnan(a) & np.isnan(b))
+            assert np.all(same), (what, k, int(np.argmin(same)))
+        else:
+            assert np.array_equal(a, b), (what, k)
+
+
+def test_c3_export_bit_exact_full_size(c3):
+    w, tg, to, _ = c3
+    _note("c3 2^21 export, bit for bit")
+    _same(tg.export(), to.export(), "c3 2^21")
+
+
+@pytest.fixture(scope="module")
+def c4():
+    _note("c4: 64 boxes, build the forest")
+    boxes = W.c4()
+    pos, rho, kappa, lum, mass, lo, hi, off = P.trevr._concat_boxes(boxes, "cuda")
+    t = P.Tree().build(pos, rho, kappa, lum, mass, lo, hi, 8, off)
+    return boxes, off, t
+
+
+def _box_oracle(bx):
+    return OracleTree(f64(bx["pos"]), f64(bx["rho"]), f64(bx["kappa"]), f64(bx["lum"]),
+                      f64(bx["mass"]), bx.get("box_lo", (0.0, 0.0, 0.0)),
+                      bx.get("box_hi", (1.0, 1.0, 1.0)), 8, mirror32=True)
+
+
+def test_c4_forest_export_box_by_box(c4):
+    boxes, off, t = c4
+    _note("c4 forest export against 64 per-box oracle trees")
+    e = t.export()
+    roots = np.nonzero(e["parent"] == -1)[0]
+    assert roots.size == len(boxes)
+    m = e["first"].size
+    ends = np.r_[roots[1:], m]
+    for b, bx in enumerate(boxes):
+        r0, r1 = int(roots[b]), int(ends[b])
+        p0, p1 = int(off[b]), int(off[b + 1])
+        o = _box_oracle(bx).export()
+        g = {"perm": e["perm"][p0:p1] - p0, "leaf_of": e["leaf_of"][p0:p1] - r0}
+        for k in o:
+            if k in ("perm", "leaf_of"):
+                continue
+            v = np.asarray(e[k][r0:r1])
+            if k == "first":
+                v = v - p0
+            elif k in ("parent", "right"):
+                v = np.where(v >= 0, v - r0, v)
+            elif k == "skip":
+                v = v - r0
+            g[k] = v
+        _same(g, o, "box %d" % b)
+
+
+def test_c4_every_box_flux_and_counters(c4):
+    boxes, off, t = c4
+    _note("c4 forest flux with counters, every box against its oracle")
+    F, C = t.flux(0.75, 0.1, counters=True)
+    F, C = F.double().cpu().numpy(), C.cpu().numpy().astype(np.int64)
+    worst = 0.0
+    for b, bx in enumerate(boxes):
+        p0, p1 = int(off[b]), int(off[b + 1])
+        Fo, Co = _box_oracle(bx).flux(0.75, 0.1, nthreads=NTHREADS)
+        g = F[p0:p1]
+        rel = np.abs(g - Fo) / np.where(Fo > 0, Fo, 1.0)
+        worst = max(worst, float(rel.max()))
+        assert rel.max() <= 1e-5, (b, float(rel.max()))
+        bad = np.nonzero(np.any(C[p0:p1] != Co, axis=1))[0]
+        assert bad.size == 0, ("box", b, "counters differ", bad[:5])
+    _note("worst rel over 64 boxes %.3g" % worst)
+
+
+def test_c3_binary32_against_pure_binary64_report(c3):
+    """Not a parity gate: how far the binary32 path (transport and geometry)
+    lies from the binary64 method on the same binary32-valued inputs.  A
+    threshold flip of eq. refcrit changes a ray's tau by at most about tau_ref,
+    and of eq. openangle merges or opens one cell."""
+    w, tg, _, sample = c3
+    _note("c3 binary32 path against the pure binary64 oracle, %d sinks" % sample.size)
+    t64 = OracleTree(f64(w["pos"]), f64(w["rho"]), f64(w["kappa"]), f64(w["lum"]), f64(w["mass"]),
+                     w["box_lo"], w["box_hi"], w["bucket_size"], mirror32=False)
+    th, tr = w["theta"], w["tau_ref"]
+    Fg, Cg = tg.flux(th, tr, counters=True)
+    Fg, Cg = Fg.double().cpu().numpy()[sample], Cg.cpu().numpy().astype(np.int64)[sample]
+    Fo, Co = t64.flux(th, tr, sinks=sample, nthreads=NTHREADS)
+    rel = np.abs(Fg - Fo) / Fo
+    flips = np.any(Cg != Co, axis=1)
+    rep = {"workload": w["name"], "theta": th, "tau_ref": tr, "sinks": int(sample.size),
+           "frac_within_1e-5": float(np.mean(rel <= 1e-5)),
+           "frac_within_1e-4": float(np.mean(rel <= 1e-4)),
+           "max_rel": float(rel.max()), "median_rel": float(np.median(rel)),
+           "p99_rel": float(np.quantile(rel, 0.99)),
+           "sinks_with_other_counters": int(flips.sum()),
+           "max_rel_where_counters_equal": float(rel[~flips].max()) if (~flips).any() else 0.0}
+    _note(json.dumps(rep))
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", "fp32_vs_fp64_c3.json"), "w") as f:
+        json.dump(rep, f, indent=1)
+    assert rep["median_rel"] < 1e-5 and rep["frac_within_1e-4"] > 0.99
