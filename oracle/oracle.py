@@ -8,7 +8,9 @@ is argument marshalling; the arithmetic is in the C file, in binary64.
 boxes, split planes, centres of luminosity, luminosities, far-vertex
 distances, alpha and alpha_max - alpha_min, particle positions and
 luminosities) rounded to binary32, as the GPU library stores them in its
-binary32 transport mode; all arithmetic stays binary64.
+binary32 transport mode, and compute each ray's geometry (direction, 1/d,
+r^2, r, plane crossings, piece lengths) in binary32 as that mode does; the
+criterion products, the alpha l terms and the sums stay binary64.
 """
 from __future__ import annotations
 
@@ -20,7 +22,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "trevr_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# TREVR_ORACLE_LIB names another build of the same source (the sanitizer tests
+# load an instrumented one); it is loaded as it is, never rebuilt
+_LIB_ENV = os.environ.get("TREVR_ORACLE_LIB")
+_LIB = _LIB_ENV or os.path.join(_HERE, "liboracle.so")
 
 NODE_F_FIELDS = (
     "lo0", "lo1", "lo2", "hi0", "hi1", "hi2", "split", "A", "B", "SL",
@@ -35,16 +40,21 @@ NODE_I_FIELDS = ("first", "count", "depth", "leaf", "parent", "right", "skip", "
 COUNTER_FIELDS = ("n_open", "n_rays", "n_psrc", "n_seg", "n_trace")
 
 
-def build_library(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, OpenMP, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call([
-            "gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
-            "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm",
-        ])
-        os.replace(tmp, _LIB)
-    return _LIB
+GCC_FLAGS = ["-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+             "-fno-fast-math"]
+
+
+def build_library(force: bool = False, path: str = None, extra=("-O2",)) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP, no FMA contraction);
+    `path` and `extra` make another build (e.g. with sanitizers)."""
+    out = path or _LIB
+    if path is None and _LIB_ENV:
+        return _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc"] + list(extra) + GCC_FLAGS + ["-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
