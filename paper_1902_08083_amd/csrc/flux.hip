@@ -7,7 +7,7 @@
 // every lane applies the opening test (eq. openangle) for its own sink, the
 // accepting lanes trace their ray at once, and the wave descends into a cell
 // if any lane opened it.  Lanes that accepted an ancestor are masked off in
-// its subtree; the per-depth masks and the cell path live in LDS.
+// its subtree; the per-depth masks live in LDS.
 //
 // A ray (Sec. 2.2.2-2.2.3) is traced by its own lane: split at the meeting
 // cell A of the sink bucket S and the source cell C, walk down from A toward
@@ -268,12 +268,8 @@ __device__ __forceinline__ void stack_pop(const RayCtx<G> &c, const StackSpill<G
   }
 }
 
-// A piece's accumulator slot in the adjoint: [0, 64) the sink chain at that
-// depth, [64, 128) the walk path at that depth, -1 the cell itself.
-constexpr int kSlotSrc = 64;
-
-// A policy receives each piece as (cell, slot, alpha, length, entry t and
-// plane, exit t and plane, spread) -- spread: for a bucket, its record's
+// A policy receives each piece as (cell, alpha, length, entry t and plane,
+// exit t and plane, spread) -- spread: for a bucket, its record's
 // spread field (the particle spread in the particle-trace kernel's records),
 // -1 for other cells.  Its traits shape the tracer at compile time: kLight
 // picks the form of the refinement step (see refine_branchy); kVar enables
@@ -288,8 +284,8 @@ struct TauSum {
   static constexpr bool kCount = true;  // per-ray counters of pieces and steps
   static constexpr bool kTags = false;  // the planes that bound each piece (adjoint scatter)
   double tau = 0.0;
-  __device__ __forceinline__ void operator()(int, int, double alpha, double l, double, int,
-                                             double, int, double) {
+  __device__ __forceinline__ void operator()(int, double alpha, double l, double, int, double,
+                                             int, double) {
     tau += alpha * l;
   }
 };
@@ -327,8 +323,8 @@ struct BandSum {
   const T *ba;  // [cell][4]
   int nb;
   double tau[kMaxBands] = {0.0, 0.0, 0.0, 0.0};
-  __device__ __forceinline__ void operator()(int node, int, double, double l, double, int,
-                                             double, int, double) {
+  __device__ __forceinline__ void operator()(int node, double, double l, double, int, double,
+                                             int, double) {
     T v[kMaxBands];
     if constexpr (sizeof(T) == 4) {  // the cell's bands in one 16-byte load
       const float4 q = reinterpret_cast<const float4 *>(ba)[node];
@@ -503,8 +499,8 @@ struct SphSum {
   int jn[kSphJobs];
   double jta[kSphJobs], jtb[kSphJobs];
 
-  __device__ __forceinline__ void operator()(int node, int, double alpha, double l, double ta,
-                                             int, double tb, int, double spread) {
+  __device__ __forceinline__ void operator()(int node, double alpha, double l, double ta, int,
+                                             double tb, int, double spread) {
     if (!(spread >= 0.0 && spread * l > tau_ref)) {
       tau += alpha * l;
       return;
@@ -606,18 +602,14 @@ struct Scatter {
   double r;
   double inv[3];
   double *abar;
-  double *acc_s, *acc_p;  // LDS, per wave
-  int d_common;           // sink-chain depths <= this are shared by the wave
-  const int32_t *path;    // the walk's current path (LDS) ...
-  int live;               // ... valid at depths <= live
-  int32_t *hk;            // per-wave LDS table of other cells: keys (-1: free) ...
-  double *hv;             // ... and their sums, written out after each round
-  int hmask;              // table slots - 1 (a power of two minus one)
-  // Other cells go to the table (one of two slots picked by two hashes of
-  // the cell), so that few device-memory atomics wait among the trace's
-  // loads; a cell whose two slots hold other cells goes straight to device
-  // memory.  One compare-and-swap per probe claims a free slot or finds the
-  // cell's own.
+  int32_t *hk;  // per-wave LDS table of cells: keys (-1: free) ...
+  double *hv;   // ... and their sums, written out after each round
+  int hmask;    // table slots - 1 (a power of two minus one)
+  // Every piece goes to the table (one of two slots picked by two hashes of
+  // the cell): a round's rays share most of their cells, so the round's
+  // sums reach device memory as about one atomic per distinct cell; a cell
+  // whose two slots hold other cells goes straight to device memory.  One
+  // compare-and-swap per probe claims a free slot or finds the cell's own.
   __device__ __forceinline__ void pool(int node, double v) {
     int sl = (int)((((uint32_t)node * 2654435761u) >> 16) & (uint32_t)hmask);
     int k = -1;  // the slot's key before: free (now ours), this cell, or another
@@ -634,19 +626,9 @@ struct Scatter {
     else
       gbl_add(&abar[node], v);
   }
-  __device__ __forceinline__ void operator()(int node, int slot, double alpha, double l,
-                                             double ta, int ga, double tb, int gb, double) {
-    const double v = -(g * l);
-    if (slot >= kSlotSrc) {  // a source-side cell: pooled while it is on the walk's path
-      const int dd = slot - kSlotSrc;
-      if (dd <= live && path[dd] == node)
-        lds_add(&acc_p[dd], v);
-      else
-        pool(node, v);
-    } else if (slot >= 0 && slot <= d_common)
-      lds_add(&acc_s[slot], v);
-    else
-      pool(node, v);
+  __device__ __forceinline__ void operator()(int node, double alpha, double l, double ta, int ga,
+                                             double tb, int gb, double) {
+    pool(node, -(g * l));
 
     const double xb = alpha * tb, xa = alpha * ta;
     u[0] += (ga == 0 ? xa : 0.0) - (gb == 0 ? xb : 0.0);
@@ -671,7 +653,7 @@ struct Scatter {
 // the light form is the faster one in the adjoint kernel (both passes), the
 // branching form in the forward kernel.
 template <typename T, typename Emit>
-__device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, T ta,
+__device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, T ta,
                                int ga, T tb, int gb, RayCtx<T> &c, StackSpill<T> &ovf, int sp0,
                                int base, Emit &emit) {
   int sp = sp0;
@@ -689,7 +671,7 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
     int ncur = cur;
     if (!split_it) {
       if constexpr (Emit::kCount) c.n_seg += l > 0;
-      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, (double)l, (double)cta, cga,
+      emit(cur, (double)rec.alpha, (double)l, (double)cta, cga,
            (double)ctb, cgb, right == 0 ? (double)rec.dalpha : -1.0);
       go = sp > base;
       if constexpr (Emit::kVar) go = go && !emit.stop();
@@ -738,7 +720,7 @@ __device__ void refine_branchy(const TraceRecT<T> *__restrict__ TR, int X, int t
   } while (go);
 }
 template <typename T, typename Emit>
-__device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top_slot, T ta,
+__device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, T ta,
                              int ga, T tb, int gb, RayCtx<T> &c, StackSpill<T> &ovf, int sp0,
                              int base, Emit &emit) {
   int sp = sp0;
@@ -828,7 +810,7 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
     raw = tr_fetch(TR, done ? cur : ncur);
     if (!split_it) {
       if constexpr (Emit::kCount) c.n_seg += l > 0;
-      emit(cur, cur == X ? top_slot : -1, (double)rec.alpha, (double)l, (double)cta, cga,
+      emit(cur, (double)rec.alpha, (double)l, (double)cta, cga,
            (double)ctb, cgb, right == 0 ? (double)rec.dalpha : -1.0);
     }
     if (done) return;  // no entry left
@@ -840,13 +822,13 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, int top
   }
 }
 template <typename T, typename Emit>
-__device__ __forceinline__ void refine(const TraceRecT<T> *__restrict__ TR, int X, int top_slot,
-                                       T ta, int ga, T tb, int gb, RayCtx<T> &c,
+__device__ __forceinline__ void refine(const TraceRecT<T> *__restrict__ TR, int X, T ta, int ga,
+                                       T tb, int gb, RayCtx<T> &c,
                                        StackSpill<T> &ovf, int sp0, int base, Emit &emit) {
   if constexpr (Emit::kLight)
-    refine_light<T>(TR, X, top_slot, ta, ga, tb, gb, c, ovf, sp0, base, emit);
+    refine_light<T>(TR, X, ta, ga, tb, gb, c, ovf, sp0, base, emit);
   else
-    refine_branchy<T>(TR, X, top_slot, ta, ga, tb, gb, c, ovf, sp0, base, emit);
+    refine_branchy<T>(TR, X, ta, ga, tb, gb, c, ovf, sp0, base, emit);
 }
 // A piece of the ray in chain cell P but outside P's child on the path: P's
 // own average, or, if P fails the refinement test, the sibling X to be
@@ -854,8 +836,8 @@ __device__ __forceinline__ void refine(const TraceRecT<T> *__restrict__ TR, int 
 // that all of a ray's refinement runs in one loop after its chains.
 template <typename T, typename Emit>
 __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
-                                            const TraceRecT<T> &rP, int P, int slot, int X, T ta,
-                                            int ga, T tb, int gb, RayCtx<T> &c,
+                                            const TraceRecT<T> &rP, int P, int X, T ta, int ga,
+                                            T tb, int gb, RayCtx<T> &c,
                                             StackSpill<T> &ovf, int &sp, Emit &emit) {
   const T l = c.r * (tb - ta);
   if constexpr (Emit::kCount) c.n_trace++;
@@ -864,12 +846,12 @@ __device__ __forceinline__ void chain_piece(const TraceRecT<T> *__restrict__ TR,
       stack_push(c, ovf, sp++, X, Emit::kTags ? gb : -1, tb);
       stack_push(c, ovf, sp++, kMark, Emit::kTags ? ga : -1, ta);
     } else {
-      refine<T>(TR, X, -1, ta, ga, tb, gb, c, ovf, sp, sp, emit);
+      refine<T>(TR, X, ta, ga, tb, gb, c, ovf, sp, sp, emit);
     }
     return;
   }
   if constexpr (Emit::kCount) c.n_seg += l > 0;
-  emit(P, slot, (double)rP.alpha, (double)l, (double)ta, ga, (double)tb, gb, -1.0);
+  emit(P, (double)rP.alpha, (double)l, (double)ta, ga, (double)tb, gb, -1.0);
 }
 
 // The sink's bucket and where its ancestors are kept: depths <= dpre are
@@ -929,7 +911,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     if constexpr (Emit::kCount) c.n_trace++;
     const T l = c.r * (T(1) - T(0));
     if constexpr (Emit::kCount) c.n_seg += l > 0;
-    emit(sk.S, sk.depthS, sk.alphaS, (double)l, 0.0, -1, 1.0, -1, sk.spreadS);
+    emit(sk.S, sk.alphaS, (double)l, 0.0, -1, 1.0, -1, sk.spreadS);
     return;
   }
   StackSpill<T> ovf;
@@ -938,7 +920,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   const int A = sink_anc<T>(a.TR, sk, ad);
   if constexpr (Emit::kVar) {
     if (a.ray_mode == 1) {  // top down: the meeting cell holds the whole ray
-      refine<T>(a.TR, A, -1, T(0), -1, T(1), -1, c, ovf, 0, 0, emit);
+      refine<T>(a.TR, A, T(0), -1, T(1), -1, c, ovf, 0, 0, emit);
       return;
     }
   }
@@ -1002,7 +984,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     }
     if (tc < tP) {
       const int sib = b ? P + 1 : rax_right(rP.right_ax);
-      chain_piece<T>(a.TR, rP, P, dd, sib, tc, gc, tP, gP, c, ovf, sp, emit);
+      chain_piece<T>(a.TR, rP, P, sib, tc, gc, tP, gP, c, ovf, sp, emit);
       tP = tc;
       gP = gc;
     }
@@ -1011,7 +993,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     if constexpr (Emit::kCount) c.n_trace++;
     const T l = c.r * (tP - T(0));
     if constexpr (Emit::kCount) c.n_seg += l > 0;
-    emit(sk.S, sk.depthS, sk.alphaS, (double)l, 0.0, -1, (double)tP, gP, sk.spreadS);
+    emit(sk.S, sk.alphaS, (double)l, 0.0, -1, (double)tP, gP, sk.spreadS);
   }
   // source side, [tQ, 1]: C's ancestors below A are found walking down from
   // A along C's path bits.  A lower child is the next cell in depth-first
@@ -1041,7 +1023,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
       }
       if (tc > tQ) {
         const int sib = b ? Q + 1 : rax_right(rQ.right_ax);
-        chain_piece<T>(a.TR, rQ, Q, kSlotSrc + dd, sib, tQ, gQ, tc, gc, c, ovf, sp, emit);
+        chain_piece<T>(a.TR, rQ, Q, sib, tQ, gQ, tc, gc, c, ovf, sp, emit);
         tQ = tc;
         gQ = gc;
       }
@@ -1051,7 +1033,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
   }
   if constexpr (Emit::kVar)
     if (emit.stop()) return;
-  int X0 = C, slot0 = kSlotSrc + depthC, ga0 = gQ, gb0 = -1;
+  int X0 = C, ga0 = gQ, gb0 = -1;
   T ta0 = tQ, tb0 = T(1);
   if (!(T(1) > tQ)) {
     // The source point lies on the meeting cell's plane, so C's interval is
@@ -1066,7 +1048,7 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
       if constexpr (Emit::kCount) c.n_trace++;
       const int right = rax_right(rX.right_ax);
       if (!((right != 0) & ((double)rX.dalpha * 0.0 > c.tau_ref))) {
-        emit(X, X == C ? slot0 : -1, (double)rX.alpha, 0.0, (double)tQ, gQ, 1.0, -1,
+        emit(X, (double)rX.alpha, 0.0, (double)tQ, gQ, 1.0, -1,
              right == 0 ? (double)rX.dalpha : -1.0);
         break;
       }
@@ -1078,9 +1060,8 @@ __device__ void trace_pieces(const FluxArgs<T> &a, int C, uint64_t keyC, int dep
     int mark;
     stack_pop(c, ovf, --sp, mark, ga0, ta0);  // the job's marker: its entry
     stack_pop(c, ovf, --sp, X0, gb0, tb0);    // its cell and exit
-    slot0 = -1;
   }
-  refine<T>(a.TR, X0, slot0, ta0, ga0, tb0, gb0, c, ovf, sp, 0, emit);
+  refine<T>(a.TR, X0, ta0, ga0, tb0, gb0, c, ovf, sp, 0, emit);
 }
 
 __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
@@ -1100,45 +1081,56 @@ __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
   return -1;
 }
 
-// LDS per wave, binary64 items first: open masks (64 x u64), the adjoint's
-// two accumulator rows (64 x f64 each), the refinement stacks (kr x 64 lanes x
-// (f64 + i32)), the ray queue (kQueue x (i32 + u8)), the per-sink counts of
-// traced pieces and steps (2 x 64 x i32, forward only), the sink-ancestor
-// windows (ks x 64 lanes x i32), the walk path and the shared sink-chain
-// prefix (64 x i32 each).
+// LDS per wave, 8-byte items first: open masks (64 x u64), the adjoint's
+// table (hn x (f64 + i32)), the refinement stacks (kr entries x 64 lanes; an
+// entry is 8 bytes for binary32, f64 + i32 for binary64), the ray queue
+// (kQueue x (i32 + u8)), the per-sink counts of traced pieces and steps
+// (2 x 64 x i32, forward only), the sink-ancestor windows (ks x 64 lanes x
+// i32) and the shared sink-chain prefix (64 x i32).
 constexpr int kQueue = 128;  // ray queue slots per wave (a power of two)
-template <bool ADJ>
+template <bool ADJ, typename T>
 __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
-  return (size_t)64 * 8 + (ADJ ? 2 * 64 * 8 + (size_t)hn * 12 : 0) + (size_t)kr * 64 * 12 +
-         kQueue * 5 + (ADJ ? 0 : 2 * 64 * 4) + (size_t)ks * 64 * 4 + 2 * 64 * 4;
+  return (size_t)64 * 8 + (ADJ ? (size_t)hn * 12 : 0) +
+         (size_t)kr * 64 * (sizeof(T) == 4 ? 8 : 12) + kQueue * 5 + (ADJ ? 0 : 2 * 64 * 4) +
+         (size_t)ks * 64 * 4 + 64 * 4;
 }
 
-// Window and stack depth per occupancy variant (waves per SIMD), chosen so
-// that that many waves fit the CU's 160 KiB of LDS.
+// Window depth, stack entries and table slots per occupancy variant (waves
+// per SIMD), chosen so that that many waves fit the CU's 160 KiB of LDS.  The
+// adjoint spends its LDS on the table first: a round's rays touch about 175
+// distinct cells at the headline workload, and a table much under that
+// sends most pieces to device-memory atomics.
 __host__ __device__ constexpr int occ_ks(int wps, bool adj) {
   return wps <= 3 ? (adj ? 2 : 14)
-                  : wps == 4 ? (adj ? 5 : 7)
+                  : wps == 4 ? (adj ? 3 : 7)
                              : wps == 5 ? (adj ? 3 : 5) : wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
 }
-__host__ __device__ constexpr int occ_kr(int wps, bool adj) {
-  return wps <= 3 ? (adj ? 11 : 10)
-                  : wps == 4 ? (adj ? 6 : 8)
-                             : wps == 5 ? (adj ? 5 : 6) : wps <= 7 ? (adj ? 3 : 5) : (adj ? 1 : 3);
+__host__ __device__ constexpr int occ_kr(int wps, bool adj, bool f32) {
+  return f32 ? (wps <= 3 ? (adj ? 16 : 15)
+                         : wps == 4 ? 12 : wps == 5 ? (adj ? 8 : 9) : wps <= 7 ? 7 : 4)
+             : (wps <= 3 ? (adj ? 11 : 10)
+                         : wps == 4 ? 8 : wps == 5 ? (adj ? 5 : 6) : wps <= 7 ? (adj ? 4 : 5)
+                                                                              : (adj ? 2 : 3));
 }
 // adjoint: slots of the per-wave table of d loss / d alpha (a power of two)
 __host__ __device__ constexpr int occ_hn(int wps, bool adj) {
-  return !adj ? 0 : wps <= 3 ? 128 : wps == 4 ? 128 : 64;
+  return !adj ? 0 : wps <= 3 ? 256 : wps <= 5 ? 128 : 64;
 }
-template <bool ADJ>
+template <bool ADJ, typename T>
 __host__ __device__ constexpr size_t occ_lds(int wps) {
-  return lds_per_wave<ADJ>(occ_ks(wps, ADJ), occ_kr(wps, ADJ), occ_hn(wps, ADJ));
+  return lds_per_wave<ADJ, T>(occ_ks(wps, ADJ), occ_kr(wps, ADJ, sizeof(T) == 4),
+                              occ_hn(wps, ADJ));
 }
 constexpr size_t kLdsPerCu = 160 * 1024;
-static_assert(occ_lds<false>(3) * 12 <= kLdsPerCu && occ_lds<true>(3) * 12 <= kLdsPerCu, "");
-static_assert(occ_lds<false>(4) * 16 <= kLdsPerCu && occ_lds<true>(4) * 16 <= kLdsPerCu, "");
-static_assert(occ_lds<false>(5) * 20 <= kLdsPerCu && occ_lds<true>(5) * 20 <= kLdsPerCu, "");
-static_assert(occ_lds<false>(6) * 24 <= kLdsPerCu && occ_lds<true>(6) * 24 <= kLdsPerCu, "");
-static_assert(occ_lds<false>(8) * 32 <= kLdsPerCu && occ_lds<true>(8) * 32 <= kLdsPerCu, "");
+template <typename T>
+constexpr bool occ_fits(int wps) {
+  return occ_lds<false, T>(wps) * 4 * wps <= kLdsPerCu &&
+         occ_lds<true, T>(wps) * 4 * wps <= kLdsPerCu;
+}
+static_assert(occ_fits<float>(3) && occ_fits<float>(4) && occ_fits<float>(5) &&
+                  occ_fits<float>(6) && occ_fits<float>(8), "");
+static_assert(occ_fits<double>(3) && occ_fits<double>(4) && occ_fits<double>(5) &&
+                  occ_fits<double>(6) && occ_fits<double>(8), "");
 
 constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source, not a cell
 
@@ -1159,31 +1151,26 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const uint64_t below = (1ull << lane) - 1;  // the lanes below this one
-  unsigned char *base = smem + wv * lds_per_wave<ADJ>(KS, KR, HN);
+  unsigned char *base = smem + wv * lds_per_wave<ADJ, T>(KS, KR, HN);
   uint64_t *s_open = reinterpret_cast<uint64_t *>(base);
   base += 64 * 8;
-  double *acc_s = reinterpret_cast<double *>(base);
-  double *acc_p = acc_s + 64;
-  double *s_hv = acc_p + 64;  // adjoint table: sums, then keys
-  if (ADJ) base += 2 * 64 * 8 + HN * 8;
+  double *s_hv = reinterpret_cast<double *>(base);  // adjoint table: sums, then keys
+  if (ADJ) base += HN * 8;
   int32_t *s_hk = reinterpret_cast<int32_t *>(base);
   if (ADJ) base += HN * 4;
-  double *s_stb = reinterpret_cast<double *>(base);
+  double *s_stb = reinterpret_cast<double *>(base);  // the stack: 8-byte entries or t ...
   base += KR * 64 * 8;
-  int32_t *s_stn = reinterpret_cast<int32_t *>(base);
-  base += KR * 64 * 4;
+  int32_t *s_stn = reinterpret_cast<int32_t *>(base);  // ... and cells (binary64)
+  if (sizeof(T) == 8) base += KR * 64 * 4;
   lds_i32 *s_qe = (lds_i32 *)reinterpret_cast<int32_t *>(base);  // entry: cell or particle
   base += kQueue * 4;
   int32_t *s_cnt = reinterpret_cast<int32_t *>(base);  // forward: pieces, steps per sink
   if (!ADJ) base += 2 * 64 * 4;
   int32_t *s_anc = reinterpret_cast<int32_t *>(base);
   base += KS * 64 * 4;
-  int32_t *s_path = reinterpret_cast<int32_t *>(base);
-  int32_t *s_pre = s_path + 64;
+  int32_t *s_pre = reinterpret_cast<int32_t *>(base);
   uint8_t *s_qo = reinterpret_cast<uint8_t *>(s_pre + 64);  // entry's owning lane
   if (ADJ) {
-    acc_s[lane] = 0.0;
-    acc_p[lane] = 0.0;
     for (int j = lane; j < HN; j += 64) {
       s_hk[j] = -1;
       s_hv[j] = 0.0;
@@ -1191,12 +1178,10 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   }
   RayCtx<T> c;
   c.tau_ref = a.tau_ref;
-  // the stack's LDS (KR x 64 x 12 bytes): binary32 entries are 8 bytes, so
-  // half as many again fit
   c.stn = s_stn + lane;
   c.stb = s_stb + lane;
   c.st = reinterpret_cast<uint64_t *>(s_stb) + lane;
-  c.kr = sizeof(T) == 4 ? KR * 3 / 2 : KR;
+  c.kr = KR;
   // a replay needs every block of the recording
   const bool replay = ADJ && a.tape_mode == 2 && *a.tape_ctr <= a.tape_cap;
   int chunk = -1, sub = a.group;
@@ -1298,7 +1283,6 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     double FB[kMaxBands] = {0.0, 0.0, 0.0, 0.0};      // flux per band (NBND > 0)
     int n_open = 0, n_rays = 0, n_psrc = 0;
     int qh = 0, qn = 0;  // the queue: first entry, entries (wave-uniform)
-    int live = -1;       // the walk's path is s_path[0 .. live]
     int tprev = -1;      // recording: the set's last block
     int tpre = 0;        // recording: lane 0's block for the next round, taken ahead
     bool tpre_ok = false;
@@ -1483,11 +1467,6 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           sc.inv[1] = (double)c.inv[1];
           sc.inv[2] = (double)c.inv[2];
           sc.abar = a.abar;
-          sc.acc_s = acc_s;
-          sc.acc_p = acc_p;
-          sc.d_common = d_common;
-          sc.path = s_path;
-          sc.live = live;
           sc.hk = s_hk;
           sc.hv = s_hv;
           sc.hmask = HN - 1;
@@ -1671,26 +1650,12 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       pending &= ~group;
       const int end = a.W[root].skip;
       int n = root;
-      int depth_prev = 0;
       uint64_t active = group;
       bool from_skip = false;
-      s_path[0] = root;
       for (;;) {
         const WalkRecT<T> w = a.W[n];
         const int depth = w.depth;
-        if (from_skip) {
-          if (ADJ && lane == 0) {  // the path cells at depths >= depth are done
-            for (int dd = depth; dd <= depth_prev; ++dd) {
-              const double v = acc_p[dd];
-              if (v != 0.0) gbl_add(&a.abar[s_path[dd]], v);
-              acc_p[dd] = 0.0;
-            }
-          }
-          active = s_open[depth - 1];
-          s_path[depth] = n;
-        }
-        depth_prev = depth;
-        live = depth;
+        if (from_skip) active = s_open[depth - 1];
         const bool mine = (active >> lane) & 1;
         uint64_t openm = 0;
         if (w.L != (T)0) {
@@ -1761,7 +1726,6 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           s_open[depth] = openm;
           active = openm;
           n = n + 1;
-          s_path[depth + 1] = n;
           from_skip = false;
           continue;
         }
@@ -1769,26 +1733,9 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         if (n >= end) break;
         from_skip = true;
       }
-      // the rest of this box's rays, while its last path is still valid
-      while (qn > 0) round();
-      live = -1;
-      if (ADJ && lane == 0) {
-        for (int dd = 0; dd <= depth_prev; ++dd) {
-          const double v = acc_p[dd];
-          if (v != 0.0) gbl_add(&a.abar[s_path[dd]], v);
-          acc_p[dd] = 0.0;
-        }
-      }
+      while (qn > 0) round();  // the rest of this box's rays
     }
-    if (ADJ) {
-      if (lane == lead0) {
-        for (int dd = 0; dd <= d_common; ++dd) {
-          const double v = acc_s[dd];
-          if (v != 0.0) gbl_add(&a.abar[s_pre[dd]], v);
-          acc_s[dd] = 0.0;
-        }
-      }
-    } else {
+    if (!ADJ) {
       wave_sync();
       if (in_list) {
         const int64_t out = a.sinks ? q : (int64_t)a.perm[k];
@@ -1822,58 +1769,67 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ), occ_hn(3, ADJ), 0, 0, 0, 0, CNT>(a);
+  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ, sizeof(T) == 4), occ_hn(3, ADJ),
+            0, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ), occ_hn(4, ADJ), 0, 0, 0, 0, CNT>(a);
+  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ, sizeof(T) == 4), occ_hn(4, ADJ),
+            0, 0, 0, 0, CNT>(a);
 }
 // The flux with the vector flux, at the 4-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4v(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(4, false), occ_kr(4, false), occ_hn(4, false), 1, 0, 0, 0, CNT>(a);
+  walk_body<T, false, occ_ks(4, false), occ_kr(4, false, sizeof(T) == 4), occ_hn(4, false),
+            1, 0, 0, 0, CNT>(a);
 }
 // The flux per opacity band, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3b(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, kMaxBands, 0, 0,
-            CNT>(a);
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4), occ_hn(3, false),
+            0, kMaxBands, 0, 0, CNT>(a);
 }
 // The flux with the walk variants, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3x(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, 0, 0, 1, CNT>(a);
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4), occ_hn(3, false),
+            0, 0, 0, 1, CNT>(a);
 }
 // The flux with the sub-bucket particle trace, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3s(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 0, 0, 1, 0, CNT>(a);
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4), occ_hn(3, false),
+            0, 0, 1, 0, CNT>(a);
 }
 // The flux with the vector flux and the second moment, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3m(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false), occ_hn(3, false), 2, 0, 0, 0, CNT>(a);
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4), occ_hn(3, false),
+            2, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ), occ_hn(5, ADJ), 0, 0, 0, 0, CNT>(a);
+  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ, sizeof(T) == 4), occ_hn(5, ADJ),
+            0, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_walk6(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ), occ_hn(6, ADJ), 0, 0, 0, 0, CNT>(a);
+  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ, sizeof(T) == 4), occ_hn(6, ADJ),
+            0, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_walk8(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ), occ_hn(8, ADJ), 0, 0, 0, 0, CNT>(a);
+  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ, sizeof(T) == 4), occ_hn(8, ADJ),
+            0, 0, 0, 0, CNT>(a);
 }
 
 __global__ void k_zero_i32(int32_t *p, int n) {
@@ -1994,9 +1950,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3b<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+        k_walk3b<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
       else
-        k_walk3b<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+        k_walk3b<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -2005,9 +1961,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3x<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+        k_walk3x<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
       else
-        k_walk3x<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+        k_walk3x<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -2016,9 +1972,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3s<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+        k_walk3s<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
       else
-        k_walk3s<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+        k_walk3s<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -2027,9 +1983,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3m<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+        k_walk3m<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
       else
-        k_walk3m<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(3), s>>>(a);
+        k_walk3m<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -2038,9 +1994,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk4v<T, true><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(4), s>>>(a);
+        k_walk4v<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(4), s>>>(a);
       else
-        k_walk4v<T, false><<<(unsigned)vb, threads, (size_t)waves * occ_lds<false>(4), s>>>(a);
+        k_walk4v<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(4), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -2048,7 +2004,7 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   const int per_simd = (L.blocks_per_cu * waves + 3) / 4;
   const int wps = per_simd >= 8 ? 8 : per_simd >= 6 ? 6 : per_simd == 5 ? 5 : per_simd == 4 ? 4 : 3;
   // waves per workgroup <= 4 x wps, so the workgroup fits the CU's LDS
-  const size_t shmem = (size_t)waves * occ_lds<ADJ>(wps);
+  const size_t shmem = (size_t)waves * occ_lds<ADJ, T>(wps);
   if (shmem > kLdsPerCu) return fail(TREVR_E_ARG, "launch shape needs more LDS than a CU has");
   // per-sink counters only when asked for (the adjoint never keeps them)
   if (!ADJ && a.counters) {
