@@ -572,18 +572,100 @@ DEFAULT_CANDIDATES = tuple((bpc, wpb, chunk)
                            for chunk in (64, 128, 256)
                            if 2 <= bpc * wpb <= 16)
 
+# Bumped when the candidate space or the meaning of a stored record changes.
+_TUNE_FORMAT = 2
+
+
+def tune_cache_path():
+    """The JSON file that keeps autotuning results across processes:
+    $TREVR_TUNE_CACHE, else ~/.cache/trevr/autotune.json."""
+    return os.environ.get("TREVR_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "trevr", "autotune.json")
+
+
+_LIB_DIGEST = None
+
+
+def _lib_digest():
+    """SHA-256 (first 16 hex digits) of the loaded library file: a rebuilt
+    kernel invalidates the stored launch shapes."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        import hashlib
+        h = hashlib.sha256()
+        with open(LIB_PATH, "rb") as f:
+            for block in iter(lambda: f.read(1 << 20), b""):
+                h.update(block)
+        _LIB_DIGEST = h.hexdigest()[:16]
+    return _LIB_DIGEST
+
+
+def tune_key(info, theta_open, tau_ref, n_sinks, device_name, lib_digest):
+    """The cache key of one tuning: the tree's shape (particles, cells, boxes,
+    depth, value type), the walk parameters, the sink count, the GPU and the
+    library build."""
+    return "|".join([
+        "v%d" % _TUNE_FORMAT, str(device_name), str(lib_digest),
+        "n=%d" % info["n"], "m=%d" % info["m"], "boxes=%d" % info["n_boxes"],
+        "depth=%d" % info["max_depth"], "prec=%s" % info["prec"],
+        "theta=%r" % float(theta_open), "tau_ref=%r" % float(tau_ref),
+        "sinks=%s" % ("all" if n_sinks is None else int(n_sinks))])
+
+
+def tune_cache_load(path):
+    """The stored tunings ({} if the file is missing or unreadable)."""
+    import json
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    if not isinstance(d, dict) or d.get("format") != _TUNE_FORMAT:
+        return {}
+    e = d.get("entries")
+    return e if isinstance(e, dict) else {}
+
+
+def tune_cache_store(path, key, record):
+    """Add one tuning to the file: read, merge, write a temporary file and
+    rename it over the old one (a concurrent writer loses at most its own
+    entry, never the file)."""
+    import json
+    entries = tune_cache_load(path)
+    entries[key] = record
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    tmp = "%s.tmp%d" % (path, os.getpid())
+    with open(tmp, "w") as f:
+        json.dump({"format": _TUNE_FORMAT, "entries": entries}, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
 
 def autotune(tree, theta_open, tau_ref, sinks=None, candidates=DEFAULT_CANDIDATES, reps=3,
-             key=None):
+             key=None, cache_path=None, persist=True):
     """Time the flux launch under each (workgroups per CU, waves per
     workgroup, sinks per queue grab) candidate and keep the fastest on the
-    tree.  Results are cached per `key` (default: tree shape and parameters)."""
+    tree.  The shape also picks the kernel's occupancy variant, and with it
+    how the LDS is split between the per-lane refinement stack, the
+    sink-ancestor window and the queue.  Results are cached in memory and,
+    with `persist`, in the JSON file `cache_path` (default tune_cache_path()),
+    keyed by tune_key(); a hit sets the stored shape without timing
+    anything.  Returns {"launch", "ms", "table", "source"}."""
     import numpy as np
     info = tree.info()
-    key = key or (info["n"], info["m"], info["n_boxes"], info["prec"], float(theta_open),
-                  float(tau_ref), None if sinks is None else int(len(sinks)))
-    if key in _TUNE_CACHE:
-        best = _TUNE_CACHE[key]
+    if key is None:
+        key = tune_key(info, theta_open, tau_ref, None if sinks is None else len(sinks),
+                       torch.cuda.get_device_name(tree.device), _lib_digest())
+    path = cache_path or tune_cache_path()
+    best = _TUNE_CACHE.get(key)
+    if best is None and persist:
+        rec = tune_cache_load(path).get(key)
+        if rec is not None and tuple(rec.get("launch", ())) in {tuple(c) for c in candidates}:
+            best = {"launch": tuple(rec["launch"]), "ms": float(rec["ms"]),
+                    "table": [(float(t), tuple(c)) for t, c in rec.get("table", [])],
+                    "source": "file"}
+            _TUNE_CACHE[key] = best
+    if best is not None:
         tree.set_launch(*best["launch"])
         return best
     s, ns = tree._sinks(sinks)
@@ -602,11 +684,18 @@ def autotune(tree, theta_open, tau_ref, sinks=None, candidates=DEFAULT_CANDIDATE
             e1.record(st)
             e1.synchronize()
             ms.append(e0.elapsed_time(e1))
-        table.append((float(np.median(ms)), cand))
+        table.append((float(np.median(ms)), tuple(cand)))
     table.sort()
-    best = {"launch": table[0][1], "ms": table[0][0], "table": table}
+    best = {"launch": table[0][1], "ms": table[0][0], "table": table, "source": "timed"}
     tree.set_launch(*best["launch"])
     _TUNE_CACHE[key] = best
+    if persist:
+        try:
+            tune_cache_store(path, key, {"launch": list(best["launch"]), "ms": best["ms"],
+                                         "table": [[t, list(c)] for t, c in table]})
+        except OSError as e:  # an unwritable cache costs a re-tune later, nothing else
+            import warnings
+            warnings.warn("autotune: could not write %s: %s" % (path, e))
     return best
 
 
@@ -617,14 +706,15 @@ class BatchedPlan:
     before capture."""
 
     def __init__(self, boxes, theta_open=0.75, tau_ref=0.1, bucket_size=8, device="cuda",
-                 tune=True, candidates=DEFAULT_CANDIDATES):
+                 tune=True, candidates=DEFAULT_CANDIDATES, tune_cache=None, persist_tuning=True):
         pos, rho, kappa, lum, mass, lo, hi, off = _concat_boxes(boxes, device)
         self.offsets = off
         self.theta_open = float(theta_open)
         self.tau_ref = float(tau_ref)
         self.tree = Tree().build(pos, rho, kappa, lum, mass, lo, hi, bucket_size, off, device)
         self.flux = torch.empty(pos.shape[0], dtype=pos.dtype, device=pos.device)
-        self.tuning = (autotune(self.tree, self.theta_open, self.tau_ref, candidates=candidates)
+        self.tuning = (autotune(self.tree, self.theta_open, self.tau_ref, candidates=candidates,
+                                cache_path=tune_cache, persist=persist_tuning)
                        if tune else None)
         self.graph = None
 

@@ -21,3 +21,15 @@ def _oracle_built():
     from oracle import oracle as o
     o.build_library()
     yield
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _private_tune_cache(tmp_path_factory):
+    """Autotuning results of the test session go to a file of its own."""
+    old = os.environ.get("TREVR_TUNE_CACHE")
+    os.environ["TREVR_TUNE_CACHE"] = str(tmp_path_factory.mktemp("tune") / "autotune.json")
+    yield
+    if old is None:
+        os.environ.pop("TREVR_TUNE_CACHE", None)
+    else:
+        os.environ["TREVR_TUNE_CACHE"] = old

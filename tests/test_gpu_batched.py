@@ -60,3 +60,30 @@ def test_autotune_keeps_results_identical():
                  (8, 4, 64), (16, 2, 128)]:
         t.set_launch(*cand)
         assert torch.equal(t.flux(0.75, 0.1), ref), cand
+
+
+def test_autotune_json_cache(tmp_path):
+    """A tuning is written to the JSON cache, and a later process (here: an
+    emptied in-memory cache) takes the stored launch without timing; a
+    candidate list without the stored launch tunes again."""
+    w = W._pack("tunecache", *W.lognormal_box(1 << 13, 0, 10.0, 5, all_sources=True), prec="f32")
+    t = P.build_tree(*[torch.as_tensor(w[k], device="cuda") for k in
+                       ("pos", "rho", "kappa", "lum", "mass")])
+    path = str(tmp_path / "tune.json")
+    cands = [(1, 1, 64), (2, 4, 128), (4, 4, 64)]
+    first = P.autotune(t, 0.75, 0.1, candidates=cands, reps=1, cache_path=path)
+    assert first["source"] == "timed"
+    stored = P.trevr.tune_cache_load(path)
+    assert len(stored) == 1
+    (key, rec), = stored.items()
+    assert tuple(rec["launch"]) == tuple(first["launch"]) and len(rec["table"]) == 3
+    P.trevr._TUNE_CACHE.clear()
+    t.set_launch(1, 1, 64)
+    again = P.autotune(t, 0.75, 0.1, candidates=cands, reps=1, cache_path=path)
+    assert again["source"] == "file" and tuple(again["launch"]) == tuple(first["launch"])
+    lo = t.get_launch()
+    assert (lo["blocks_per_cu"], lo["waves_per_block"], lo["chunk"]) == tuple(first["launch"])
+    P.trevr._TUNE_CACHE.clear()
+    other = [c for c in [(3, 4, 64), (2, 2, 64)] if c != tuple(first["launch"])]
+    third = P.autotune(t, 0.75, 0.1, candidates=other, reps=1, cache_path=path)
+    assert third["source"] == "timed" and tuple(third["launch"]) in other
