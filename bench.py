@@ -85,6 +85,33 @@ def counters_run(P, tree, w):
     return P.sum_counters(C).cpu().numpy()
 
 
+def paper_context(torch, P):
+    """Context only: mean rays and pieces per gas particle on the paper's test
+    set as the workloads module stands it in (64^3 gas + 64^3 stars, 24
+    modes; Sec. 3.1.1, App. A), theta 0.75, tau_ref 0.1, beside the paper's
+    figures (about 200 rays, Sec. 3.1.2; about 850 segments, Sec. 3.1.3).
+    The paper does not state the bucket size of that test: the counts are
+    given at N_B = 8 (the workloads' value) and at 16 and 32."""
+    from paper_1902_08083_amd import workloads as W
+    w = W.ctx_lattice()
+    n = w["n_gas"]
+    pos, rho, kappa, lum, mass = to_dev(w, torch)
+    sinks = torch.arange(n, dtype=torch.int32, device="cuda")
+    by_nb = {}
+    for nb in (8, 16, 32):
+        t = P.build_tree(pos, rho, kappa, lum, mass, w["box_lo"], w["box_hi"], nb)
+        _, C = t.flux(w["theta"], w["tau_ref"], sinks=sinks, counters=True)
+        tot = P.sum_counters(C).cpu().numpy().astype(np.float64)
+        by_nb[str(nb)] = {"rays_per_element": tot[1] / n,
+                          "single_particle_rays_per_element": tot[2] / n,
+                          "segments_per_element": tot[3] / n}
+    out = {"workload": w["name"], "elements": n}
+    out.update(by_nb["8"])
+    out.update({"by_bucket_size": by_nb,
+                "paper": {"rays_per_element": 200, "segments_per_element": 850},
+                "note": "context, not parity: jittered lattice for the paper's glass"})
+    return out
+
 def vector_flux(torch, tree, w, reps=3):
     """The flux with the net (vector) flux, and with the vector flux and the
     second moment (radiation pressure tensor times c), on the headline tree:
@@ -544,6 +571,9 @@ def main():
         out["background_shell"] = background_shell(torch, P)
         log("ionisation equilibrium (Stromgren) at 64^3")
         out["stromgren"] = stromgren_run(torch, P)
+    if not args.no_vector:
+        log("paper-context counters (64^3 gas + 64^3 stars)")
+        out["paper_context"] = paper_context(torch, P)
     if not args.no_adjoint:
         log("adjoint ratio on the 2^20 workload")
         out["adjoint"] = adjoint_ratio(torch, P)

@@ -159,3 +159,79 @@ def c5(seed=5, target_seed=55, n=1 << 20):
 def scaled(w_fn, n, **kw):
     """A smaller instance of a configuration's recipe (parity tests)."""
     return w_fn(n=n, **kw)
+
+
+# Table tab:modes (App. A): wave vector (k_x, k_y, k_z) and phase phi of the
+# 24 sinusoidal modes of eq. manfft.
+TAB_MODES = np.array([
+    [-3.918398, +1.727743, -4.476095, 0.829776],  # 01
+    [-3.681821, -4.619688, +4.865007, 3.891157],  # 02
+    [-4.831801, +3.769470, +0.567451, 3.668730],  # 03
+    [-2.298279, +1.501757, +4.716946, 1.528348],  # 04
+    [-0.289974, -3.097958, +1.270028, 4.113001],  # 05
+    [+1.262943, -1.661726, -2.600413, 4.481799],  # 06
+    [+1.588224, +4.072259, +0.616444, 2.971965],  # 07
+    [-2.253394, -2.806478, +2.749155, 0.442241],  # 08
+    [-1.432569, +3.324710, +4.842991, 2.871989],  # 09
+    [+1.287742, -4.575517, -4.001723, 1.727810],  # 10
+    [+4.769704, +0.540096, -4.203839, 5.872117],  # 11
+    [-3.013200, -1.871251, -2.514416, 1.574008],  # 12
+    [-4.588620, +4.384224, +1.246849, 1.985715],  # 13
+    [-0.372817, +0.195243, +4.074056, 6.248739],  # 14
+    [-1.842232, +0.901598, -4.453613, 6.273336],  # 15
+    [+1.986937, -1.037650, +1.958888, 2.177783],  # 16
+    [-1.748485, -1.386029, +3.755833, 0.532604],  # 17
+    [+4.852406, -3.272506, +0.826504, 5.525470],  # 18
+    [+3.663293, -4.597598, -0.890135, 4.528870],  # 19
+    [-1.720903, +2.726011, +3.192427, 3.875610],  # 20
+    [+4.973332, +4.777182, -2.515792, 0.406737],  # 21
+    [+0.057238, -2.972427, -1.828550, 4.125258],  # 22
+    [+0.938234, -0.487023, -2.755097, 1.335299],  # 23
+    [+1.943361, +0.388178, -3.783953, 4.774938],  # 24
+])
+MODE_AMPLITUDE = 1.0 / 275.0
+
+
+def perturb_modes(r0):
+    """eq. manfft, read as printed: every coordinate of a particle moves by the
+    same scalar, sum_i A sin(k_i . r0 + phi_i) with A = 1/275, evaluated at
+    the unperturbed position.  Returns the moved positions and the Jacobian
+    determinant of the map, det(I + 1 grad f) = 1 + sum_i A (k_x + k_y +
+    k_z)_i cos(k_i . r0 + phi_i), so that rho = rho0 / det."""
+    ph = r0 @ TAB_MODES[:, :3].T + TAB_MODES[:, 3]
+    f = MODE_AMPLITUDE * np.sin(ph).sum(axis=1)
+    det = 1.0 + MODE_AMPLITUDE * (np.cos(ph) * TAB_MODES[:, :3].sum(axis=1)).sum(axis=1)
+    return r0 + f[:, None], det
+
+
+def ctx_lattice(n_side=64, jitter=0.25, seed=61, prec="f32"):
+    """Paper-context workload (Sec. 3.1.1, App. A): N gas and N star
+    particles, N = n_side^3.  The 16^3 glass the paper tiles is replaced by a
+    lattice of cell centres with a seeded uniform jitter of +-jitter spacings
+    per coordinate; the stars take the glass with coordinates reassigned
+    (x, y, z)_star = (y, z, x)_gas; both are then moved by the 24 modes
+    (perturb_modes).  Gas: total mass 1 (m = 1/N), kappa = 1, rho = 1 / det of
+    the map (the exact density of a unit-density medium under it), L = 0.
+    Stars: L = 1, mass 0 (they do not absorb).  Particles [0, N) are gas (the
+    sinks, "resolution elements"), [N, 2N) stars.  The box is [-0.05, 1.05]^3,
+    which holds every moved particle (|f| <= 24/275)."""
+    rng = np.random.default_rng(seed)
+    g = (np.arange(n_side) + 0.5) / n_side
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    glass = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    glass = glass + rng.uniform(-jitter, jitter, glass.shape) / n_side
+    n = glass.shape[0]
+    gas, det = perturb_modes(glass)
+    stars, _ = perturb_modes(glass[:, [1, 2, 0]])
+    pos = np.concatenate([gas, stars])
+    rho = np.concatenate([1.0 / det, np.ones(n)])
+    kappa = np.concatenate([np.ones(n), np.zeros(n)])
+    lum = np.concatenate([np.zeros(n), np.ones(n)])
+    mass = np.concatenate([np.full(n, 1.0 / n), np.zeros(n)])
+    dt = np.float64 if prec == "f64" else np.float32
+    return {"name": "ctx_lattice%d_f%s" % (n_side, "64" if prec == "f64" else "32"),
+            "prec": prec, "pos": pos.astype(dt), "rho": rho.astype(dt),
+            "kappa": kappa.astype(dt), "lum": lum.astype(dt), "mass": mass.astype(dt),
+            "box_lo": (-0.05, -0.05, -0.05), "box_hi": (1.05, 1.05, 1.05), "bucket_size": 8,
+            "theta": 0.75, "tau_ref": 0.1, "n_gas": n, "det_min": float(det.min()),
+            "det_max": float(det.max())}
