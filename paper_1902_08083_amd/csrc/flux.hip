@@ -91,7 +91,8 @@ struct FluxArgs {
   int32_t *tape_head;  // [64-sink sets] the set's first block, -1 if it has none
   int32_t *tape_ctr;   // blocks taken; above tape_cap the tape is incomplete
   int32_t tape_cap;
-  int32_t tape_mode;  // 0 none, 1 record, 2 replay
+  int32_t tape_mode;   // 0 none, 1 record, 2 replay
+  int32_t tape_chunk;  // record: blocks a wave takes from the counter at once
   // adjoint
   const T *__restrict__ grad_flux;
   double *abar;    // [m]  d loss / d alpha
@@ -1085,14 +1086,14 @@ __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
 // table (hn x (f64 + i32)), the refinement stacks (kr entries x 64 lanes; an
 // entry is 8 bytes for binary32, f64 + i32 for binary64), the ray queue
 // (kQueue x (i32 + u8)), the per-sink counts of traced pieces and steps
-// (2 x 64 x i32, forward only), the sink-ancestor windows (ks x 64 lanes x
-// i32) and the shared sink-chain prefix (64 x i32).
+// (2 x 64 x i32, a forward that keeps counters), the sink-ancestor windows
+// (ks x 64 lanes x i32) and the shared sink-chain prefix (64 x i32).
 constexpr int kQueue = 128;  // ray queue slots per wave (a power of two)
-template <bool ADJ, typename T>
+template <bool ADJ, typename T, bool CNT = true>
 __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
   return (size_t)64 * 8 + (ADJ ? (size_t)hn * 12 : 0) +
-         (size_t)kr * 64 * (sizeof(T) == 4 ? 8 : 12) + kQueue * 5 + (ADJ ? 0 : 2 * 64 * 4) +
-         (size_t)ks * 64 * 4 + 64 * 4;
+         (size_t)kr * 64 * (sizeof(T) == 4 ? 8 : 12) + kQueue * 5 +
+         (ADJ || !CNT ? 0 : 2 * 64 * 4) + (size_t)ks * 64 * 4 + 64 * 4;
 }
 
 // Window depth, stack entries and table slots per occupancy variant (waves
@@ -1101,31 +1102,38 @@ __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
 // distinct cells at the headline workload, and a table much under that
 // sends most pieces to device-memory atomics.
 __host__ __device__ constexpr int occ_ks(int wps, bool adj) {
-  return wps <= 3 ? (adj ? 2 : 14)
-                  : wps == 4 ? (adj ? 3 : 7)
-                             : wps == 5 ? (adj ? 3 : 5) : wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
+  if (wps <= 3) return adj ? 3 : 14;
+  if (wps == 4) return adj ? 3 : 4;
+  if (wps == 5) return adj ? 3 : 5;
+  return wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
 }
-__host__ __device__ constexpr int occ_kr(int wps, bool adj, bool f32) {
-  return f32 ? (wps <= 3 ? (adj ? 16 : 15)
-                         : wps == 4 ? 12 : wps == 5 ? (adj ? 8 : 9) : wps <= 7 ? 7 : 4)
-             : (wps <= 3 ? (adj ? 11 : 10)
-                         : wps == 4 ? 8 : wps == 5 ? (adj ? 5 : 6) : wps <= 7 ? (adj ? 4 : 5)
-                                                                              : (adj ? 2 : 3));
+__host__ __device__ constexpr int occ_kr(int wps, bool adj, bool f32, bool cnt) {
+  if (f32) {
+    if (wps <= 3) return adj ? 16 : 15;
+    if (wps == 4) return adj ? 12 : cnt ? 14 : 15;  // one more without the per-sink counts
+    if (wps == 5) return adj ? 8 : 9;
+    return wps <= 7 ? 7 : 4;
+  }
+  if (wps <= 3) return adj ? 11 : 10;
+  if (wps == 4) return adj ? 8 : 9;
+  if (wps == 5) return adj ? 5 : 6;
+  return wps <= 7 ? (adj ? 4 : 5) : (adj ? 2 : 3);
 }
 // adjoint: slots of the per-wave table of d loss / d alpha (a power of two)
 __host__ __device__ constexpr int occ_hn(int wps, bool adj) {
   return !adj ? 0 : wps <= 3 ? 256 : wps <= 5 ? 128 : 64;
 }
-template <bool ADJ, typename T>
+template <bool ADJ, typename T, bool CNT>
 __host__ __device__ constexpr size_t occ_lds(int wps) {
-  return lds_per_wave<ADJ, T>(occ_ks(wps, ADJ), occ_kr(wps, ADJ, sizeof(T) == 4),
-                              occ_hn(wps, ADJ));
+  return lds_per_wave<ADJ, T, CNT>(occ_ks(wps, ADJ), occ_kr(wps, ADJ, sizeof(T) == 4, CNT),
+                                   occ_hn(wps, ADJ));
 }
 constexpr size_t kLdsPerCu = 160 * 1024;
 template <typename T>
 constexpr bool occ_fits(int wps) {
-  return occ_lds<false, T>(wps) * 4 * wps <= kLdsPerCu &&
-         occ_lds<true, T>(wps) * 4 * wps <= kLdsPerCu;
+  return occ_lds<false, T, true>(wps) * 4 * wps <= kLdsPerCu &&
+         occ_lds<false, T, false>(wps) * 4 * wps <= kLdsPerCu &&
+         occ_lds<true, T, false>(wps) * 4 * wps <= kLdsPerCu;
 }
 static_assert(occ_fits<float>(3) && occ_fits<float>(4) && occ_fits<float>(5) &&
                   occ_fits<float>(6) && occ_fits<float>(8), "");
@@ -1151,7 +1159,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const uint64_t below = (1ull << lane) - 1;  // the lanes below this one
-  unsigned char *base = smem + wv * lds_per_wave<ADJ, T>(KS, KR, HN);
+  unsigned char *base = smem + wv * lds_per_wave<ADJ, T, CNT>(KS, KR, HN);
   uint64_t *s_open = reinterpret_cast<uint64_t *>(base);
   base += 64 * 8;
   double *s_hv = reinterpret_cast<double *>(base);  // adjoint table: sums, then keys
@@ -1165,7 +1173,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   lds_i32 *s_qe = (lds_i32 *)reinterpret_cast<int32_t *>(base);  // entry: cell or particle
   base += kQueue * 4;
   int32_t *s_cnt = reinterpret_cast<int32_t *>(base);  // forward: pieces, steps per sink
-  if (!ADJ) base += 2 * 64 * 4;
+  if (!ADJ && CNT) base += 2 * 64 * 4;
   int32_t *s_anc = reinterpret_cast<int32_t *>(base);
   base += KS * 64 * 4;
   int32_t *s_pre = reinterpret_cast<int32_t *>(base);
@@ -1185,6 +1193,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   // a replay needs every block of the recording
   const bool replay = ADJ && a.tape_mode == 2 && *a.tape_ctr <= a.tape_cap;
   int chunk = -1, sub = a.group;
+  int tc_next = 0, tc_end = 0;  // recording: the wave's blocks not yet used
   for (;;) {
     if (sub == a.group) {
       chunk = wave_take(a.queue, a.n_chunks);
@@ -1269,7 +1278,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         node = ((sk.keyS >> (62 - dd)) & 1) ? right : node + 1;
       }
     }
-    if (!ADJ) {
+    if (!ADJ && CNT) {
       s_cnt[lane] = 0;
       s_cnt[64 + lane] = 0;
     }
@@ -1284,8 +1293,6 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     int n_open = 0, n_rays = 0, n_psrc = 0;
     int qh = 0, qn = 0;  // the queue: first entry, entries (wave-uniform)
     int tprev = -1;      // recording: the set's last block
-    int tpre = 0;        // recording: lane 0's block for the next round, taken ahead
-    bool tpre_ok = false;
     int tcur = -1;       // replay: the set's next block
     if (!ADJ && a.tape_mode == 1 && lane == 0) a.tape_head[set] = -1;
     if (replay) tcur = a.tape_head[set];
@@ -1329,16 +1336,16 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       int tblk = -1;     // this round's tape block
       bool rp = false;   // tau from the tape
       if (!ADJ && a.tape_mode == 1) {
-        // This round's block was taken a round ahead, so that the atomic's
-        // return is not waited for on the spot; the numbers a wave takes still
-        // increase (the set's last one taken ahead goes unused).
-        int b = tpre;
-        if (lane == 0) {
-          if (!tpre_ok) b = atomicAdd(a.tape_ctr, 1);
-          tpre = atomicAdd(a.tape_ctr, 1);
+        // Blocks come from one counter, tape_chunk at a time per wave, so
+        // that few atomics meet on it; the numbers a wave takes increase (the
+        // wave's last unused ones are left over).
+        if (tc_next == tc_end) {
+          int c0 = 0;
+          if (lane == 0) c0 = atomicAdd(a.tape_ctr, a.tape_chunk);
+          tc_next = __builtin_amdgcn_readfirstlane(c0);
+          tc_end = tc_next + a.tape_chunk;
         }
-        tpre_ok = true;
-        b = __builtin_amdgcn_readfirstlane(b);
+        const int b = tc_next++;
         if (b < a.tape_cap) {  // blocks come in increasing order, so a full tape stays full
           if (lane == 0) {
             if (tprev < 0)
@@ -1749,7 +1756,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         if (NBND > 0)
           for (int b = 0; b < kMaxBands; ++b)
             if (b < a.n_bands) a.flux_bands[b * a.n_sinks + out] = bad ? (T)NAN : (T)FB[b];
-        if (a.counters) {
+        if (CNT && a.counters) {
           int32_t *o = a.counters + 5 * out;
           o[0] = bad ? -1 : n_open;
           o[1] = bad ? -1 : n_rays;
@@ -1769,66 +1776,66 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ, sizeof(T) == 4), occ_hn(3, ADJ),
+  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ, sizeof(T) == 4, CNT), occ_hn(3, ADJ),
             0, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ, sizeof(T) == 4), occ_hn(4, ADJ),
+  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ, sizeof(T) == 4, CNT), occ_hn(4, ADJ),
             0, 0, 0, 0, CNT>(a);
 }
 // The flux with the vector flux, at the 4-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4v(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(4, false), occ_kr(4, false, sizeof(T) == 4), occ_hn(4, false),
+  walk_body<T, false, occ_ks(4, false), occ_kr(4, false, sizeof(T) == 4, CNT), occ_hn(4, false),
             1, 0, 0, 0, CNT>(a);
 }
 // The flux per opacity band, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3b(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4), occ_hn(3, false),
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4, CNT), occ_hn(3, false),
             0, kMaxBands, 0, 0, CNT>(a);
 }
 // The flux with the walk variants, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3x(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4), occ_hn(3, false),
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4, CNT), occ_hn(3, false),
             0, 0, 0, 1, CNT>(a);
 }
 // The flux with the sub-bucket particle trace, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3s(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4), occ_hn(3, false),
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4, CNT), occ_hn(3, false),
             0, 0, 1, 0, CNT>(a);
 }
 // The flux with the vector flux and the second moment, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3m(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4), occ_hn(3, false),
+  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4, CNT), occ_hn(3, false),
             2, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ, sizeof(T) == 4), occ_hn(5, ADJ),
+  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ, sizeof(T) == 4, CNT), occ_hn(5, ADJ),
             0, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_walk6(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ, sizeof(T) == 4), occ_hn(6, ADJ),
+  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ, sizeof(T) == 4, CNT), occ_hn(6, ADJ),
             0, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_walk8(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ, sizeof(T) == 4), occ_hn(8, ADJ),
+  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ, sizeof(T) == 4, CNT), occ_hn(8, ADJ),
             0, 0, 0, 0, CNT>(a);
 }
 
@@ -1950,9 +1957,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3b<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
+        k_walk3b<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(3), s>>>(a);
       else
-        k_walk3b<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
+        k_walk3b<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -1961,9 +1968,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3x<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
+        k_walk3x<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(3), s>>>(a);
       else
-        k_walk3x<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
+        k_walk3x<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -1972,9 +1979,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3s<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
+        k_walk3s<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(3), s>>>(a);
       else
-        k_walk3s<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
+        k_walk3s<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -1983,9 +1990,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3m<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
+        k_walk3m<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(3), s>>>(a);
       else
-        k_walk3m<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(3), s>>>(a);
+        k_walk3m<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(3), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -1994,9 +2001,9 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk4v<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T>(4), s>>>(a);
+        k_walk4v<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(4), s>>>(a);
       else
-        k_walk4v<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T>(4), s>>>(a);
+        k_walk4v<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(4), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -2004,10 +2011,12 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   const int per_simd = (L.blocks_per_cu * waves + 3) / 4;
   const int wps = per_simd >= 8 ? 8 : per_simd >= 6 ? 6 : per_simd == 5 ? 5 : per_simd == 4 ? 4 : 3;
   // waves per workgroup <= 4 x wps, so the workgroup fits the CU's LDS
-  const size_t shmem = (size_t)waves * occ_lds<ADJ, T>(wps);
-  if (shmem > kLdsPerCu) return fail(TREVR_E_ARG, "launch shape needs more LDS than a CU has");
   // per-sink counters only when asked for (the adjoint never keeps them)
-  if (!ADJ && a.counters) {
+  const bool cnt = !ADJ && a.counters;
+  const size_t shmem = (size_t)waves * (cnt ? occ_lds<ADJ, T, true>(wps)
+                                            : occ_lds<ADJ, T, false>(wps));
+  if (shmem > kLdsPerCu) return fail(TREVR_E_ARG, "launch shape needs more LDS than a CU has");
+  if (cnt) {
     if (wps == 8)
       k_walk8<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
     else if (wps == 6)
@@ -2057,6 +2066,17 @@ static void set_tape(FluxArgs<T> &a, int mode, const TapeBufs *tb) {
   a.tape_head = tb->head;
   a.tape_ctr = tb->ctr;
   a.tape_cap = (int32_t)tb->cap;
+  a.tape_chunk = 1;
+}
+
+// Blocks per counter atomic of a recording: 8 when the tape has room for
+// eight left over per wave many times over (the last recording's count plus a
+// quarter sizes it), else 1.
+static int32_t tape_chunk(const trevr_tree *t, int64_t cap) {
+  const trevr_launch &L = t->launch;
+  const int64_t waves = (int64_t)t->num_cu * L.blocks_per_cu *
+                        (L.waves_per_block > 4 ? 4 : L.waves_per_block);
+  return cap >= 16 * 8 * waves ? 8 : 1;
 }
 
 template <typename T>
@@ -2071,6 +2091,7 @@ static int flux_typed(const trevr_tree *t, double theta, double tau_ref, const i
   a.flux_mom = static_cast<T *>(flux_mom);
   a.counters = counters;
   set_tape<T>(a, tape_mode, tb);
+  if (tape_mode == 1) a.tape_chunk = tape_chunk(t, tb->cap);
   return launch_walk<T, false>(t, a, s);
 }
 
