@@ -1101,8 +1101,8 @@ __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
 // adjoint spends its LDS on the table first: a round's rays touch about 175
 // distinct cells at the headline workload, and a table much under that
 // sends most pieces to device-memory atomics.
-__host__ __device__ constexpr int occ_ks(int wps, bool adj) {
-  if (wps <= 3) return adj ? 3 : 14;
+__host__ __device__ constexpr int occ_ks(int wps, bool adj, bool f32) {
+  if (wps <= 3) return adj ? (f32 ? 3 : 2) : 14;
   if (wps == 4) return adj ? 3 : 4;
   if (wps == 5) return adj ? 3 : 5;
   return wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
@@ -1125,7 +1125,8 @@ __host__ __device__ constexpr int occ_hn(int wps, bool adj) {
 }
 template <bool ADJ, typename T, bool CNT>
 __host__ __device__ constexpr size_t occ_lds(int wps) {
-  return lds_per_wave<ADJ, T, CNT>(occ_ks(wps, ADJ), occ_kr(wps, ADJ, sizeof(T) == 4, CNT),
+  constexpr bool f32 = sizeof(T) == 4;
+  return lds_per_wave<ADJ, T, CNT>(occ_ks(wps, ADJ, f32), occ_kr(wps, ADJ, f32, CNT),
                                    occ_hn(wps, ADJ));
 }
 constexpr size_t kLdsPerCu = 160 * 1024;
@@ -1769,6 +1770,14 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   }
 }
 
+// The walk at the LDS split of an occupancy variant (waves per SIMD).
+template <typename T, bool ADJ, int WPS, int MOM, int NBND, int SPH, int VAR, bool CNT>
+__device__ __forceinline__ void walk_at(const FluxArgs<T> &a) {
+  constexpr bool f32 = sizeof(T) == 4;
+  walk_body<T, ADJ, occ_ks(WPS, ADJ, f32), occ_kr(WPS, ADJ, f32, CNT), occ_hn(WPS, ADJ), MOM, NBND,
+            SPH, VAR, CNT>(a);
+}
+
 // The walk kernel at several register budgets: with fewer VGPRs more waves
 // share a SIMD (better latency hiding) at the price of spills; the launch
 // shape picks one (waves per SIMD = workgroups per CU x waves per workgroup
@@ -1776,67 +1785,57 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(3, ADJ), occ_kr(3, ADJ, sizeof(T) == 4, CNT), occ_hn(3, ADJ),
-            0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 3, 0, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(4, ADJ), occ_kr(4, ADJ, sizeof(T) == 4, CNT), occ_hn(4, ADJ),
-            0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 4, 0, 0, 0, 0, CNT>(a);
 }
 // The flux with the vector flux, at the 4-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4v(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(4, false), occ_kr(4, false, sizeof(T) == 4, CNT), occ_hn(4, false),
-            1, 0, 0, 0, CNT>(a);
+  walk_at<T, false, 4, 1, 0, 0, 0, CNT>(a);
 }
 // The flux per opacity band, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3b(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4, CNT), occ_hn(3, false),
-            0, kMaxBands, 0, 0, CNT>(a);
+  walk_at<T, false, 3, 0, kMaxBands, 0, 0, CNT>(a);
 }
 // The flux with the walk variants, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3x(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4, CNT), occ_hn(3, false),
-            0, 0, 0, 1, CNT>(a);
+  walk_at<T, false, 3, 0, 0, 0, 1, CNT>(a);
 }
 // The flux with the sub-bucket particle trace, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3s(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4, CNT), occ_hn(3, false),
-            0, 0, 1, 0, CNT>(a);
+  walk_at<T, false, 3, 0, 0, 1, 0, CNT>(a);
 }
 // The flux with the vector flux and the second moment, at the 3-wave budget.
 template <typename T, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3m(
     FluxArgs<T> a) {
-  walk_body<T, false, occ_ks(3, false), occ_kr(3, false, sizeof(T) == 4, CNT), occ_hn(3, false),
-            2, 0, 0, 0, CNT>(a);
+  walk_at<T, false, 3, 2, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(5, ADJ), occ_kr(5, ADJ, sizeof(T) == 4, CNT), occ_hn(5, ADJ),
-            0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 5, 0, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_walk6(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(6, ADJ), occ_kr(6, ADJ, sizeof(T) == 4, CNT), occ_hn(6, ADJ),
-            0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 6, 0, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_walk8(
     FluxArgs<T> a) {
-  walk_body<T, ADJ, occ_ks(8, ADJ), occ_kr(8, ADJ, sizeof(T) == 4, CNT), occ_hn(8, ADJ),
-            0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 8, 0, 0, 0, 0, CNT>(a);
 }
 
 __global__ void k_zero_i32(int32_t *p, int n) {

@@ -7,6 +7,8 @@
   * a tape too small for the recording: the taped adjoint falls back to
     tracing twice with the same result; the next automatically sized
     recording is complete;
+  * tape blocks taken eight at a time (a large tape) or one at a time give
+    the same recording and gradients;
   * the taped adjoint without a recording, or after a rebuild, is refused
     with TREVR_E_STATE;
   * the taped adjoint against the oracle's adjoint.
@@ -91,6 +93,28 @@ def test_taped_adjoint_sink_subset_overflow_and_resize():
     _grads_close(tg.adjoint_taped(gF), g_two, 1e-12, "resized tape")
     with pytest.raises(P.TrevrError):
         tg.reserve_tape(-1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tape_blocks_taken_in_chunks(prec):
+    """A tape with room for eight leftover blocks per wave many times over
+    makes each wave take its blocks eight at a time; the recording and the
+    taped adjoint are the same as with one block per atomic."""
+    _note("tape blocks eight at a time, %s" % prec)
+    w = _workload(1 << 13, 400, 10.0, 47, prec)
+    tg = _tree(w)
+    tg.set_launch(1, 1, 64)  # 256 waves: chunks of 8 need >= 16 x 8 x 256 blocks
+    n = w["pos"].shape[0]
+    gF = torch.as_tensor(np.random.default_rng(48).standard_normal(n), dtype=tg.dtype,
+                         device="cuda")
+    tol = 1e-12 if prec == "f64" else 2e-6
+    F0, C0 = tg.flux(0.75, 0.1, counters=True)
+    g_two = tg.adjoint(0.75, 0.1, gF, mode=P.ADJ_RECOMPUTE)
+    for blocks in (16 * 8 * 256 - 1, 16 * 8 * 256, 100000):  # one at a time, then chunks
+        tg.reserve_tape(blocks)
+        F1, C1 = tg.flux(0.75, 0.1, counters=True, tape=True)
+        assert torch.equal(F0, F1) and torch.equal(C0, C1), blocks
+        _grads_close(tg.adjoint_taped(gF), g_two, tol, "tape of %d blocks" % blocks)
 
 
 def test_taped_adjoint_refused_without_recording():
