@@ -208,16 +208,37 @@ struct RayCtx {
   int kr;
 };
 
+// The deeper part of the lane's stack, in private memory, in the LDS part's
+// format: binary32 entries packed in 8 bytes, binary64 ones in 12.
 template <typename G>
-struct StackEntry {
-  int32_t node, tag;
-  G tb;
+struct StackSpill;
+template <>
+struct StackSpill<float> {
+  uint64_t e[kRefineStack];
 };
-// The deeper part of the lane's stack (rarely reached), in private memory.
-template <typename G>
-struct StackSpill {
-  StackEntry<G> e[kRefineStack];
+template <>
+struct StackSpill<double> {
+  uint32_t n[kRefineStack];
+  double t[kRefineStack];
 };
+__device__ __forceinline__ void spill_write(StackSpill<float> &o, int i, uint32_t e, float t) {
+  o.e[i] = (uint64_t)e | ((uint64_t)__float_as_uint(t) << 32);
+}
+__device__ __forceinline__ void spill_write(StackSpill<double> &o, int i, uint32_t e, double t) {
+  o.n[i] = e;
+  o.t[i] = t;
+}
+__device__ __forceinline__ void spill_read(const StackSpill<float> &o, int i, uint32_t &e,
+                                           float &t) {
+  const uint64_t v = o.e[i];
+  e = (uint32_t)v;
+  t = __uint_as_float((uint32_t)(v >> 32));
+}
+__device__ __forceinline__ void spill_read(const StackSpill<double> &o, int i, uint32_t &e,
+                                           double &t) {
+  e = o.n[i];
+  t = o.t[i];
+}
 
 // A stack entry whose cell is kMark opens a deferred refinement job: its tag
 // and parameter are the job's entry crossing; the entry below it holds the
@@ -246,27 +267,22 @@ __device__ __forceinline__ void st_read(const RayCtx<double> &c, int k, uint32_t
 template <typename G>
 __device__ __forceinline__ void stack_push(RayCtx<G> &c, StackSpill<G> &ovf, int k, int node,
                                            int tag, G t) {
-  if (k < c.kr) {
-    st_write(c, k, (uint32_t)node | ((uint32_t)(tag + 1) << 30), t);
-  } else {
-    ovf.e[k - c.kr].node = node;
-    ovf.e[k - c.kr].tag = tag;
-    ovf.e[k - c.kr].tb = t;
-  }
+  const uint32_t e = (uint32_t)node | ((uint32_t)(tag + 1) << 30);
+  if (k < c.kr)
+    st_write(c, k, e, t);
+  else
+    spill_write(ovf, k - c.kr, e, t);
 }
 template <typename G>
 __device__ __forceinline__ void stack_pop(const RayCtx<G> &c, const StackSpill<G> &ovf, int k,
                                           int &node, int &tag, G &t) {
-  if (k < c.kr) {
-    uint32_t e;
+  uint32_t e;
+  if (k < c.kr)
     st_read(c, k, e, t);
-    node = (int)(e & 0x3fffffffu);
-    tag = (int)(e >> 30) - 1;
-  } else {
-    node = ovf.e[k - c.kr].node;
-    tag = ovf.e[k - c.kr].tag;
-    t = ovf.e[k - c.kr].tb;
-  }
+  else
+    spill_read(ovf, k - c.kr, e, t);
+  node = (int)(e & 0x3fffffffu);
+  tag = (int)(e >> 30) - 1;
 }
 
 // A policy receives each piece as (cell, alpha, length, entry t and plane,
@@ -755,13 +771,11 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, T ta,
     // not the lane pushes; reads of the two top slots are clamped in range.
     {
       const int tg = Emit::kTags ? cgb : -1;
-      if (sp < c.kr) {
-        st_write(c, sp, (uint32_t)farc | ((uint32_t)(tg + 1) << 30), ctb);
-      } else if (push) {
-        ovf.e[sp - c.kr].node = farc;
-        ovf.e[sp - c.kr].tag = tg;
-        ovf.e[sp - c.kr].tb = ctb;
-      }
+      const uint32_t e = (uint32_t)farc | ((uint32_t)(tg + 1) << 30);
+      if (sp < c.kr)
+        st_write(c, sp, e, ctb);
+      else if (push)
+        spill_write(ovf, sp - c.kr, e, ctb);
     }
     int nd1, tg1, nd2, tg2;
     T tt1, tt2;
@@ -772,20 +786,12 @@ __device__ void refine_light(const TraceRecT<T> *__restrict__ TR, int X, T ta,
       uint32_t e1, e2;
       st_read(c, r1, e1, tt1);
       st_read(c, r2, e2, tt2);
+      if (pop && k1 >= c.kr) spill_read(ovf, k1 - c.kr, e1, tt1);
       nd1 = (int)(e1 & 0x3fffffffu);
       tg1 = (int)(e1 >> 30) - 1;
+      if (pop && nd1 == kMark && k2 >= c.kr) spill_read(ovf, k2 - c.kr, e2, tt2);
       nd2 = (int)(e2 & 0x3fffffffu);
       tg2 = (int)(e2 >> 30) - 1;
-      if (pop && k1 >= c.kr) {
-        nd1 = ovf.e[k1 - c.kr].node;
-        tg1 = ovf.e[k1 - c.kr].tag;
-        tt1 = ovf.e[k1 - c.kr].tb;
-      }
-      if (pop && nd1 == kMark && k2 >= c.kr) {
-        nd2 = ovf.e[k2 - c.kr].node;
-        tg2 = ovf.e[k2 - c.kr].tag;
-        tt2 = ovf.e[k2 - c.kr].tb;
-      }
     }
     const bool job = pop & (nd1 == kMark);  // a deferred job: its entry, then its cell and exit
     const bool done = split_it ? !(has_near | has_far) : !pop;
