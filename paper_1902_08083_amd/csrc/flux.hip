@@ -1108,14 +1108,14 @@ __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
 // distinct cells at the headline workload, and a table much under that
 // sends most pieces to device-memory atomics.
 __host__ __device__ constexpr int occ_ks(int wps, bool adj, bool f32) {
-  if (wps <= 3) return adj ? (f32 ? 3 : 2) : 14;
+  if (wps <= 3) return adj ? (f32 ? 3 : 2) : (f32 ? 6 : 14);
   if (wps == 4) return adj ? 3 : 4;
   if (wps == 5) return adj ? 3 : 5;
   return wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
 }
 __host__ __device__ constexpr int occ_kr(int wps, bool adj, bool f32, bool cnt) {
   if (f32) {
-    if (wps <= 3) return adj ? 16 : 15;
+    if (wps <= 3) return adj ? 16 : cnt ? 19 : 20;
     if (wps == 4) return adj ? 12 : cnt ? 14 : 15;  // one more without the per-sink counts
     if (wps == 5) return adj ? 8 : 9;
     return wps <= 7 ? 7 : 4;
