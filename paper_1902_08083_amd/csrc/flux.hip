@@ -624,9 +624,14 @@ struct Scatter {
   int hmask;    // table slots - 1 (a power of two minus one)
   // Every piece goes to the table (one of two slots picked by two hashes of
   // the cell): a round's rays share most of their cells, so the round's
-  // sums reach device memory as about one atomic per distinct cell; a cell
-  // whose two slots hold other cells goes straight to device memory.  One
+  // sums reach device memory as about one atomic per distinct cell.  One
   // compare-and-swap per probe claims a free slot or finds the cell's own.
+  // A cell whose two slots hold other cells takes the second one over: the
+  // slot's old sum goes to device memory, so the table keeps the cells the
+  // round is working on.  Of several lanes of one call that would take the
+  // same slot, one does (a compare-and-swap on the key it saw); the others
+  // send their own sum to device memory.  The call's hits land before any
+  // slot changes hands.
   __device__ __forceinline__ void pool(int node, double v) {
     int sl = (int)((((uint32_t)node * 2654435761u) >> 16) & (uint32_t)hmask);
     int k = -1;  // the slot's key before: free (now ours), this cell, or another
@@ -638,10 +643,23 @@ struct Scatter {
       __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &k, node, __ATOMIC_RELAXED,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
-    if (k == -1 || k == node)
-      lds_add(&hv[sl], v);
-    else
-      gbl_add(&abar[node], v);
+    const bool hit = k == -1 || k == node;
+    if (hit) lds_add(&hv[sl], v);
+    // The two branches exclude each other per lane, so without this the
+    // compiler may order a take-over before another lane's hit on that slot.
+    wave_sync();
+    if (!hit) {
+      int kk = k;
+      __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &kk, node, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      if (kk == k) {
+        const double old = __hip_atomic_exchange((lds_d *)hv + sl, v, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
+        gbl_add(&abar[k], old);
+      } else {
+        gbl_add(&abar[node], v);
+      }
+    }
   }
   __device__ __forceinline__ void operator()(int node, double alpha, double l, double ta, int ga,
                                              double tb, int gb, double) {
