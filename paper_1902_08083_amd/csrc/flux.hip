@@ -665,10 +665,16 @@ struct Scatter {
                                              double tb, int gb, double) {
     pool(node, -(g * l));
 
+    // Each crossing goes to its axis's sum by an FMA with a coefficient of 1,
+    // -1 or 0 (a select of the high word only): cheaper than selecting the
+    // binary64 terms themselves.
     const double xb = alpha * tb, xa = alpha * ta;
-    u[0] += (ga == 0 ? xa : 0.0) - (gb == 0 ? xb : 0.0);
-    u[1] += (ga == 1 ? xa : 0.0) - (gb == 1 ? xb : 0.0);
-    u[2] += (ga == 2 ? xa : 0.0) - (gb == 2 ? xb : 0.0);
+    u[0] = fma(ga == 0 ? 1.0 : 0.0, xa, u[0]);
+    u[1] = fma(ga == 1 ? 1.0 : 0.0, xa, u[1]);
+    u[2] = fma(ga == 2 ? 1.0 : 0.0, xa, u[2]);
+    u[0] = fma(gb == 0 ? -1.0 : 0.0, xb, u[0]);
+    u[1] = fma(gb == 1 ? -1.0 : 0.0, xb, u[1]);
+    u[2] = fma(gb == 2 ? -1.0 : 0.0, xb, u[2]);
   }
 };
 
