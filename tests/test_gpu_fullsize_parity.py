@@ -6,6 +6,9 @@ times (default launch shapes), through the C ABI.
     sweep {0.5, 0.75, 1.0} x {0.05, 0.1, 0.2}; the oracle (binary32 mirror)
     evaluates a seeded 65,536-sink sample (seed 7): fluxes within 1e-5,
     counters identical;
+  * the headline point at every one of the 2,097,152 sinks, in 8 parts of
+    262,144 consecutive sinks so that each part's oracle run is short: fluxes
+    within 1e-5, counters identical;
   * the same tree exported bit for bit against the oracle's (order,
     topology, keys, every binary64 cell value);
   * the 64-box forest (uneven boxes, 2^12..2^17 particles): its export, box by
@@ -72,6 +75,30 @@ def test_c3_sweep_full_size(c3, theta, tau_ref):
     assert rel.max() <= 1e-5, (int(sample[np.argmax(rel)]), rel.max())
     bad = np.nonzero(np.any(Cg[sample] != Co, axis=1))[0]
     assert bad.size == 0, ("counters differ", sample[bad[:5]], Cg[sample[bad[:5]]], Co[bad[:5]])
+
+
+@pytest.fixture(scope="module")
+def c3_headline_gpu(c3):
+    w, tg, _, _ = c3
+    _note("c3 2^21 headline point: every sink on the GPU, with counters")
+    F, C = tg.flux(w["theta"], w["tau_ref"], counters=True)
+    return F.double().cpu().numpy(), C.cpu().numpy().astype(np.int64)
+
+
+@pytest.mark.parametrize("part", range(8))
+def test_c3_headline_every_sink(c3, c3_headline_gpu, part):
+    w, _, to, _ = c3
+    Fg, Cg = c3_headline_gpu
+    n = Fg.size
+    lo, hi = part * n // 8, (part + 1) * n // 8
+    _note("c3 2^21 headline, sinks [%d, %d) on the oracle" % (lo, hi))
+    sinks = np.arange(lo, hi)
+    Fo, Co = to.flux(w["theta"], w["tau_ref"], sinks=sinks, nthreads=NTHREADS)
+    rel = np.abs(Fg[lo:hi] - Fo) / Fo
+    _note("max rel %.3g, median %.3g" % (rel.max(), np.median(rel)))
+    assert rel.max() <= 1e-5, (lo + int(np.argmax(rel)), rel.max())
+    bad = np.nonzero(np.any(Cg[lo:hi] != Co, axis=1))[0]
+    assert bad.size == 0, ("counters differ", lo + bad[:5], Cg[lo + bad[:5]], Co[bad[:5]])
 
 
 def _same(g, o, what):
