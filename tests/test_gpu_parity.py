@@ -205,6 +205,26 @@ def test_adjoint_kernel_variants_full_refinement_fp64(launch):
         assert err.max() <= 1e-10, (name, launch, float(err.max()))
 
 
+@pytest.mark.parametrize("launch", [(3, 4, 64), (4, 4, 64), (6, 4, 64), (8, 4, 64)])
+def test_adjoint_kernel_variants_fp32(launch):
+    """Binary32 transport on every adjoint table size: 256 slots at 3 waves per
+    SIMD, 128 at 4, 64 at 6 and 8, where most of a round's cells miss the
+    table and take slots over from each other."""
+    _note("adjoint variant %s, fp32" % (launch,))
+    w = small_lognormal(1 << 14, 400, 10.0, 24, prec="f32")
+    gF = np.random.default_rng(25).standard_normal(w["pos"].shape[0])
+    tg = gpu_tree(w)
+    tg.set_launch(*launch, adjoint=True)
+    gr, gk, gl = tg.adjoint(0.75, 0.1, torch.as_tensor(gF, dtype=torch.float32, device="cuda"))
+    gF = gF.astype(np.float32).astype(np.float64)
+    orr, ok, ol = oracle_tree(w).adjoint(0.75, 0.1, gF, nthreads=NTHREADS)
+    for name, g, o in (("rho", gr, orr), ("kappa", gk, ok), ("lum", gl, ol)):
+        g = g.cpu().numpy().astype(np.float64)
+        scale = np.max(np.abs(o))
+        err = np.abs(g - o) / (np.abs(o) + 1e-6 * scale)
+        assert err.max() <= 2e-6, (name, launch, float(err.max()))
+
+
 def test_flux_sink_subset_and_order():
     _note("flux sink subset")
     w = small_lognormal(40000, 2000, 5.0, 13)
