@@ -237,7 +237,7 @@ int trevr_compute_flux_adjoint_noalloc(trevr_tree *tree, double theta_open, doub
  * n_sinks sinks on the built tree: RECOMPUTE 8 (5 m + n) bytes (per cell
  * d loss / d alpha, d loss / d L_C and d loss / d x_L; per particle the
  * single sources' d loss / d L), STORE that plus the recording's flux, the
- * tape's per-set heads and a tape of 516 B per 64 rays, sized as the tree
+ * tape's per-set heads and a tape of 837 B per 64 rays, sized as the tree
  * sizes its own (the last recording's block count plus a quarter, or 1024
  * rays per sink); AUTO 0 (it takes none).  A smaller STORE scratch that still
  * holds one tape block per 64 sinks is accepted: a recording that outgrows
@@ -416,12 +416,13 @@ int trevr_export_sph(const trevr_tree *tree, int64_t *n_entries, int64_t *offset
 
 /* The flux and its adjoint with the traversal recorded once.  The recording
  * flux computes exactly what trevr_compute_flux computes (same arguments and
- * errors) and in addition stores every ray's optical depth tau (binary64, in
- * a tape owned by the tree: 8 B per ray in blocks of 64); the taped adjoint
- * computes what trevr_compute_flux_adjoint computes for the arguments of the
- * last recording call on this tree, taking each ray's tau from the tape, so
- * each ray is traced once (for the scatter of Sec. 2.2.3's pieces) instead
- * of twice.  The sink array of the recording call must be unchanged until
+ * errors) and in addition stores every ray's optical depth tau (binary64)
+ * and each round's list of rays (source and sink) in a tape owned by the
+ * tree: 13 B per ray in blocks of 64; the taped adjoint computes what
+ * trevr_compute_flux_adjoint computes for the arguments of the last
+ * recording call on this tree, taking its rays from the tape instead of
+ * walking the tree again and each ray's tau from it, so each ray is traced
+ * once (for the scatter of Sec. 2.2.3's pieces) instead of twice.  The sink array of the recording call must be unchanged until
  * the taped adjoint has run, and both run on one stream (or are ordered).
  * Tape size: the last recording's block count plus a quarter, a first guess
  * of 1024 rays per sink within half the free device memory, or what

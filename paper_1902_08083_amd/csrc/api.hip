@@ -77,7 +77,8 @@ trevr_tree::~trevr_tree() {
                           &n_amax, &n_alpha_min, &n_alpha_max, &n_dalpha, &n_xl, &n_lc,
                           &n_lfar, &keys_in, &keys_out, &vals_in, &vals_out, &sort_tmp, &bfs,
                           &flags, &scan, &err, &box_key, &skeys, &small, &queue, &adj_node,
-                          &adj_part, &adj_heap, &adj_flux, &tape, &tape_next, &tape_head, &tape_ctr,
+                          &adj_part, &adj_heap, &adj_flux, &tape, &tape_src, &tape_own, &tape_nb,
+                          &tape_next, &tape_head, &tape_ctr,
                           &band_alpha, &band_dmax, &band_trace, &bs_A, &bs_alpha, &bs_amin,
                           &bs_amax, &bs_amin_d, &bs_amax_d, &bs_dalpha, &pkappa, &sph_pos,
                           &sph_mk, &sph_dp, &sph_hmax, &sph_cnt, &sph_off, &sph_nb,

@@ -85,8 +85,12 @@ struct FluxArgs {
   int32_t *queue;  // kXcd counters
   // Tape of per-ray optical depths: one block of 64 per round, the blocks of
   // one 64-sink set chained in round order.  Mode 1 (flux) writes it, mode 2
-  // (adjoint) reads it instead of tracing each ray for tau a first time.
+  // (adjoint) reads it instead of tracing each ray for tau a first time, and
+  // takes its rounds from the recorded ray lists instead of walking again.
   double *tape;        // [tape_cap][64]
+  uint32_t *tape_src;  // [tape_cap][64] the ray's queue entry (its source)
+  uint8_t *tape_own;   // [tape_cap][64] the ray's owning lane (its sink)
+  uint8_t *tape_nb;    // [tape_cap] rays in the block's round (1..64)
   int32_t *tape_next;  // [tape_cap] the set's next block, -1 after its last
   int32_t *tape_head;  // [64-sink sets] the set's first block, -1 if it has none
   int32_t *tape_ctr;   // blocks taken; above tape_cap the tape is incomplete
@@ -1458,7 +1462,13 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         } else {
           trace_pieces<T>(a, C, keyC, depthC, tk, c, ts);
         }
-        if (!ADJ && tblk >= 0) a.tape[(int64_t)tblk * 64 + lane] = ts.tau;
+        if (!ADJ && tblk >= 0) {  // lane 0 is busy in every round
+          const int64_t r = (int64_t)tblk * 64 + lane;
+          a.tape[r] = ts.tau;
+          a.tape_src[r] = e;
+          a.tape_own[r] = (uint8_t)owner;
+          if (lane == 0) a.tape_nb[tblk] = (uint8_t)nb;
+        }
         f = ((double)L * exp(-ts.tau)) / ((4.0 * M_PI) * (double)c.r2);
         if constexpr (VAR > 0) {
           if (a.bg_pos && !psrc) {  // a merged background cell radiates from the sphere
@@ -1690,7 +1700,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       int n = root;
       uint64_t active = group;
       bool from_skip = false;
-      for (;;) {
+      for (; !replay;) {  // a replay takes its rays from the tape below
         const WalkRecT<T> w = a.W[n];
         const int depth = w.depth;
         if (from_skip) active = s_open[depth - 1];
@@ -1771,7 +1781,23 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         if (n >= end) break;
         from_skip = true;
       }
-      while (qn > 0) round();  // the rest of this box's rays
+      // The rest of this box's rays.  A replay walks no tree: the recording's
+      // rounds come back block by block from their ray lists, the same rays
+      // in the same rounds and order as the recording's walk made them.
+      for (;;) {
+        if (replay && qn == 0 && tcur >= 0) {
+          const int nbt = a.tape_nb[tcur];
+          if (lane < nbt) {
+            const int64_t r = (int64_t)tcur * 64 + lane;
+            const int slot = (qh + lane) & (kQueue - 1);
+            s_qe[slot] = (int32_t)a.tape_src[r];
+            s_qo[slot] = a.tape_own[r];
+          }
+          qn = nbt;
+        }
+        if (qn == 0) break;
+        round();
+      }
     }
     if (!ADJ) {
       wave_sync();
@@ -2076,14 +2102,19 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
 // caller's scratch buffer.
 struct TapeBufs {
   double *tape;     // [cap][64]
+  uint32_t *src;    // [cap][64]
+  uint8_t *own;     // [cap][64]
+  uint8_t *nb;      // [cap]
   int32_t *next;    // [cap]
   int32_t *head;    // [64-sink sets]
   int32_t *ctr;     // blocks taken
   int64_t cap;      // blocks
 };
 static TapeBufs tree_tape(const trevr_tree *t) {
-  return TapeBufs{t->tape.as<double>(), t->tape_next.as<int32_t>(), t->tape_head.as<int32_t>(),
-                  t->tape_ctr.as<int32_t>(), t->tape_cap};
+  return TapeBufs{t->tape.as<double>(),       t->tape_src.as<uint32_t>(),
+                  t->tape_own.as<uint8_t>(),    t->tape_nb.as<uint8_t>(),
+                  t->tape_next.as<int32_t>(),   t->tape_head.as<int32_t>(),
+                  t->tape_ctr.as<int32_t>(),    t->tape_cap};
 }
 
 template <typename T>
@@ -2091,6 +2122,9 @@ static void set_tape(FluxArgs<T> &a, int mode, const TapeBufs *tb) {
   a.tape_mode = mode;
   if (mode == 0) return;
   a.tape = tb->tape;
+  a.tape_src = tb->src;
+  a.tape_own = tb->own;
+  a.tape_nb = tb->nb;
   a.tape_next = tb->next;
   a.tape_head = tb->head;
   a.tape_ctr = tb->ctr;
@@ -2243,14 +2277,20 @@ static int64_t tape_want(const trevr_tree *t, int64_t n_sinks) {
   if (cap > INT32_MAX - 65536) cap = INT32_MAX - 65536;
   return cap < 1 ? 1 : cap;
 }
+// Bytes per tape block (64 rays): taus, sources, owners, the ray count and
+// the link to the set's next block.
+constexpr size_t kTapeBlockBytes =
+    64 * sizeof(double) + 64 * sizeof(uint32_t) + 64 * sizeof(uint8_t) + sizeof(uint8_t) +
+    sizeof(int32_t);
 // The same, cut to what fits in half the free device memory (beyond what the
 // tree's tape already holds); `fits` tells whether it was cut.
 static int tape_blocks(trevr_tree *t, int64_t n_sinks, int64_t &cap, bool &fits) {
   cap = tape_want(t, n_sinks);
   size_t free_b = 0, total_b = 0;
   TREVR_HIP(hipMemGetInfo(&free_b, &total_b));
-  const size_t per = 64 * sizeof(double) + sizeof(int32_t);
-  const int64_t fit = (int64_t)((free_b / 2 + t->tape.bytes + t->tape_next.bytes) / per);
+  const size_t held = t->tape.bytes + t->tape_src.bytes + t->tape_own.bytes + t->tape_nb.bytes +
+                      t->tape_next.bytes;
+  const int64_t fit = (int64_t)((free_b / 2 + held) / kTapeBlockBytes);
   fits = cap <= fit;
   if (!fits && t->tape_reserve <= 0) cap = fit;
   if (cap < 1) cap = 1;
@@ -2289,6 +2329,9 @@ int flux_taped_impl(trevr_tree *t, double theta, double tau_ref, const int32_t *
   }
   (void)fits;  // a short tape only makes the taped adjoint trace twice
   TREVR_HIP(t->tape.ensure((size_t)cap * 64 * sizeof(double)));
+  TREVR_HIP(t->tape_src.ensure((size_t)cap * 64 * sizeof(uint32_t)));
+  TREVR_HIP(t->tape_own.ensure((size_t)cap * 64 * sizeof(uint8_t)));
+  TREVR_HIP(t->tape_nb.ensure((size_t)cap * sizeof(uint8_t)));
   TREVR_HIP(t->tape_next.ensure((size_t)cap * sizeof(int32_t)));
   TREVR_HIP(t->tape_head.ensure((size_t)(sets > 0 ? sets : 1) * sizeof(int32_t)));
   TREVR_HIP(t->tape_ctr.ensure(sizeof(int32_t)));
@@ -2374,7 +2417,8 @@ static int tree_adj_bufs(trevr_tree *t, AdjBufs &ab) {
 // Caller scratch layout, each part 256-byte aligned: the accumulators
 // (5 m + n doubles); in store mode then the recording's flux (n_sinks of the
 // tree's precision), the tape's per-set heads (4 B per 64 sinks), its block
-// counter, and the tape itself, cap blocks of 64 taus plus a 4-byte link each.
+// counter, and the tape itself, cap blocks of kTapeBlockBytes (64 taus, 64
+// sources, 64 owners, the ray count and the link), each array on its own.
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 static size_t adj_part_bytes(const trevr_tree *t) {
   return al256(sizeof(double) * 5 * (size_t)(t->m > 0 ? t->m : 1)) +
@@ -2387,7 +2431,10 @@ static size_t store_fixed_bytes(const trevr_tree *t, int64_t n_sinks) {
          al256(sizeof(int32_t) * (size_t)(sets > 0 ? sets : 1)) + 256;
 }
 static size_t store_block_bytes(int64_t cap) {
-  return al256((size_t)cap * 64 * sizeof(double)) + al256((size_t)cap * sizeof(int32_t));
+  const size_t c = (size_t)cap;
+  return al256(c * 64 * sizeof(double)) + al256(c * 64 * sizeof(uint32_t)) +
+         al256(c * 64 * sizeof(uint8_t)) + al256(c * sizeof(uint8_t)) +
+         al256(c * sizeof(int32_t));
 }
 
 int adjoint_scratch_size_impl(const trevr_tree *t, int mode, int64_t n_sinks, size_t *bytes) {
@@ -2426,13 +2473,21 @@ static bool carve(const trevr_tree *t, int mode, int64_t n_sinks, void *scratch,
   tb.ctr = reinterpret_cast<int32_t *>(p);
   p += 256;
   left -= fixed;
-  // the largest cap whose blocks fit (each block 512 B of taus + 4 B of link)
-  int64_t cap = (int64_t)(left / (64 * sizeof(double) + sizeof(int32_t)));
+  // the largest cap whose blocks fit
+  int64_t cap = (int64_t)(left / kTapeBlockBytes);
   while (cap > 0 && store_block_bytes(cap) > left) --cap;
   if (cap > INT32_MAX - 65536) cap = INT32_MAX - 65536;
   if (cap < (sets > 0 ? sets : 1)) return false;
+  const size_t c = (size_t)cap;
   tb.tape = reinterpret_cast<double *>(p);
-  tb.next = reinterpret_cast<int32_t *>(p + al256((size_t)cap * 64 * sizeof(double)));
+  p += al256(c * 64 * sizeof(double));
+  tb.src = reinterpret_cast<uint32_t *>(p);
+  p += al256(c * 64 * sizeof(uint32_t));
+  tb.own = reinterpret_cast<uint8_t *>(p);
+  p += al256(c * 64 * sizeof(uint8_t));
+  tb.nb = reinterpret_cast<uint8_t *>(p);
+  p += al256(c * sizeof(uint8_t));
+  tb.next = reinterpret_cast<int32_t *>(p);
   tb.cap = cap;
   return true;
 }

@@ -169,8 +169,9 @@ struct trevr_tree {
   // (x, y, z; L = 1 for such a cell, 0 otherwise)
   bool bg_ok = false;
   trevr::DevBuf bg_pos, bg_nonbg;
-  // tape of per-ray optical depths from the last recording flux call
-  trevr::DevBuf tape, tape_next, tape_head, tape_ctr;
+  // tape of per-ray optical depths (and each round's ray list) from the last
+  // recording flux call
+  trevr::DevBuf tape, tape_src, tape_own, tape_nb, tape_next, tape_head, tape_ctr;
   int64_t tape_cap = 0;             // blocks of 64
   int64_t tape_reserve = 0;         // blocks for later recordings, 0 = sized automatically
   int32_t *tape_used_h = nullptr;   // pinned: blocks the last recording took
