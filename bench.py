@@ -429,8 +429,9 @@ def walk_kernel_name(launch):
     waves = min(launch["waves_per_block"], 4)
     per_simd = (launch["blocks_per_cu"] * waves + 3) // 4
     wps = 8 if per_simd >= 8 else 6 if per_simd >= 6 else per_simd if per_simd >= 4 else 3
-    # <precision, adjoint, per-sink counters>: the timed flux asks for no counters
-    return "trevr::k_walk%s<float, false, false>" % ("" if wps == 3 else str(wps))
+    # <precision, adjoint, per-sink counters, recording>: the timed flux asks
+    # for no counters and records no tape
+    return "trevr::k_walk%s<float, false, false, false>" % ("" if wps == 3 else str(wps))
 
 
 def recorded_counters(launch_key):

@@ -1187,9 +1187,12 @@ constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source,
 // owning sink's context by lane shuffles; each owner adds its results in
 // queue order, so a sink's sum is in its own walk order whatever the other
 // sinks of the wave are.
+// REC: the recording flux (tape mode 1), an instance of its own so that the
+// plain flux carries none of the tape's code.
 template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0, int NBND = 0, int SPH = 0,
-          int VAR = 0, bool CNT = true>
+          int VAR = 0, bool CNT = true, bool REC = false>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
+  static_assert(!(ADJ && REC), "the adjoint records nothing");
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -1329,7 +1332,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
     int qh = 0, qn = 0;  // the queue: first entry, entries (wave-uniform)
     int tprev = -1;      // recording: the set's last block
     int tcur = -1;       // replay: the set's next block
-    if (!ADJ && a.tape_mode == 1 && lane == 0) a.tape_head[set] = -1;
+    if (REC && lane == 0) a.tape_head[set] = -1;
     if (replay) tcur = a.tape_head[set];
 
     // One round: the first min(qn, 64) queued rays, one per lane.
@@ -1370,7 +1373,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       double fb[kMaxBands] = {0.0, 0.0, 0.0, 0.0};      // f per band
       int tblk = -1;     // this round's tape block
       bool rp = false;   // tau from the tape
-      if (!ADJ && a.tape_mode == 1) {
+      if constexpr (REC) {
         // Blocks come from one counter, tape_chunk at a time per wave, so
         // that few atomics meet on it; the numbers a wave takes increase (the
         // wave's last unused ones are left over).
@@ -1462,7 +1465,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         } else {
           trace_pieces<T>(a, C, keyC, depthC, tk, c, ts);
         }
-        if (!ADJ && tblk >= 0) {  // lane 0 is busy in every round
+        if (REC && tblk >= 0) {  // lane 0 is busy in every round
           const int64_t r = (int64_t)tblk * 64 + lane;
           a.tape[r] = ts.tau;
           a.tape_src[r] = e;
@@ -1827,26 +1830,27 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
 }
 
 // The walk at the LDS split of an occupancy variant (waves per SIMD).
-template <typename T, bool ADJ, int WPS, int MOM, int NBND, int SPH, int VAR, bool CNT>
+template <typename T, bool ADJ, int WPS, int MOM, int NBND, int SPH, int VAR, bool CNT,
+          bool REC = false>
 __device__ __forceinline__ void walk_at(const FluxArgs<T> &a) {
   constexpr bool f32 = sizeof(T) == 4;
   walk_body<T, ADJ, occ_ks(WPS, ADJ, f32), occ_kr(WPS, ADJ, f32, CNT), occ_hn(WPS, ADJ), MOM, NBND,
-            SPH, VAR, CNT>(a);
+            SPH, VAR, CNT, REC>(a);
 }
 
 // The walk kernel at several register budgets: with fewer VGPRs more waves
 // share a SIMD (better latency hiding) at the price of spills; the launch
 // shape picks one (waves per SIMD = workgroups per CU x waves per workgroup
 // / 4, at least 3).
-template <typename T, bool ADJ, bool CNT>
+template <typename T, bool ADJ, bool CNT, bool REC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 3, 0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 3, 0, 0, 0, 0, CNT, REC>(a);
 }
-template <typename T, bool ADJ, bool CNT>
+template <typename T, bool ADJ, bool CNT, bool REC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 4, 0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 4, 0, 0, 0, 0, CNT, REC>(a);
 }
 // The flux with the vector flux, at the 4-wave budget.
 template <typename T, bool CNT>
@@ -1878,20 +1882,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     FluxArgs<T> a) {
   walk_at<T, false, 3, 2, 0, 0, 0, CNT>(a);
 }
-template <typename T, bool ADJ, bool CNT>
+template <typename T, bool ADJ, bool CNT, bool REC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 5, 0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 5, 0, 0, 0, 0, CNT, REC>(a);
 }
-template <typename T, bool ADJ, bool CNT>
+template <typename T, bool ADJ, bool CNT, bool REC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_walk6(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 6, 0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 6, 0, 0, 0, 0, CNT, REC>(a);
 }
-template <typename T, bool ADJ, bool CNT>
+template <typename T, bool ADJ, bool CNT, bool REC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_walk8(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 8, 0, 0, 0, 0, CNT>(a);
+  walk_at<T, ADJ, 8, 0, 0, 0, 0, CNT, REC>(a);
 }
 
 __global__ void k_zero_i32(int32_t *p, int n) {
@@ -1997,6 +2001,22 @@ static FluxArgs<T> make_args(const trevr_tree *t, double theta, double tau_ref,
   return a;
 }
 
+// The walk kernel of an occupancy variant (waves per SIMD).
+template <typename T, bool ADJ, bool CNT, bool REC>
+static void walk_kernel(int wps, int64_t blocks, int threads, size_t shmem, const FluxArgs<T> &a,
+                        hipStream_t s) {
+  if (wps == 8)
+    k_walk8<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  else if (wps == 6)
+    k_walk6<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  else if (wps == 5)
+    k_walk5<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  else if (wps == 4)
+    k_walk4<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  else
+    k_walk<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+}
+
 template <typename T, bool ADJ>
 static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s) {
   k_zero_i32<<<1, 64, 0, s>>>(a.queue, kXcd);
@@ -2071,28 +2091,18 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   const size_t shmem = (size_t)waves * (cnt ? occ_lds<ADJ, T, true>(wps)
                                             : occ_lds<ADJ, T, false>(wps));
   if (shmem > kLdsPerCu) return fail(TREVR_E_ARG, "launch shape needs more LDS than a CU has");
-  if (cnt) {
-    if (wps == 8)
-      k_walk8<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
-    else if (wps == 6)
-      k_walk6<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
-    else if (wps == 5)
-      k_walk5<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
-    else if (wps == 4)
-      k_walk4<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
-    else
-      k_walk<T, ADJ, true><<<(unsigned)blocks, threads, shmem, s>>>(a);
+  if constexpr (ADJ) {
+    walk_kernel<T, true, false, false>(wps, blocks, threads, shmem, a, s);
   } else {
-    if (wps == 8)
-      k_walk8<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
-    else if (wps == 6)
-      k_walk6<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
-    else if (wps == 5)
-      k_walk5<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
-    else if (wps == 4)
-      k_walk4<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    const bool rec = a.tape_mode == 1;
+    if (cnt && rec)
+      walk_kernel<T, false, true, true>(wps, blocks, threads, shmem, a, s);
+    else if (cnt)
+      walk_kernel<T, false, true, false>(wps, blocks, threads, shmem, a, s);
+    else if (rec)
+      walk_kernel<T, false, false, true>(wps, blocks, threads, shmem, a, s);
     else
-      k_walk<T, ADJ, false><<<(unsigned)blocks, threads, shmem, s>>>(a);
+      walk_kernel<T, false, false, false>(wps, blocks, threads, shmem, a, s);
   }
   TREVR_HIP(hipGetLastError());
   return TREVR_OK;
