@@ -1121,13 +1121,17 @@ __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
 // entry is 8 bytes for binary32, f64 + i32 for binary64), the ray queue
 // (kQueue x (i32 + u8)), the per-sink counts of traced pieces and steps
 // (2 x 64 x i32, a forward that keeps counters), the sink-ancestor windows
-// (ks x 64 lanes x i32) and the shared sink-chain prefix (64 x i32).
-constexpr int kQueue = 128;  // ray queue slots per wave (a power of two)
-template <bool ADJ, typename T, bool CNT = true>
+// (ks x 64 lanes x i32) and the shared sink-chain prefix (64 x i32).  The
+// adjoint's replay instance (ADJ with TAPE) walks no tree: it has no open
+// masks, and its queue holds one round.
+constexpr int kQueue = 128;       // ray queue slots per wave (a power of two)
+constexpr int kQueueReplay = 64;  // the same in the replay instance
+template <bool ADJ, typename T, bool CNT = true, bool TAPE = false>
 __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
-  return (size_t)64 * 8 + (ADJ ? (size_t)hn * 12 : 0) +
-         (size_t)kr * 64 * (sizeof(T) == 4 ? 8 : 12) + kQueue * 5 +
-         (ADJ || !CNT ? 0 : 2 * 64 * 4) + (size_t)ks * 64 * 4 + 64 * 4;
+  return (ADJ && TAPE ? 0 : (size_t)64 * 8) + (ADJ ? (size_t)hn * 12 : 0) +
+         (size_t)kr * 64 * (sizeof(T) == 4 ? 8 : 12) +
+         (size_t)(ADJ && TAPE ? kQueueReplay : kQueue) * 5 + (ADJ || !CNT ? 0 : 2 * 64 * 4) +
+         (size_t)ks * 64 * 4 + 64 * 4;
 }
 
 // Window depth, stack entries and table slots per occupancy variant (waves
@@ -1157,18 +1161,25 @@ __host__ __device__ constexpr int occ_kr(int wps, bool adj, bool f32, bool cnt) 
 __host__ __device__ constexpr int occ_hn(int wps, bool adj) {
   return !adj ? 0 : wps <= 3 ? 256 : wps <= 5 ? 128 : 64;
 }
-template <bool ADJ, typename T, bool CNT>
+// The replay instance spends the walk's LDS (open masks, half the queue:
+// 832 bytes) on three more window levels (768 bytes): 113.6 -> 110.8 ms for
+// the taped adjoint at 2^20, where a 17th stack entry gave 111.8 ms.
+__host__ __device__ constexpr int occ_ks_t(int wps, bool adj, bool f32, bool tape) {
+  return occ_ks(wps, adj, f32) + (adj && tape ? 3 : 0);
+}
+template <bool ADJ, typename T, bool CNT, bool TAPE = false>
 __host__ __device__ constexpr size_t occ_lds(int wps) {
   constexpr bool f32 = sizeof(T) == 4;
-  return lds_per_wave<ADJ, T, CNT>(occ_ks(wps, ADJ, f32), occ_kr(wps, ADJ, f32, CNT),
-                                   occ_hn(wps, ADJ));
+  return lds_per_wave<ADJ, T, CNT, TAPE>(occ_ks_t(wps, ADJ, f32, TAPE),
+                                         occ_kr(wps, ADJ, f32, CNT), occ_hn(wps, ADJ));
 }
 constexpr size_t kLdsPerCu = 160 * 1024;
 template <typename T>
 constexpr bool occ_fits(int wps) {
   return occ_lds<false, T, true>(wps) * 4 * wps <= kLdsPerCu &&
          occ_lds<false, T, false>(wps) * 4 * wps <= kLdsPerCu &&
-         occ_lds<true, T, false>(wps) * 4 * wps <= kLdsPerCu;
+         occ_lds<true, T, false>(wps) * 4 * wps <= kLdsPerCu &&
+         occ_lds<true, T, false, true>(wps) <= occ_lds<true, T, false>(wps);
 }
 static_assert(occ_fits<float>(3) && occ_fits<float>(4) && occ_fits<float>(5) &&
                   occ_fits<float>(6) && occ_fits<float>(8), "");
@@ -1187,19 +1198,27 @@ constexpr uint32_t kQParticle = 0x80000000u;  // queue entry: a particle source,
 // owning sink's context by lane shuffles; each owner adds its results in
 // queue order, so a sink's sum is in its own walk order whatever the other
 // sinks of the wave are.
-// REC: the recording flux (tape mode 1), an instance of its own so that the
-// plain flux carries none of the tape's code.
+// TAPE: the tape's instances.  In the forward, the recording flux (tape mode
+// 1), so that the plain flux carries none of the tape's code; in the adjoint,
+// the replay of a complete recording (tape mode 2), which walks no tree.
 template <typename T, bool ADJ, int KS, int KR, int HN, int MOM = 0, int NBND = 0, int SPH = 0,
-          int VAR = 0, bool CNT = true, bool REC = false>
+          int VAR = 0, bool CNT = true, bool TAPE = false>
 __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
-  static_assert(!(ADJ && REC), "the adjoint records nothing");
+  constexpr bool REC = !ADJ && TAPE;
+  constexpr bool RPL = ADJ && TAPE;
+  constexpr int QN = RPL ? kQueueReplay : kQueue;
+  // The adjoint from a tape is launched as a pair: the replay instance runs
+  // when the recording is complete, the walking one (which traces each ray
+  // twice) when it is not, and each returns at once in the other case.
+  if constexpr (ADJ)
+    if (a.tape_mode == 2 && (*a.tape_ctr <= a.tape_cap) != RPL) return;
   extern __shared__ unsigned char smem[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const uint64_t below = (1ull << lane) - 1;  // the lanes below this one
-  unsigned char *base = smem + wv * lds_per_wave<ADJ, T, CNT>(KS, KR, HN);
+  unsigned char *base = smem + wv * lds_per_wave<ADJ, T, CNT, TAPE>(KS, KR, HN);
   uint64_t *s_open = reinterpret_cast<uint64_t *>(base);
-  base += 64 * 8;
+  if (!RPL) base += 64 * 8;
   double *s_hv = reinterpret_cast<double *>(base);  // adjoint table: sums, then keys
   if (ADJ) base += HN * 8;
   int32_t *s_hk = reinterpret_cast<int32_t *>(base);
@@ -1209,7 +1228,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   int32_t *s_stn = reinterpret_cast<int32_t *>(base);  // ... and cells (binary64)
   if (sizeof(T) == 8) base += KR * 64 * 4;
   lds_i32 *s_qe = (lds_i32 *)reinterpret_cast<int32_t *>(base);  // entry: cell or particle
-  base += kQueue * 4;
+  base += QN * 4;
   int32_t *s_cnt = reinterpret_cast<int32_t *>(base);  // forward: pieces, steps per sink
   if (!ADJ && CNT) base += 2 * 64 * 4;
   int32_t *s_anc = reinterpret_cast<int32_t *>(base);
@@ -1228,8 +1247,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   c.stb = s_stb + lane;
   c.st = reinterpret_cast<uint64_t *>(s_stb) + lane;
   c.kr = KR;
-  // a replay needs every block of the recording
-  const bool replay = ADJ && a.tape_mode == 2 && *a.tape_ctr <= a.tape_cap;
+  constexpr bool replay = RPL;  // rounds from the recording's ray lists
   int chunk = -1, sub = a.group;
   int tc_next = 0, tc_end = 0;  // recording: the wave's blocks not yet used
   for (;;) {
@@ -1343,11 +1361,11 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
       uint32_t e = 0;
       int owner = 0;
       if (busy) {
-        const int slot = (qh + lane) & (kQueue - 1);
+        const int slot = (qh + lane) & (QN - 1);
         e = (uint32_t)s_qe[slot];
         owner = s_qo[slot];
       }
-      qh = (qh + nb) & (kQueue - 1);
+      qh = (qh + nb) & (QN - 1);
       qn -= nb;
       // the owner's sink
       const T ox = __shfl(me.x, owner), oy = __shfl(me.y, owner), oz = __shfl(me.z, owner);
@@ -1746,7 +1764,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           // queue invariant: qn < 64 here, so a visit's cell rays fit
           if (acc) {
             if (CNT) n_rays++;
-            const int slot = (qh + qn + __popcll(accm & below)) & (kQueue - 1);
+            const int slot = (qh + qn + __popcll(accm & below)) & (QN - 1);
             s_qe[slot] = n;
             s_qo[slot] = (uint8_t)lane;
           }
@@ -1764,7 +1782,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
                   n_rays++;
                   n_psrc++;
                 }
-                const int slot = (qh + qn + __popcll(um & below)) & (kQueue - 1);
+                const int slot = (qh + qn + __popcll(um & below)) & (QN - 1);
                 s_qe[slot] = (int32_t)((uint32_t)kk | kQParticle);
                 s_qo[slot] = (uint8_t)lane;
               }
@@ -1792,7 +1810,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
           const int nbt = a.tape_nb[tcur];
           if (lane < nbt) {
             const int64_t r = (int64_t)tcur * 64 + lane;
-            const int slot = (qh + lane) & (kQueue - 1);
+            const int slot = (qh + lane) & (QN - 1);
             s_qe[slot] = (int32_t)a.tape_src[r];
             s_qo[slot] = a.tape_own[r];
           }
@@ -1831,26 +1849,26 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
 
 // The walk at the LDS split of an occupancy variant (waves per SIMD).
 template <typename T, bool ADJ, int WPS, int MOM, int NBND, int SPH, int VAR, bool CNT,
-          bool REC = false>
+          bool TAPE = false>
 __device__ __forceinline__ void walk_at(const FluxArgs<T> &a) {
   constexpr bool f32 = sizeof(T) == 4;
-  walk_body<T, ADJ, occ_ks(WPS, ADJ, f32), occ_kr(WPS, ADJ, f32, CNT), occ_hn(WPS, ADJ), MOM, NBND,
-            SPH, VAR, CNT, REC>(a);
+  walk_body<T, ADJ, occ_ks_t(WPS, ADJ, f32, TAPE), occ_kr(WPS, ADJ, f32, CNT), occ_hn(WPS, ADJ),
+            MOM, NBND, SPH, VAR, CNT, TAPE>(a);
 }
 
 // The walk kernel at several register budgets: with fewer VGPRs more waves
 // share a SIMD (better latency hiding) at the price of spills; the launch
 // shape picks one (waves per SIMD = workgroups per CU x waves per workgroup
 // / 4, at least 3).
-template <typename T, bool ADJ, bool CNT, bool REC>
+template <typename T, bool ADJ, bool CNT, bool TAPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 3, 0, 0, 0, 0, CNT, REC>(a);
+  walk_at<T, ADJ, 3, 0, 0, 0, 0, CNT, TAPE>(a);
 }
-template <typename T, bool ADJ, bool CNT, bool REC>
+template <typename T, bool ADJ, bool CNT, bool TAPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 4, 0, 0, 0, 0, CNT, REC>(a);
+  walk_at<T, ADJ, 4, 0, 0, 0, 0, CNT, TAPE>(a);
 }
 // The flux with the vector flux, at the 4-wave budget.
 template <typename T, bool CNT>
@@ -1882,20 +1900,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     FluxArgs<T> a) {
   walk_at<T, false, 3, 2, 0, 0, 0, CNT>(a);
 }
-template <typename T, bool ADJ, bool CNT, bool REC>
+template <typename T, bool ADJ, bool CNT, bool TAPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 5, 0, 0, 0, 0, CNT, REC>(a);
+  walk_at<T, ADJ, 5, 0, 0, 0, 0, CNT, TAPE>(a);
 }
-template <typename T, bool ADJ, bool CNT, bool REC>
+template <typename T, bool ADJ, bool CNT, bool TAPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_walk6(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 6, 0, 0, 0, 0, CNT, REC>(a);
+  walk_at<T, ADJ, 6, 0, 0, 0, 0, CNT, TAPE>(a);
 }
-template <typename T, bool ADJ, bool CNT, bool REC>
+template <typename T, bool ADJ, bool CNT, bool TAPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_walk8(
     FluxArgs<T> a) {
-  walk_at<T, ADJ, 8, 0, 0, 0, 0, CNT, REC>(a);
+  walk_at<T, ADJ, 8, 0, 0, 0, 0, CNT, TAPE>(a);
 }
 
 __global__ void k_zero_i32(int32_t *p, int n) {
@@ -2002,19 +2020,19 @@ static FluxArgs<T> make_args(const trevr_tree *t, double theta, double tau_ref,
 }
 
 // The walk kernel of an occupancy variant (waves per SIMD).
-template <typename T, bool ADJ, bool CNT, bool REC>
+template <typename T, bool ADJ, bool CNT, bool TAPE>
 static void walk_kernel(int wps, int64_t blocks, int threads, size_t shmem, const FluxArgs<T> &a,
                         hipStream_t s) {
   if (wps == 8)
-    k_walk8<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    k_walk8<T, ADJ, CNT, TAPE><<<(unsigned)blocks, threads, shmem, s>>>(a);
   else if (wps == 6)
-    k_walk6<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    k_walk6<T, ADJ, CNT, TAPE><<<(unsigned)blocks, threads, shmem, s>>>(a);
   else if (wps == 5)
-    k_walk5<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    k_walk5<T, ADJ, CNT, TAPE><<<(unsigned)blocks, threads, shmem, s>>>(a);
   else if (wps == 4)
-    k_walk4<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    k_walk4<T, ADJ, CNT, TAPE><<<(unsigned)blocks, threads, shmem, s>>>(a);
   else
-    k_walk<T, ADJ, CNT, REC><<<(unsigned)blocks, threads, shmem, s>>>(a);
+    k_walk<T, ADJ, CNT, TAPE><<<(unsigned)blocks, threads, shmem, s>>>(a);
 }
 
 template <typename T, bool ADJ>
@@ -2092,6 +2110,11 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
                                             : occ_lds<ADJ, T, false>(wps));
   if (shmem > kLdsPerCu) return fail(TREVR_E_ARG, "launch shape needs more LDS than a CU has");
   if constexpr (ADJ) {
+    if (a.tape_mode == 2) {  // the replay; the walking instance below only if it was short
+      const size_t shmem_r = (size_t)waves * occ_lds<true, T, false, true>(wps);
+      walk_kernel<T, true, false, true>(wps, blocks, threads, shmem_r, a, s);
+      k_zero_i32<<<1, 64, 0, s>>>(a.queue, kXcd);
+    }
     walk_kernel<T, true, false, false>(wps, blocks, threads, shmem, a, s);
   } else {
     const bool rec = a.tape_mode == 1;
