@@ -1162,24 +1162,35 @@ __host__ __device__ constexpr int occ_hn(int wps, bool adj) {
   return !adj ? 0 : wps <= 3 ? 256 : wps <= 5 ? 128 : 64;
 }
 // The replay instance spends the walk's LDS (open masks, half the queue:
-// 832 bytes) on three more window levels (768 bytes): 113.6 -> 110.8 ms for
-// the taped adjoint at 2^20, where a 17th stack entry gave 111.8 ms.
+// 832 bytes), as measured for the taped adjoint at 2^20: at 4 waves per SIMD
+// on two more stack entries (one in binary64), 117.9 -> 113.1 ms against
+// three more window levels; elsewhere on three more window levels (768
+// bytes), at 3 waves 113.5 -> 110.8 ms, where a 17th stack entry and a 4th
+// level gave 111.8 ms.
 __host__ __device__ constexpr int occ_ks_t(int wps, bool adj, bool f32, bool tape) {
-  return occ_ks(wps, adj, f32) + (adj && tape ? 3 : 0);
+  return occ_ks(wps, adj, f32) + (adj && tape && wps != 4 ? 3 : 0);
+}
+__host__ __device__ constexpr int occ_kr_t(int wps, bool adj, bool f32, bool cnt, bool tape) {
+  return occ_kr(wps, adj, f32, cnt) + (adj && tape && wps == 4 ? (f32 ? 2 : 1) : 0);
 }
 template <bool ADJ, typename T, bool CNT, bool TAPE = false>
 __host__ __device__ constexpr size_t occ_lds(int wps) {
   constexpr bool f32 = sizeof(T) == 4;
   return lds_per_wave<ADJ, T, CNT, TAPE>(occ_ks_t(wps, ADJ, f32, TAPE),
-                                         occ_kr(wps, ADJ, f32, CNT), occ_hn(wps, ADJ));
+                                         occ_kr_t(wps, ADJ, f32, CNT, TAPE), occ_hn(wps, ADJ));
 }
 constexpr size_t kLdsPerCu = 160 * 1024;
+// wps workgroups of 4 waves per CU; a workgroup's LDS is allocated in 512-byte
+// granules (measured: 4 x 13,632 bytes left room for only two workgroups)
+constexpr bool lds_fits(size_t per_wave, int wps) {
+  return (per_wave * 4 + 511) / 512 * 512 * wps <= kLdsPerCu;
+}
 template <typename T>
 constexpr bool occ_fits(int wps) {
-  return occ_lds<false, T, true>(wps) * 4 * wps <= kLdsPerCu &&
-         occ_lds<false, T, false>(wps) * 4 * wps <= kLdsPerCu &&
-         occ_lds<true, T, false>(wps) * 4 * wps <= kLdsPerCu &&
-         occ_lds<true, T, false, true>(wps) <= occ_lds<true, T, false>(wps);
+  return lds_fits(occ_lds<false, T, true>(wps), wps) &&
+         lds_fits(occ_lds<false, T, false>(wps), wps) &&
+         lds_fits(occ_lds<true, T, false>(wps), wps) &&
+         lds_fits(occ_lds<true, T, false, true>(wps), wps);
 }
 static_assert(occ_fits<float>(3) && occ_fits<float>(4) && occ_fits<float>(5) &&
                   occ_fits<float>(6) && occ_fits<float>(8), "");
@@ -1852,8 +1863,8 @@ template <typename T, bool ADJ, int WPS, int MOM, int NBND, int SPH, int VAR, bo
           bool TAPE = false>
 __device__ __forceinline__ void walk_at(const FluxArgs<T> &a) {
   constexpr bool f32 = sizeof(T) == 4;
-  walk_body<T, ADJ, occ_ks_t(WPS, ADJ, f32, TAPE), occ_kr(WPS, ADJ, f32, CNT), occ_hn(WPS, ADJ),
-            MOM, NBND, SPH, VAR, CNT, TAPE>(a);
+  walk_body<T, ADJ, occ_ks_t(WPS, ADJ, f32, TAPE), occ_kr_t(WPS, ADJ, f32, CNT, TAPE),
+            occ_hn(WPS, ADJ), MOM, NBND, SPH, VAR, CNT, TAPE>(a);
 }
 
 // The walk kernel at several register budgets: with fewer VGPRs more waves
