@@ -122,3 +122,30 @@ def test_autograd_with_a_reused_tree():
     for a, b in zip(*grads):
         assert torch.allclose(a, b, rtol=1e-12, atol=1e-12 * float(b.abs().max())), \
             "reused tree differs"
+
+
+def test_autograd_two_forwards_on_one_tree_before_backward():
+    """Forwards A and B share a tree, and a target flux under no_grad uses it
+    too, all before either backward: each backward still returns its own
+    forward's gradients (the tree's recording is B's, then the target's, so
+    both backwards refit and record again)."""
+    _note("autograd: two forwards and a no_grad flux on one tree before backward")
+    dt = torch.float64
+    pos, rho, kappa, lum, mass = _arrays(4000, 95, dt)
+    t = P.Tree().build(pos, rho, kappa, lum, mass)
+    vals = {"A": (rho * 1.3, kappa * 0.7, lum), "B": (rho * 0.6, kappa * 1.9, lum * 2.0)}
+    leaves, outs = {}, {}
+    for name, (r0, k0, l0) in vals.items():
+        leaves[name] = [v.clone().requires_grad_(True) for v in (r0, k0, l0)]
+        outs[name] = P.flux(pos, *leaves[name], mass, tree=t)
+    with torch.no_grad():
+        P.flux(pos, rho, kappa, lum, mass, tree=t)
+    for name in ("A", "B"):
+        (outs[name].log().sum()).backward()
+        fresh = [v.clone().requires_grad_(True) for v in vals[name]]
+        F = P.flux(pos, *fresh, mass)  # its own tree
+        (F.log().sum()).backward()
+        assert torch.allclose(outs[name].detach(), F.detach(), rtol=1e-13, atol=0.0), name
+        for got, want in zip(leaves[name], fresh):
+            g, w = got.grad, want.grad
+            assert torch.allclose(g, w, rtol=1e-12, atol=1e-12 * float(w.abs().max())), name
