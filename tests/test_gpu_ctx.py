@@ -2,7 +2,7 @@
 App. A; theta_open 0.75, tau_ref 0.1) with the gas as sinks.  A seeded
 2048-sink sample is checked against the oracle (binary32 mirror): counters
 identical, flux within 1e-5.  The mean rays and pieces per gas particle are
-written to gpurun_out/ctx_counts.json beside the paper's figures (about 200
+written to ctx_counts.json in the run's output folder beside the paper's figures (about 200
 rays, Sec. 3.1.2, and 850 segments, Sec. 3.1.3, per element) as context: the
 paper's glass is replaced by a jittered lattice."""
 import json

@@ -16,7 +16,8 @@ times (default launch shapes), through the C ABI.
     at every sink of every box against each box's oracle, counters identical;
   * the binary32 path against the pure binary64 oracle on the headline sample
     (a report: the fraction of sinks within 1e-5, the largest error, sinks
-    whose counters differ), written to gpurun_out/fp32_vs_fp64_c3.json.
+    whose counters differ), written to fp32_vs_fp64_c3.json in the run's
+    output folder.
 """
 import json
 import os
