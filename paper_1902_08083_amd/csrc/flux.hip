@@ -1139,18 +1139,16 @@ __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
 // adjoint spends its LDS on the table first: a round's rays touch about 175
 // distinct cells at the headline workload, and a table much under that
 // sends most pieces to device-memory atomics.
-__host__ __device__ constexpr int occ_ks(int wps, bool adj, bool f32, bool cnt) {
+__host__ __device__ constexpr int occ_ks(int wps, bool adj, bool f32) {
   if (wps <= 3) return adj ? (f32 ? 3 : 2) : (f32 ? 6 : 14);
-  if (wps == 4) return adj ? 3 : f32 && !cnt ? 6 : 4;
+  if (wps == 4) return adj ? 3 : 4;
   if (wps == 5) return adj ? 3 : 5;
   return wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
 }
 __host__ __device__ constexpr int occ_kr(int wps, bool adj, bool f32, bool cnt) {
   if (f32) {
     if (wps <= 3) return adj ? 16 : cnt ? 19 : 20;
-    // without the per-sink counts: their LDS and one stack entry's as window
-    // levels (6, 14), 173.0 -> 171.2 ms at the headline
-    if (wps == 4) return adj ? 12 : 14;
+    if (wps == 4) return adj ? 12 : cnt ? 14 : 15;  // one more without the per-sink counts
     if (wps == 5) return adj ? 8 : 9;
     return wps <= 7 ? 7 : 4;
   }
@@ -1169,8 +1167,8 @@ __host__ __device__ constexpr int occ_hn(int wps, bool adj) {
 // three more window levels; elsewhere on three more window levels (768
 // bytes), at 3 waves 113.5 -> 110.8 ms, where a 17th stack entry and a 4th
 // level gave 111.8 ms.
-__host__ __device__ constexpr int occ_ks_t(int wps, bool adj, bool f32, bool cnt, bool tape) {
-  return occ_ks(wps, adj, f32, cnt) + (adj && tape && wps != 4 ? 3 : 0);
+__host__ __device__ constexpr int occ_ks_t(int wps, bool adj, bool f32, bool tape) {
+  return occ_ks(wps, adj, f32) + (adj && tape && wps != 4 ? 3 : 0);
 }
 __host__ __device__ constexpr int occ_kr_t(int wps, bool adj, bool f32, bool cnt, bool tape) {
   return occ_kr(wps, adj, f32, cnt) + (adj && tape && wps == 4 ? (f32 ? 2 : 1) : 0);
@@ -1178,7 +1176,7 @@ __host__ __device__ constexpr int occ_kr_t(int wps, bool adj, bool f32, bool cnt
 template <bool ADJ, typename T, bool CNT, bool TAPE = false>
 __host__ __device__ constexpr size_t occ_lds(int wps) {
   constexpr bool f32 = sizeof(T) == 4;
-  return lds_per_wave<ADJ, T, CNT, TAPE>(occ_ks_t(wps, ADJ, f32, CNT, TAPE),
+  return lds_per_wave<ADJ, T, CNT, TAPE>(occ_ks_t(wps, ADJ, f32, TAPE),
                                          occ_kr_t(wps, ADJ, f32, CNT, TAPE), occ_hn(wps, ADJ));
 }
 constexpr size_t kLdsPerCu = 160 * 1024;
@@ -1865,7 +1863,7 @@ template <typename T, bool ADJ, int WPS, int MOM, int NBND, int SPH, int VAR, bo
           bool TAPE = false>
 __device__ __forceinline__ void walk_at(const FluxArgs<T> &a) {
   constexpr bool f32 = sizeof(T) == 4;
-  walk_body<T, ADJ, occ_ks_t(WPS, ADJ, f32, CNT, TAPE), occ_kr_t(WPS, ADJ, f32, CNT, TAPE),
+  walk_body<T, ADJ, occ_ks_t(WPS, ADJ, f32, TAPE), occ_kr_t(WPS, ADJ, f32, CNT, TAPE),
             occ_hn(WPS, ADJ), MOM, NBND, SPH, VAR, CNT, TAPE>(a);
 }
 
