@@ -1899,9 +1899,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     FluxArgs<T> a) {
   walk_at<T, false, 3, 0, 0, 0, 1, CNT>(a);
 }
-// The flux with the sub-bucket particle trace, at the 3-wave budget.
+// The flux with the sub-bucket particle trace, with the 3-wave LDS split at
+// 2 waves per SIMD: its binary64 kernel integrals need the registers (862.6
+// -> 805.3 ms at 2^21, where 2 waves made the other walk modes 36-43 %
+// slower).
 template <typename T, bool CNT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3s(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_walk3s(
     FluxArgs<T> a) {
   walk_at<T, false, 3, 0, 0, 1, 0, CNT>(a);
 }
@@ -2078,8 +2081,8 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
-    if (a.sph_nb) {  // the particle trace: the 3-wave kernel, at most 3 waves per SIMD
-      const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
+    if (a.sph_nb) {  // the particle trace: the 2-wave kernel, at most 2 waves per SIMD
+      const int bpc = L.blocks_per_cu * waves > 8 ? 8 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
