@@ -1887,17 +1887,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     FluxArgs<T> a) {
   walk_at<T, false, 4, 1, 0, 0, 0, CNT>(a);
 }
-// The flux per opacity band, at the 3-wave budget.
+// The flux per opacity band, at the 4-wave budget.
 template <typename T, bool CNT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3b(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4b(
     FluxArgs<T> a) {
-  walk_at<T, false, 3, 0, kMaxBands, 0, 0, CNT>(a);
+  walk_at<T, false, 4, 0, kMaxBands, 0, 0, CNT>(a);
 }
-// The flux with the walk variants, at the 3-wave budget.
+// The flux with the walk variants, at the 4-wave budget.
 template <typename T, bool CNT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3x(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4x(
     FluxArgs<T> a) {
-  walk_at<T, false, 3, 0, 0, 0, 1, CNT>(a);
+  walk_at<T, false, 4, 0, 0, 0, 1, CNT>(a);
 }
 // The flux with the sub-bucket particle trace, with the 3-wave LDS split at
 // 2 waves per SIMD: its binary64 kernel integrals need the registers (862.6
@@ -1908,11 +1908,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     FluxArgs<T> a) {
   walk_at<T, false, 3, 0, 0, 1, 0, CNT>(a);
 }
-// The flux with the vector flux and the second moment, at the 3-wave budget.
+// The flux with the vector flux and the second moment, at the 4-wave budget.
+// The band, variant and moment kernels use up to 164 VGPRs without spills at
+// 3 waves per SIMD; at 4, with spills, they ran 3-14 % faster at 2^21.
 template <typename T, bool CNT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_walk3m(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_walk4m(
     FluxArgs<T> a) {
-  walk_at<T, false, 3, 2, 0, 0, 0, CNT>(a);
+  walk_at<T, false, 4, 2, 0, 0, 0, CNT>(a);
 }
 template <typename T, bool ADJ, bool CNT, bool TAPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_walk5(
@@ -2059,25 +2061,25 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
   const int64_t need = (a.n_chunks + waves - 1) / waves;
   if (blocks > need) blocks = need;
   if constexpr (!ADJ) {
-    if (a.flux_bands) {  // the bands: the 3-wave kernel, at most 3 waves per SIMD
-      const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
+    if (a.flux_bands) {  // the bands: the 4-wave kernel, at most 4 waves per SIMD
+      const int bpc = L.blocks_per_cu * waves > 16 ? 16 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3b<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(3), s>>>(a);
+        k_walk4b<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(4), s>>>(a);
       else
-        k_walk3b<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(3), s>>>(a);
+        k_walk4b<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(4), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
-    if (a.variant) {  // the walk variants: the 3-wave kernel, at most 3 waves per SIMD
-      const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
+    if (a.variant) {  // the walk variants: the 4-wave kernel, at most 4 waves per SIMD
+      const int bpc = L.blocks_per_cu * waves > 16 ? 16 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3x<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(3), s>>>(a);
+        k_walk4x<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(4), s>>>(a);
       else
-        k_walk3x<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(3), s>>>(a);
+        k_walk4x<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(4), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
@@ -2092,14 +2094,14 @@ static int launch_walk(const trevr_tree *t, const FluxArgs<T> &a, hipStream_t s)
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
-    if (a.flux_mom) {  // the moments: the 3-wave kernel, at most 3 waves per SIMD
-      const int bpc = L.blocks_per_cu * waves > 12 ? 12 / waves : L.blocks_per_cu;
+    if (a.flux_mom) {  // the moments: the 4-wave kernel, at most 4 waves per SIMD
+      const int bpc = L.blocks_per_cu * waves > 16 ? 16 / waves : L.blocks_per_cu;
       int64_t vb = (int64_t)bpc * t->num_cu;
       if (vb > need) vb = need;
       if (a.counters)
-        k_walk3m<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(3), s>>>(a);
+        k_walk4m<T, true><<<(unsigned)vb, threads, waves * occ_lds<false, T, true>(4), s>>>(a);
       else
-        k_walk3m<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(3), s>>>(a);
+        k_walk4m<T, false><<<(unsigned)vb, threads, waves * occ_lds<false, T, false>(4), s>>>(a);
       TREVR_HIP(hipGetLastError());
       return TREVR_OK;
     }
