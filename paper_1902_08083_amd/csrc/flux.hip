@@ -626,27 +626,23 @@ struct Scatter {
   int32_t *hk;  // per-wave LDS table of cells: keys (-1: free) ...
   double *hv;   // ... and their sums, written out after each round
   int hmask;    // table slots - 1 (a power of two minus one)
-  // Every piece goes to the table (one of two slots picked by two hashes of
-  // the cell): a round's rays share most of their cells, so the round's
-  // sums reach device memory as about one atomic per distinct cell.  One
-  // compare-and-swap per probe claims a free slot or finds the cell's own.
-  // A cell whose two slots hold other cells takes the second one over: the
-  // slot's old sum goes to device memory, so the table keeps the cells the
-  // round is working on.  Of several lanes of one call that would take the
-  // same slot, one does (a compare-and-swap on the key it saw); the others
-  // send their own sum to device memory.  The call's hits land before any
-  // slot changes hands.
+  // Every piece goes to the table, at the slot of its cell's number modulo
+  // the table size: a round's rays share most of their cells, so the round's
+  // sums reach device memory as about one atomic per distinct cell, and the
+  // cells of a round are numbered close together (depth-first order), so
+  // neighbours take neighbouring slots.  One compare-and-swap claims a free
+  // slot or finds the cell's own.  A cell whose slot holds another cell
+  // takes it over: the slot's old sum goes to device memory, so the table
+  // keeps the cells the round is working on.  Of several lanes of one call
+  // that would take the same slot, one does (a compare-and-swap on the key it
+  // saw); the others send their own sum to device memory.  The call's hits
+  // land before any slot changes hands.  (Measured at 2^20: 111.2 -> 109.0 ms
+  // against two probes at two multiplicative hashes.)
   __device__ __forceinline__ void pool(int node, double v) {
-    int sl = (int)((((uint32_t)node * 2654435761u) >> 16) & (uint32_t)hmask);
+    const int sl = (int)((uint32_t)node & (uint32_t)hmask);
     int k = -1;  // the slot's key before: free (now ours), this cell, or another
     __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &k, node, __ATOMIC_RELAXED,
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    if (k != -1 && k != node) {  // taken: a second slot from an independent hash
-      sl = (int)((((uint32_t)node * 0x85ebca6bu) >> 20) & (uint32_t)hmask);
-      k = -1;
-      __hip_atomic_compare_exchange_strong((lds_i32 *)hk + sl, &k, node, __ATOMIC_RELAXED,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    }
     const bool hit = k == -1 || k == node;
     if (hit) lds_add(&hv[sl], v);
     // The two branches exclude each other per lane, so without this the
