@@ -1117,17 +1117,20 @@ __device__ __forceinline__ int wave_take(int32_t *queue, int n_chunks) {
 // entry is 8 bytes for binary32, f64 + i32 for binary64), the ray queue
 // (kQueue x (i32 + u8)), the per-sink counts of traced pieces and steps
 // (2 x 64 x i32, a forward that keeps counters), the sink-ancestor windows
-// (ks x 64 lanes x i32) and the shared sink-chain prefix (64 x i32).  The
+// (ks x 64 lanes x i32) and the shared sink-chain prefix (kPre x i32).  The
 // adjoint's replay instance (ADJ with TAPE) walks no tree: it has no open
 // masks, and its queue holds one round.
 constexpr int kQueue = 128;       // ray queue slots per wave (a power of two)
+// Depths of the wave-shared sink-chain prefix: deeper shared levels (trees
+// deeper than the headline's 29) are found by descending from its last one.
+constexpr int kPre = 32;
 constexpr int kQueueReplay = 64;  // the same in the replay instance
 template <bool ADJ, typename T, bool CNT = true, bool TAPE = false>
 __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
   return (ADJ && TAPE ? 0 : (size_t)64 * 8) + (ADJ ? (size_t)hn * 12 : 0) +
          (size_t)kr * 64 * (sizeof(T) == 4 ? 8 : 12) +
          (size_t)(ADJ && TAPE ? kQueueReplay : kQueue) * 5 + (ADJ || !CNT ? 0 : 2 * 64 * 4) +
-         (size_t)ks * 64 * 4 + 64 * 4;
+         (size_t)ks * 64 * 4 + kPre * 4;
 }
 
 // Window depth, stack entries and table slots per occupancy variant (waves
@@ -1137,7 +1140,9 @@ __host__ __device__ constexpr size_t lds_per_wave(int ks, int kr, int hn) {
 // sends most pieces to device-memory atomics.
 __host__ __device__ constexpr int occ_ks(int wps, bool adj, bool f32) {
   if (wps <= 3) return adj ? (f32 ? 3 : 2) : (f32 ? 6 : 14);
-  if (wps == 4) return adj ? 3 : 4;
+  // binary32 4-wave forward: the prefix's freed 128 bytes and the slack make
+  // a 5th window level (173.1 -> 171.9 ms at the headline, 15 stack entries)
+  if (wps == 4) return adj ? 3 : (f32 ? 5 : 4);
   if (wps == 5) return adj ? 3 : 5;
   return wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
 }
@@ -1241,7 +1246,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
   int32_t *s_anc = reinterpret_cast<int32_t *>(base);
   base += KS * 64 * 4;
   int32_t *s_pre = reinterpret_cast<int32_t *>(base);
-  uint8_t *s_qo = reinterpret_cast<uint8_t *>(s_pre + 64);  // entry's owning lane
+  uint8_t *s_qo = reinterpret_cast<uint8_t *>(s_pre + kPre);  // entry's owning lane
   if (ADJ) {
     for (int j = lane; j < HN; j += 64) {
       s_hk[j] = -1;
@@ -1323,7 +1328,7 @@ __device__ __forceinline__ void walk_body(const FluxArgs<T> &a) {
         const int other = __shfl_xor(dc, o);
         dc = other < dc ? other : dc;
       }
-      d_common = vmask ? dc : -1;
+      d_common = vmask ? (dc < kPre - 1 ? dc : kPre - 1) : -1;
     }
     sk.root = my_root;
     sk.dpre = d_common;
