@@ -1144,7 +1144,7 @@ __host__ __device__ constexpr int occ_ks(int wps, bool adj, bool f32) {
   // a 5th window level (173.1 -> 171.9 ms at the headline, 15 stack entries)
   if (wps == 4) return adj ? 3 : (f32 ? 5 : 4);
   if (wps == 5) return adj ? 3 : 5;
-  return wps <= 7 ? (adj ? 4 : 3) : (adj ? 3 : 2);
+  return wps <= 7 ? (adj ? (f32 ? 3 : 4) : 3) : (adj ? 3 : 2);
 }
 __host__ __device__ constexpr int occ_kr(int wps, bool adj, bool f32, bool cnt) {
   if (f32) {
@@ -1181,10 +1181,12 @@ __host__ __device__ constexpr size_t occ_lds(int wps) {
                                          occ_kr_t(wps, ADJ, f32, CNT, TAPE), occ_hn(wps, ADJ));
 }
 constexpr size_t kLdsPerCu = 160 * 1024;
-// wps workgroups of 4 waves per CU; a workgroup's LDS is allocated in 512-byte
-// granules (measured: 4 x 13,632 bytes left room for only two workgroups)
+// wps workgroups of 4 waves per CU.  A workgroup's LDS is taken in granules:
+// measured at 3 workgroups per CU, 4 x 13,440 bytes fit and 4 x 13,504 did
+// not; at 4, 4 x 10,240 fit.  A 2,560-byte granule fits every measured case.
+constexpr size_t kLdsGranule = 2560;
 constexpr bool lds_fits(size_t per_wave, int wps) {
-  return (per_wave * 4 + 511) / 512 * 512 * wps <= kLdsPerCu;
+  return (per_wave * 4 + kLdsGranule - 1) / kLdsGranule * kLdsGranule * wps <= kLdsPerCu;
 }
 template <typename T>
 constexpr bool occ_fits(int wps) {
