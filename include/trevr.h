@@ -180,8 +180,10 @@ int trevr_compute_flux(const trevr_tree *tree, double theta_open, double tau_ref
  *   TREVR_ADJ_RECOMPUTE: one kernel traces every ray twice, once for its
  *     optical depth and once to scatter d loss / d alpha over its pieces
  *     (segments recomputed, nothing stored per ray);
- *   TREVR_ADJ_STORE: a recording flux stores each ray's optical depth (8 B
- *     per ray), then the adjoint traces each ray once, for the scatter;
+ *   TREVR_ADJ_STORE: a recording flux stores each ray's optical depth and
+ *     each round's list of rays (13 B per ray), then the adjoint replays the
+ *     rounds without walking the tree and traces each ray once, for the
+ *     scatter (a recording that outgrew its tape is traced twice instead);
  *   TREVR_ADJ_AUTO: STORE while the tree holds no recording of the caller's
  *     (trevr_compute_flux_taped) and the tape fits in half the free device
  *     memory, else RECOMPUTE; scratch owned by the tree. */
