@@ -375,8 +375,16 @@ def batched(torch, P, reps=5):
         b.synchronize()
         ms.append(a.elapsed_time(b))
     ms_graph = float(np.median(ms))
+    # the same launch's work, counted by one call with counters (after timing)
+    _, C = plan.tree.flux(plan.theta_open, plan.tau_ref, counters=True)
+    n_open, n_rays, n_psrc, n_seg, n_trace = [int(v) for v in P.sum_counters(C).cpu().numpy()]
+    alg_bytes = (BYTES_OPEN * n_open + BYTES_TRACE * n_trace + BYTES_PSRC * n_psrc
+                 + BYTES_SINK * n)
+    achieved = alg_bytes / (ms_graph * 1e-3) / 1e9
     return {"workload": "c4_batched64_f32", "boxes": len(boxes), "n_particles": n,
             "graph_replay_ms": ms_graph, "sink_fluxes_per_s": n / (ms_graph * 1e-3),
+            "cell_visits_per_s": (n_open + n_trace) / (ms_graph * 1e-3),
+            "roofline_frac": achieved / HBM_PEAK_GBS,
             "autotuned_launch": list(plan.tuning["launch"]),
             "autotune_best_ms": plan.tuning["ms"],
             "autotune_worst_ms": plan.tuning["table"][-1][0],
